@@ -1,0 +1,215 @@
+/*
+ * tfim.h - C ABI of libtfim: Metropolis + parallel tempering sampling of the
+ * classical Trotter-Suzuki lattice of the 2D transverse-field Ising spin
+ * glass, multispin-coded (64 disorder samples per uint64), on one MI355X.
+ *
+ * Paper: Bernaschi, Gonzalez-Adalid Pemartin, Martin-Mayor, Parisi,
+ * "The Quantum Transition of the Two-Dimensional Ising Spin Glass"
+ * (arXiv:2310.07486).  A problem is what the paper's Methods define it by:
+ * an instance of +-1 couplings ("Model and simulations"), lattice sizes L and
+ * Ltau and a coupling k or a ladder of k ("The Trotter-Suzuki formula":
+ * p(S) = exp(-k E(S))/Z, periodic in tau), real replicas and tempering over
+ * k ("Simulation details", Table I), and the one-time observables
+ * ("One-time observables": M, M-hat, chi^(2), F^(2), xi^(2)).
+ *
+ * Conventions used by every call:
+ *   - Site (x, y, tau), xy = x + L*y, lin = xy + L*L*tau.  Colour
+ *     (x + y + tau) mod 2; L and Ltau must be even.
+ *   - Spin bit 1 <=> S = -1; coupling bit 1 <=> J = -1.  Bit b of sample
+ *     word j is sample 64*j + b of the shape.
+ *   - Canonical host layouts: spins u64[r][w][j][tau][y][x] (replica r,
+ *     walker w), couplings u64[j][d][y][x] (d = 0: bond (x,y)-(x+1,y);
+ *     d = 1: bond (x,y)-(x,y+1)), k labels u8[r][s][w] (k-index of walker w
+ *     of replica r, sample s), energies u32[r][s][w] = number of
+ *     unsatisfied bonds U (E = 2U - 3N, N = L*L*Ltau).
+ *   - Random numbers: Philox4x32-10, key = seed, counter layout fixed by
+ *     the library (a shape's streams depend on seed, stream_id, the global
+ *     word index word_offset + j, the sweep counter t and the tempering
+ *     counter m), so a shape reproduces bit-for-bit whether it runs alone
+ *     or batched, whole or split into word ranges.
+ *
+ * Ownership: the caller allocates ONE device arena of the size reported by
+ * tfim_plan_sizes and keeps it alive while the plan is bound; the library
+ * never allocates or frees device memory of its own except HIP graph
+ * objects.  The plan (an opaque host object) owns its copies of the shapes,
+ * the threshold tables, the tuner choice and the graph cache.
+ *
+ * Errors: every call returns a tfim_status and never throws.  Argument
+ * errors return before anything is enqueued and leave the state unchanged.
+ * A device error poisons the plan: later calls return TFIM_ESTATE.
+ * tfim_last_error_detail() describes the last failure of this thread.
+ *
+ * Concurrency: calls that enqueue work (init, sweep, pt_swap) are
+ * asynchronous on the bound stream; calls that return data to the host
+ * (measure, export, get_state) synchronise that stream.  A plan is not
+ * thread-safe; distinct plans are independent.
+ */
+#ifndef TFIM_H
+#define TFIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tfim_status;
+#define TFIM_OK 0
+#define TFIM_EINVAL (-1)       /* bad argument or shape */
+#define TFIM_EUNSUPPORTED (-2) /* valid request this build does not provide */
+#define TFIM_EDEVICE (-3)      /* HIP runtime or kernel failure */
+#define TFIM_ESTATE (-4)       /* wrong call order, unbound or poisoned plan */
+#define TFIM_EOVERFLOW (-5)    /* sweep or tempering counter would pass 2^32 */
+
+/* Boundary condition along tau (Methods, "The Trotter-Suzuki formula"). */
+#define TFIM_BC_PERIODIC 0u
+#define TFIM_BC_ANTIPERIODIC 1u /* returns TFIM_EUNSUPPORTED */
+
+/* One problem shape: n_words*64 disorder samples of an L x L x Ltau lattice,
+ * n_replicas independent real replicas, each with n_k walkers that share the
+ * ladder k[0] < k[1] < ... < k[n_k-1] through tempering. */
+typedef struct {
+    uint32_t L;           /* even, 2..24 (one thread per spatial column) */
+    uint32_t Ltau;        /* multiple of 8, 8..65536 (else TFIM_EUNSUPPORTED) */
+    uint32_t n_words;     /* >= 1; samples = 64*n_words */
+    uint32_t word_offset; /* global index of word 0 (word_offset + n_words <= 2^20) */
+    uint32_t n_replicas;  /* 1..64 */
+    uint32_t n_k;         /* 1..255 */
+    const double *k;      /* n_k couplings, > 0, strictly increasing; copied */
+    uint32_t bc_tau;      /* TFIM_BC_PERIODIC */
+    uint32_t pt_every;    /* tempering after every pt_every-th sweep; 0 = never */
+    uint32_t stream_id;   /* 0..255, distinct within a plan */
+} tfim_shape;
+
+typedef struct tfim_plan tfim_plan;
+
+/* Device arena layout, in bytes (offsets are 256-byte aligned). */
+typedef struct {
+    size_t total;     /* size of the arena to pass to tfim_bind */
+    size_t spins;     /* all shapes' spin words */
+    size_t couplings; /* all shapes' coupling words */
+    size_t labels;    /* k labels, walker-of-k maps, energies, lane masks */
+    size_t tables;    /* threshold tables and counters */
+    size_t measure;   /* measurement records */
+} tfim_sizes;
+
+/* Create a plan for n_shapes shapes sampled together with one seed.
+ * TFIM_EINVAL: odd or out-of-range L/Ltau, n_words = 0, bad ladder,
+ * repeated stream_id.  TFIM_EUNSUPPORTED: antiperiodic bc_tau. */
+tfim_status tfim_plan_create(const tfim_shape *shapes, uint32_t n_shapes, uint64_t seed,
+                             tfim_plan **plan_out);
+void tfim_plan_destroy(tfim_plan *plan);
+
+/* Sizes of the device arena (host-only). */
+tfim_status tfim_plan_sizes(const tfim_plan *plan, tfim_sizes *sizes_out);
+
+/* Bind the caller's device arena (at least sizes.total bytes, 256-byte
+ * aligned) and HIP stream (NULL = default stream) to the plan. */
+tfim_status tfim_bind(tfim_plan *plan, void *device_arena, size_t arena_bytes,
+                      void *hip_stream);
+
+/* Instance (Methods, "Model and simulations": J = +-1 with probability 1/2).
+ * J_host == NULL: draw the couplings on the device from the seed;
+ * otherwise copy n_words*2*L*L canonical words from the host. */
+tfim_status tfim_init_couplings(tfim_plan *plan, uint32_t shape, const uint64_t *J_host);
+
+/* Initial state: hot start (i.i.d. spins) when S_host == NULL, otherwise a
+ * canonical host array of n_replicas*n_k*n_words*L*L*Ltau words.  Resets
+ * k labels to the identity, recounts energies and sets t = m = 0 for the
+ * whole plan.  Couplings must be initialised first (else TFIM_ESTATE). */
+tfim_status tfim_init_spins(tfim_plan *plan, uint32_t shape, const uint64_t *S_host);
+
+/* n sweeps of every shape (Methods, "Simulation details"; Table I): a
+ * checkerboard Metropolis sweep (colour 0 then colour 1), the energy
+ * recount, and a tempering step after sweep t when pt_every > 0 and
+ * (t+1) % pt_every == 0.  Asynchronous.  TFIM_EOVERFLOW if t would pass
+ * 2^32 - 1. */
+tfim_status tfim_sweep(tfim_plan *plan, uint64_t n);
+
+/* One explicit tempering step of every shape (uses and advances m). */
+tfim_status tfim_pt_swap(tfim_plan *plan);
+
+/* Measurement (Methods, "One-time observables"), synchronous.
+ * what = TFIM_MEASURE_RECORDS: int64 records [n_k][samples][pairs][2L+3],
+ *   pairs = replica pairs a<b in lexicographic order, each record
+ *   [D_x[0..L-1], D_y[0..L-1], trQ, sum Q^2, sum Q^4] where, for the
+ *   configurations S^a, S^b (L^2 x Ltau, +-1) at k-index i,
+ *   G = S S^T, D_x[d] = sum_{(x1-y1) mod L = d} G^a_xy G^b_xy,
+ *   Q = S^aT S^b.  Needs n_replicas >= 2.
+ * what = TFIM_MEASURE_BUCKETS: int64 A[n_k][2][L] = records' D_x and D_y
+ *   summed over samples and pairs.
+ * what = TFIM_MEASURE_ENERGY: u32 U[r][s][i] of the walker at k-index i.
+ * host_bytes must be at least the size of the result. */
+#define TFIM_MEASURE_RECORDS 1u
+#define TFIM_MEASURE_BUCKETS 2u
+#define TFIM_MEASURE_ENERGY 3u
+tfim_status tfim_measure(tfim_plan *plan, uint32_t shape, uint32_t what, void *host_out,
+                         size_t host_bytes);
+
+/* Debug dump of the integer matrices of one configuration pair:
+ * G^a (L^2 x L^2, int32), G^b, and Q^{ab} (Ltau x Ltau, int32) for sample s
+ * at k-index i, replicas a < b.  Synchronous. */
+tfim_status tfim_dump_gram(tfim_plan *plan, uint32_t shape, uint32_t i, uint32_t s,
+                           uint32_t a, uint32_t b, int32_t *Ga, int32_t *Gb, int32_t *Q);
+
+/* Second-moment correlation length (Methods, "One-time observables"):
+ * for each k-index, chi = sum_d A[d], F = sum_d A[d] cos(2 pi d/L),
+ * xi = sqrt(chi/F - 1) / (2 sin(pi/L)); +inf if F <= 0, NaN if chi/F < 1.
+ * A is [n_k][L] int64 (e.g. the D_x half of the buckets).  Host-only. */
+tfim_status tfim_xi2(const int64_t *A, uint32_t L, uint32_t n_k, double *xi_out);
+
+/* Threshold tables of a shape (host-only): Tm[n_k][3] with
+ * Tm[i][u] = floor(2^32 exp(-k_i (12 - 4u))) for u = 0,1,2 unsatisfied
+ * bonds of six; dmax[n_k-1]; Tpt[sum dmax] with, for pair i, entries
+ * d = 1..dmax[i] equal to floor(2^32 exp(-(k_{i+1}-k_i) 2d)).
+ * Any pointer may be NULL.  *n_tpt receives sum(dmax). */
+tfim_status tfim_get_thresholds(const tfim_plan *plan, uint32_t shape, uint32_t *Tm,
+                                uint32_t *dmax, uint32_t *Tpt, size_t tpt_capacity,
+                                size_t *n_tpt);
+
+/* Copy state back in canonical layouts (synchronous). */
+tfim_status tfim_export_spins(tfim_plan *plan, uint32_t shape, uint64_t *S_host);
+tfim_status tfim_export_couplings(tfim_plan *plan, uint32_t shape, uint64_t *J_host);
+tfim_status tfim_get_state(tfim_plan *plan, uint32_t shape, uint8_t *kidx_host,
+                           uint32_t *U_host);
+/* Sweep counter t and tempering counter m of a shape (they key its random
+ * streams; every shape's t advances with each tfim_sweep). */
+tfim_status tfim_get_counters(const tfim_plan *plan, uint32_t shape, uint64_t *t, uint64_t *m);
+
+/* Restore a saved state: spins (canonical) and k labels of one shape, and
+ * that shape's counters t, m; energies and lane masks are recomputed.  Resuming from
+ * a saved state continues bit-for-bit. */
+tfim_status tfim_set_state(tfim_plan *plan, uint32_t shape, const uint64_t *S_host,
+                           const uint8_t *kidx_host, uint64_t t, uint64_t m);
+
+/* Launch schedule of tfim_sweep.
+ * TFIM_SCHED_BATCHED: one persistent kernel covers all shapes and all n
+ *   sweeps (work items handed out in order, tempering done by the last
+ *   walker of each group), captured in a HIP graph.
+ * TFIM_SCHED_PER_SHAPE: one sweep launch per shape and sweep, one
+ *   tempering launch per shape and step (the plain form).
+ * Both give bit-identical results. */
+#define TFIM_SCHED_BATCHED 0u
+#define TFIM_SCHED_PER_SHAPE 1u
+tfim_status tfim_set_schedule(tfim_plan *plan, uint32_t schedule);
+
+/* Autotuner: times each candidate launch configuration of the sweep on the
+ * bound state (the state is saved and restored around the trials, so the
+ * chain is unchanged) and keeps the fastest.  Synchronous.
+ * tfim_get_tuning reports the chosen configuration id and its time. */
+tfim_status tfim_autotune(tfim_plan *plan, uint32_t sweeps_per_trial);
+tfim_status tfim_get_tuning(const tfim_plan *plan, uint32_t *config_id, double *ms_per_sweep);
+
+/* Wait for the bound stream; asynchronous device faults surface here as
+ * TFIM_EDEVICE. */
+tfim_status tfim_sync(tfim_plan *plan);
+
+const char *tfim_strerror(tfim_status status);
+const char *tfim_last_error_detail(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TFIM_H */

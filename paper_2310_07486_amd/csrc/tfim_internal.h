@@ -1,0 +1,91 @@
+// Internal declarations shared by the libtfim host runtime and its kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tfim {
+
+// Philox4x32-10 purposes (fourth counter word, bits 28..31).
+enum : uint32_t { kTagMetro = 0u, kTagTemper = 1u, kTagSpin = 2u, kTagCoupling = 3u };
+
+// Everything a kernel needs to know about one shape, by value.
+struct ShapeDev {
+    int L, L2, Lt, nk, W, R, P;  // P = replica pairs
+    uint32_t sid, word_offset;
+    uint32_t pt_every;
+    uint64_t* S;            // spins  [R][nk][W][Lt][L2]
+    uint64_t* J;            // couplings [W][2][L2]
+    uint8_t* kidx;          // [R][W*64][nk]  k-index of walker w
+    uint8_t* winv;          // [R][W*64][nk]  walker holding k-index i
+    uint32_t* U;            // [R][W*64][nk]  unsatisfied bonds of walker w
+    uint64_t* mask;         // [R][W][nk][nk+1] lanes whose walker w has k-index < K
+    const uint32_t* Tu;     // [nk][3]  Metropolis thresholds by unsatisfied count u
+    const uint32_t* Tpt;    // swap thresholds, pair i at tpt_off[i] + d - 1
+    const uint32_t* tpt_off;
+    const uint32_t* dmax;
+    int64_t* rec;           // measurement records [nk][W*64][P][2L+3]
+    int64_t* buckets;       // [nk][2][L]
+};
+
+// Plan-wide device counters.
+struct Counters {
+    uint32_t t;         // sweeps done
+    uint32_t m;         // tempering steps done
+    uint32_t error;     // nonzero: a kernel detected an inconsistency
+    uint32_t pad;
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the
+// two-multiplier S-box; the key advances by the Weyl increments each round.
+// ---------------------------------------------------------------------------
+struct U4 {
+    uint32_t v[4];
+};
+
+__host__ __device__ inline U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                       uint32_t key0, uint32_t key1) {
+    constexpr uint32_t kMulA = 0xD2511F53u, kMulB = 0xCD9E8D57u;
+    constexpr uint32_t kWeylA = 0x9E3779B9u, kWeylB = 0xBB67AE85u;
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t pa = (uint64_t)kMulA * c0;
+        const uint64_t pb = (uint64_t)kMulB * c2;
+        const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ key0;
+        const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ key1;
+        c1 = (uint32_t)pb;
+        c3 = (uint32_t)pa;
+        c0 = n0;
+        c2 = n2;
+        key0 += kWeylA;
+        key1 += kWeylB;
+    }
+    U4 r;
+    r.v[0] = c0; r.v[1] = c1; r.v[2] = c2; r.v[3] = c3;
+    return r;
+}
+
+__host__ __device__ inline uint32_t ctr_word3(uint32_t j_global, uint32_t sid, uint32_t tag) {
+    return (j_global & 0xFFFFFu) | ((sid & 0xFFu) << 20) | (tag << 28);
+}
+
+}  // namespace tfim
+
+// Kernel launchers (defined in the .hip files, called by the runtime).
+namespace tfim {
+hipError_t launch_init_couplings(const ShapeDev& sh, uint64_t seed, hipStream_t st);
+hipError_t launch_init_spins(const ShapeDev& sh, uint64_t seed, hipStream_t st);
+hipError_t launch_labels_identity(const ShapeDev& sh, hipStream_t st);
+hipError_t launch_energy(const ShapeDev& sh, hipStream_t st);
+hipError_t launch_mask_rebuild(const ShapeDev& sh, hipStream_t st);
+hipError_t launch_sweep(const ShapeDev& sh, uint64_t seed, const Counters* ctr, int variant,
+                        hipStream_t st);
+hipError_t launch_temper(const ShapeDev& sh, uint64_t seed, const Counters* ctr, hipStream_t st);
+hipError_t launch_advance(Counters* ctr, uint32_t dt, uint32_t dm, hipStream_t st);
+hipError_t launch_measure(const ShapeDev& sh, hipStream_t st);
+hipError_t launch_dump_gram(const ShapeDev& sh, int i, int s, int a, int b, int32_t* Ga,
+                            int32_t* Gb, int32_t* Q, hipStream_t st);
+int sweep_variants();
+const char* sweep_variant_name(int v);
+}  // namespace tfim

@@ -1,0 +1,311 @@
+"""ctypes binding of libtfim (include/tfim.h): same names, argument
+marshalling only.  Every step of the sampler runs in the HIP library; torch
+only allocates the device arena and supplies the current HIP stream.
+
+The library must be built (``python -m paper_2310_07486_amd.build`` or
+``__graft_entry__.build()``); loading fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtfim.so")
+
+TFIM_OK = 0
+TFIM_EINVAL = -1
+TFIM_EUNSUPPORTED = -2
+TFIM_EDEVICE = -3
+TFIM_ESTATE = -4
+TFIM_EOVERFLOW = -5
+TFIM_BC_PERIODIC = 0
+TFIM_BC_ANTIPERIODIC = 1
+TFIM_MEASURE_RECORDS = 1
+TFIM_MEASURE_BUCKETS = 2
+TFIM_MEASURE_ENERGY = 3
+TFIM_SCHED_BATCHED = 0
+TFIM_SCHED_PER_SHAPE = 1
+
+# Every symbol include/tfim.h declares.
+SYMBOLS = [
+    "tfim_plan_create", "tfim_plan_destroy", "tfim_plan_sizes", "tfim_bind",
+    "tfim_init_couplings", "tfim_init_spins", "tfim_sweep", "tfim_pt_swap", "tfim_measure",
+    "tfim_dump_gram", "tfim_xi2", "tfim_get_thresholds", "tfim_export_spins",
+    "tfim_export_couplings", "tfim_get_state", "tfim_get_counters", "tfim_set_state",
+    "tfim_set_schedule", "tfim_autotune", "tfim_get_tuning", "tfim_sync", "tfim_strerror",
+    "tfim_last_error_detail",
+]
+
+
+class TfimError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: status {status}: {detail}")
+        self.status = status
+
+
+class tfim_shape(ctypes.Structure):
+    _fields_ = [
+        ("L", ctypes.c_uint32), ("Ltau", ctypes.c_uint32), ("n_words", ctypes.c_uint32),
+        ("word_offset", ctypes.c_uint32), ("n_replicas", ctypes.c_uint32),
+        ("n_k", ctypes.c_uint32), ("k", ctypes.POINTER(ctypes.c_double)),
+        ("bc_tau", ctypes.c_uint32), ("pt_every", ctypes.c_uint32),
+        ("stream_id", ctypes.c_uint32),
+    ]
+
+
+class tfim_sizes(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_size_t) for n in
+                ("total", "spins", "couplings", "labels", "tables", "measure")]
+
+
+_lib = None
+
+
+def lib():
+    """Load libtfim.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libtfim.so not built at {LIB_PATH}; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P, U32, U64, SZ = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t
+        sig = {
+            "tfim_plan_create": [P, U32, U64, P],
+            "tfim_plan_destroy": [P],
+            "tfim_plan_sizes": [P, P],
+            "tfim_bind": [P, P, SZ, P],
+            "tfim_init_couplings": [P, U32, P],
+            "tfim_init_spins": [P, U32, P],
+            "tfim_sweep": [P, U64],
+            "tfim_pt_swap": [P],
+            "tfim_measure": [P, U32, U32, P, SZ],
+            "tfim_dump_gram": [P, U32, U32, U32, U32, U32, P, P, P],
+            "tfim_xi2": [P, U32, U32, P],
+            "tfim_get_thresholds": [P, U32, P, P, P, SZ, P],
+            "tfim_export_spins": [P, U32, P],
+            "tfim_export_couplings": [P, U32, P],
+            "tfim_get_state": [P, U32, P, P],
+            "tfim_get_counters": [P, U32, P, P],
+            "tfim_set_state": [P, U32, P, P, U64, U64],
+            "tfim_set_schedule": [P, U32],
+            "tfim_autotune": [P, U32],
+            "tfim_get_tuning": [P, P, P],
+            "tfim_sync": [P],
+            "tfim_strerror": [ctypes.c_int32],
+            "tfim_last_error_detail": [],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int32
+        L.tfim_plan_destroy.restype = None
+        L.tfim_strerror.restype = ctypes.c_char_p
+        L.tfim_last_error_detail.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(st: int, where: str):
+    if st != TFIM_OK:
+        raise TfimError(st, where, lib().tfim_last_error_detail().decode())
+
+
+def _ptr(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"]
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def tfim_xi2(A: np.ndarray, L: int) -> np.ndarray:
+    """xi^(2) per k-index from int64 buckets A[n_k][L] (host-only call)."""
+    A = np.ascontiguousarray(A, dtype=np.int64)
+    n_k = A.shape[0]
+    out = np.zeros(n_k, dtype=np.float64)
+    _check(lib().tfim_xi2(_ptr(A), L, n_k, _ptr(out)), "tfim_xi2")
+    return out
+
+
+class Plan:
+    """A plan over one or more shapes; owns a torch device arena.
+
+    shapes: sequence of objects with L, Ltau, n_words, n_replicas, k,
+    pt_every, stream_id, word_offset (see workloads.Shape)."""
+
+    def __init__(self, shapes: Sequence, seed: int, *, device: str = "cuda", stream=None,
+                 bind: bool = True):
+        self.shapes = list(shapes)
+        self.seed = int(seed)
+        self._k = [np.ascontiguousarray(np.asarray(s.k, dtype=np.float64)) for s in self.shapes]
+        arr = (tfim_shape * len(self.shapes))()
+        for i, s in enumerate(self.shapes):
+            arr[i] = tfim_shape(s.L, s.Ltau, s.n_words, getattr(s, "word_offset", 0),
+                                s.n_replicas, len(self._k[i]),
+                                self._k[i].ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                getattr(s, "bc_tau", TFIM_BC_PERIODIC), s.pt_every,
+                                getattr(s, "stream_id", i))
+        self._arr = arr
+        h = ctypes.c_void_p()
+        _check(lib().tfim_plan_create(arr, len(self.shapes), self.seed, ctypes.byref(h)),
+               "tfim_plan_create")
+        self._h = h
+        sz = tfim_sizes()
+        _check(lib().tfim_plan_sizes(self._h, ctypes.byref(sz)), "tfim_plan_sizes")
+        self.sizes = {n: getattr(sz, n) for n, _ in tfim_sizes._fields_}
+        self.arena = None
+        self.stream = None
+        if bind:
+            self.bind(device=device, stream=stream)
+
+    # -- lifetime ------------------------------------------------------------
+    def bind(self, device: str = "cuda", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("libtfim needs a HIP device (torch.cuda.is_available() is False)")
+        self.arena = torch.empty(self.sizes["total"], dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        _check(lib().tfim_bind(self._h, ctypes.c_void_p(self.arena.data_ptr()),
+                               self.sizes["total"], ctypes.c_void_p(self.stream.cuda_stream)),
+               "tfim_bind")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().tfim_plan_destroy(self._h)
+            self._h = None
+        self.arena = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- geometry ------------------------------------------------------------
+    def _dims(self, shape: int):
+        s = self.shapes[shape]
+        return s.L, s.Ltau, s.n_words, s.n_replicas, len(self._k[shape])
+
+    # -- ABI calls -------------------------------------------------------------
+    def init_couplings(self, shape: int = 0, J: Optional[np.ndarray] = None):
+        p = None if J is None else _ptr(np.ascontiguousarray(J, dtype=np.uint64))
+        _check(lib().tfim_init_couplings(self._h, shape, p), "tfim_init_couplings")
+
+    def init_spins(self, shape: int = 0, S: Optional[np.ndarray] = None):
+        p = None if S is None else _ptr(np.ascontiguousarray(S, dtype=np.uint64))
+        _check(lib().tfim_init_spins(self._h, shape, p), "tfim_init_spins")
+
+    def init(self):
+        for i in range(len(self.shapes)):
+            self.init_couplings(i)
+        for i in range(len(self.shapes)):
+            self.init_spins(i)
+
+    def sweep(self, n: int = 1):
+        _check(lib().tfim_sweep(self._h, int(n)), "tfim_sweep")
+
+    def pt_swap(self):
+        _check(lib().tfim_pt_swap(self._h), "tfim_pt_swap")
+
+    def sync(self):
+        _check(lib().tfim_sync(self._h), "tfim_sync")
+
+    def set_schedule(self, schedule: int):
+        _check(lib().tfim_set_schedule(self._h, schedule), "tfim_set_schedule")
+
+    def autotune(self, sweeps_per_trial: int = 2):
+        _check(lib().tfim_autotune(self._h, sweeps_per_trial), "tfim_autotune")
+
+    def tuning(self):
+        cid = ctypes.c_uint32()
+        ms = ctypes.c_double()
+        _check(lib().tfim_get_tuning(self._h, ctypes.byref(cid), ctypes.byref(ms)), "tfim_get_tuning")
+        return cid.value, ms.value
+
+    def export_spins(self, shape: int = 0) -> np.ndarray:
+        L, Lt, W, R, nk = self._dims(shape)
+        S = np.zeros((R, nk, W, Lt, L * L), dtype=np.uint64)
+        _check(lib().tfim_export_spins(self._h, shape, _ptr(S)), "tfim_export_spins")
+        return S
+
+    def export_couplings(self, shape: int = 0) -> np.ndarray:
+        L, Lt, W, R, nk = self._dims(shape)
+        J = np.zeros((W, 2, L * L), dtype=np.uint64)
+        _check(lib().tfim_export_couplings(self._h, shape, _ptr(J)), "tfim_export_couplings")
+        return J
+
+    def get_state(self, shape: int = 0):
+        L, Lt, W, R, nk = self._dims(shape)
+        kidx = np.zeros((R, 64 * W, nk), dtype=np.uint8)
+        U = np.zeros((R, 64 * W, nk), dtype=np.uint32)
+        _check(lib().tfim_get_state(self._h, shape, _ptr(kidx), _ptr(U)), "tfim_get_state")
+        return kidx, U
+
+    def counters(self, shape: int = 0):
+        t = ctypes.c_uint64()
+        m = ctypes.c_uint64()
+        _check(lib().tfim_get_counters(self._h, shape, ctypes.byref(t), ctypes.byref(m)),
+               "tfim_get_counters")
+        return t.value, m.value
+
+    def set_state(self, shape: int, S: np.ndarray, kidx: np.ndarray, t: int, m: int):
+        _check(lib().tfim_set_state(self._h, shape, _ptr(np.ascontiguousarray(S, dtype=np.uint64)),
+                                    _ptr(np.ascontiguousarray(kidx, dtype=np.uint8)), t, m),
+               "tfim_set_state")
+
+    def thresholds(self, shape: int = 0):
+        nk = len(self._k[shape])
+        Tm = np.zeros((nk, 3), dtype=np.uint32)
+        dmax = np.zeros(max(nk - 1, 1), dtype=np.uint32)
+        n = ctypes.c_size_t()
+        _check(lib().tfim_get_thresholds(self._h, shape, _ptr(Tm), _ptr(dmax), None, 0,
+                                         ctypes.byref(n)), "tfim_get_thresholds")
+        Tpt = np.zeros(max(n.value, 1), dtype=np.uint32)
+        _check(lib().tfim_get_thresholds(self._h, shape, None, None, _ptr(Tpt), Tpt.size,
+                                         ctypes.byref(n)), "tfim_get_thresholds")
+        return Tm, dmax[:nk - 1], Tpt[:n.value]
+
+    def measure(self, shape: int = 0, what: int = TFIM_MEASURE_RECORDS) -> np.ndarray:
+        L, Lt, W, R, nk = self._dims(shape)
+        P = R * (R - 1) // 2
+        if what == TFIM_MEASURE_RECORDS:
+            out = np.zeros((nk, 64 * W, P, 2 * L + 3), dtype=np.int64)
+        elif what == TFIM_MEASURE_BUCKETS:
+            out = np.zeros((nk, 2, L), dtype=np.int64)
+        elif what == TFIM_MEASURE_ENERGY:
+            out = np.zeros((R, 64 * W, nk), dtype=np.uint32)
+        else:
+            raise ValueError("unknown measurement")
+        _check(lib().tfim_measure(self._h, shape, what, _ptr(out), out.nbytes), "tfim_measure")
+        return out
+
+    def dump_gram(self, shape: int, i: int, s: int, a: int, b: int):
+        L, Lt, W, R, nk = self._dims(shape)
+        Ga = np.zeros((L * L, L * L), dtype=np.int32)
+        Gb = np.zeros((L * L, L * L), dtype=np.int32)
+        Q = np.zeros((Lt, Lt), dtype=np.int32)
+        _check(lib().tfim_dump_gram(self._h, shape, i, s, a, b, _ptr(Ga), _ptr(Gb), _ptr(Q)),
+               "tfim_dump_gram")
+        return Ga, Gb, Q
+
+
+def plan_shapes_only(shapes: Sequence, seed: int) -> Plan:
+    """A plan without a device arena (host-only calls: sizes, thresholds)."""
+    return Plan(shapes, seed, bind=False)
+
+
+def unpack_lane(words: np.ndarray, b: int) -> np.ndarray:
+    """+-1 int8 spins of lane b from uint64 words (bit 1 = -1)."""
+    bits = (words >> np.uint64(b)) & np.uint64(1)
+    return (1 - 2 * bits.astype(np.int8)).astype(np.int8)
+
+
+def lanes_of(words: np.ndarray, samples: List[int], word_axis: int) -> np.ndarray:
+    """Gather +-1 spins of the given samples from canonical words; the word
+    axis is replaced by a sample axis."""
+    out = []
+    for s in samples:
+        w = np.take(words, s // 64, axis=word_axis)
+        out.append(unpack_lane(w, s % 64))
+    return np.stack(out, axis=word_axis)

@@ -1,0 +1,105 @@
+"""Host-side checks of the C ABI (no GPU needed): every declared symbol is
+exported, argument validation, arena sizes, and the host threshold tables and
+xi^(2) against the oracle."""
+import math
+import re
+import os
+
+import numpy as np
+import pytest
+
+from paper_2310_07486_amd import tfim
+from paper_2310_07486_amd.workloads import Shape, ladder, c2_multispin, c3_large
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    return tfim.lib()
+
+
+def test_header_symbols_exported(L):
+    text = open(os.path.join(ROOT, "include", "tfim.h")).read()
+    declared = set(re.findall(r"\b(tfim_[a-z0-9_]+)\s*\(", text))
+    assert declared == set(tfim.SYMBOLS)
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def _plan(shapes, seed=1):
+    return tfim.plan_shapes_only(shapes, seed)
+
+
+@pytest.mark.parametrize("bad,status", [
+    (dict(L=7), tfim.TFIM_EINVAL), (dict(L=26), tfim.TFIM_EINVAL),
+    (dict(Ltau=30), tfim.TFIM_EUNSUPPORTED), (dict(Ltau=3), tfim.TFIM_EINVAL),
+    (dict(n_words=0), tfim.TFIM_EINVAL), (dict(n_replicas=0), tfim.TFIM_EINVAL),
+    (dict(k=[0.3, 0.2]), tfim.TFIM_EINVAL), (dict(k=[0.0, 0.2]), tfim.TFIM_EINVAL),
+    (dict(k=[0.2, 0.2]), tfim.TFIM_EINVAL),
+])
+def test_plan_validation(bad, status):
+    kw = dict(L=8, Ltau=32, n_words=1, n_replicas=2, k=[0.2, 0.3], pt_every=1)
+    kw.update(bad)
+    with pytest.raises(tfim.TfimError) as e:
+        _plan([Shape(**kw)])
+    assert e.value.status == status
+
+
+def test_antiperiodic_unsupported_and_stream_ids():
+    s = Shape(8, 32, 1, 2, [0.2, 0.3])
+    s.bc_tau = tfim.TFIM_BC_ANTIPERIODIC
+    with pytest.raises(tfim.TfimError) as e:
+        _plan([s])
+    assert e.value.status == tfim.TFIM_EUNSUPPORTED
+    with pytest.raises(tfim.TfimError) as e:
+        _plan([Shape(8, 32, 1, 2, [0.2], stream_id=3), Shape(8, 64, 1, 2, [0.2], stream_id=3)])
+    assert e.value.status == tfim.TFIM_EINVAL
+
+
+def test_arena_sizes_cover_state():
+    w = c3_large()
+    p = _plan(w.shapes)
+    s = w.shapes[0]
+    assert p.sizes["spins"] == s.n_replicas * len(s.k) * s.n_words * s.L ** 2 * s.Ltau * 8
+    assert p.sizes["spins"] == 19_327_352_832  # 19.33 GB of spin words
+    assert p.sizes["total"] >= sum(v for k, v in p.sizes.items() if k != "total")
+
+
+def test_unbound_plan_refuses_device_calls():
+    p = _plan([Shape(8, 32, 1, 2, [0.2, 0.3])])
+    with pytest.raises(tfim.TfimError) as e:
+        p.sweep(1)
+    assert e.value.status == tfim.TFIM_ESTATE
+
+
+def test_thresholds_equal_oracle(oracle_lib):
+    for w in (c2_multispin(), c3_large()):
+        s = w.shapes[0]
+        p = _plan(w.shapes)
+        Tm, dmax, Tpt = p.thresholds(0)
+        To = oracle_lib.metro_thresholds(s.k)  # [i][q], dE = 4(q+1)
+        assert np.array_equal(Tm, To[:, ::-1])  # u unsatisfied -> dE = 12 - 4u
+        off = 0
+        for i in range(len(s.k) - 1):
+            dk = s.k[i + 1] - s.k[i]
+            for d in [1, 2, 3, 50, int(dmax[i])]:
+                assert Tpt[off + d - 1] == oracle_lib.pt_threshold(dk, 2 * d)
+            assert oracle_lib.pt_threshold(dk, 2 * (int(dmax[i]) + 1)) == 0
+            off += int(dmax[i])
+        assert off == len(Tpt)
+    # the default ladder's largest swap table entry index (32-bit resolution)
+    assert int(dmax[0]) == 2455
+
+
+def test_xi2_matches_oracle(oracle_lib):
+    from oracle import measure as om
+    rng = np.random.default_rng(4)
+    for L in (8, 12, 24):
+        A = rng.integers(10**9, 10**12, size=(5, L)).astype(np.int64)
+        A[:, 0] *= 50  # a dominant zero-distance bucket keeps chi/F > 1
+        got = tfim.tfim_xi2(A, L)
+        for i in range(5):
+            want = om.xi2(A[i], L)
+            assert abs(got[i] - want) <= 1e-12 * abs(want), (L, i, got[i], want)
+    assert math.isinf(tfim.tfim_xi2(np.array([[1] + [0] * 5 + [9] + [0] * 5]), 12)[0])

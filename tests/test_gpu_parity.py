@@ -1,0 +1,181 @@
+"""GPU parity: the HIP path (through the C ABI) against the oracle, bit for
+bit, on spins, k labels (tempering decisions) and energies.
+
+Sizes span several spatial tiles and tau chunks; the full-size shapes are
+compared on a subset of samples, which the oracle follows exactly (a
+sample's trajectory depends only on its own couplings, spins and labels and
+on the shared counter-based random numbers).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2310_07486_amd import tfim
+from paper_2310_07486_amd.workloads import Shape, ladder, c1_plain, c2_multispin, c3_large
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _compare(plan, shape_idx, sh, seed, lanes, n_sweeps, chain=None):
+    S = plan.export_spins(shape_idx)
+    kidx, U = plan.get_state(shape_idx)
+    if chain is None:
+        chain = oracle.Chain(sh.L, sh.Ltau, sh.k, sh.n_replicas, seed, lanes,
+                             pt_every=sh.pt_every, stream_id=sh.stream_id,
+                             word_offset=sh.word_offset)
+        chain.run(n_sweeps)
+    got = tfim.lanes_of(S, lanes, word_axis=2)
+    nbad = int((got != chain.S).sum())
+    assert nbad == 0, f"{nbad} spins differ"
+    assert np.array_equal(kidx[:, lanes], chain.kidx), "k labels differ"
+    assert np.array_equal(U[:, lanes], chain.U), "energies differ"
+    return chain
+
+
+def test_init_couplings_spins_energy():
+    sh = Shape(12, 64, 2, 3, ladder(0.2, 0.4, 5), pt_every=1, stream_id=7, word_offset=3)
+    seed = 77
+    _say("init parity L=12 Ltau=64 W=2 R=3 nk=5")
+    plan = tfim.Plan([sh], seed)
+    plan.init()
+    J = plan.export_couplings(0)
+    lanes = [0, 1, 63, 64, 100, 127]
+    ch = oracle.Chain(sh.L, sh.Ltau, sh.k, sh.n_replicas, seed, lanes, stream_id=7, word_offset=3)
+    Jx = tfim.lanes_of(J[:, 0], lanes, word_axis=0)
+    Jy = tfim.lanes_of(J[:, 1], lanes, word_axis=0)
+    assert np.array_equal(Jx, ch.Jx) and np.array_equal(Jy, ch.Jy)
+    _compare(plan, 0, sh, seed, lanes, 0, chain=ch)
+    assert plan.counters() == (0, 0)
+
+
+@pytest.mark.parametrize("L,Lt,W,R,nk,pt", [
+    (4, 16, 1, 2, 4, 1), (6, 24, 1, 2, 3, 2), (8, 32, 2, 2, 6, 1), (10, 8, 1, 1, 2, 1),
+    (16, 64, 1, 2, 8, 3), (24, 16, 1, 2, 4, 1), (2, 8, 1, 2, 2, 1),
+])
+def test_sweep_and_tempering_small(L, Lt, W, R, nk, pt):
+    sh = Shape(L, Lt, W, R, ladder(0.18, 0.42, nk), pt_every=pt)
+    seed = 1000 + L
+    _say(f"sweep parity L={L} Lt={Lt} W={W} R={R} nk={nk} pt={pt}")
+    plan = tfim.Plan([sh], seed)
+    plan.init()
+    plan.sweep(9)
+    plan.sweep(6)
+    plan.sync()
+    lanes = list(range(64 * W)) if L <= 8 else [0, 5, 31, 62, 63]
+    _compare(plan, 0, sh, seed, lanes, 15)
+    assert plan.counters() == (15, (15 // pt))
+
+
+def test_explicit_pt_swap_and_counters():
+    sh = Shape(8, 16, 1, 2, ladder(0.2, 0.5, 6), pt_every=0)
+    seed = 5
+    _say("explicit pt_swap L=8 Lt=16")
+    plan = tfim.Plan([sh], seed)
+    plan.init()
+    plan.sweep(3)
+    plan.pt_swap()
+    plan.sweep(2)
+    plan.pt_swap()
+    plan.pt_swap()
+    plan.sync()
+    lanes = list(range(64))
+    ch = oracle.Chain(sh.L, sh.Ltau, sh.k, sh.n_replicas, seed, lanes, pt_every=0)
+    ch.run(3)
+    ch.pt_step()
+    ch.run(2)
+    ch.pt_step()
+    ch.pt_step()
+    _compare(plan, 0, sh, seed, lanes, 0, chain=ch)
+    assert plan.counters() == (5, 3)
+
+
+def test_c1_plain_lane_2000_sweeps():
+    w = c1_plain()
+    sh = w.shapes[0]
+    _say("C1 parity: L=8 Ltau=32 k=0.29 R=2, 2000 sweeps")
+    plan = tfim.Plan([sh], w.seed)
+    plan.init()
+    plan.sweep(w.sweeps)
+    plan.sync()
+    _compare(plan, 0, sh, w.seed, [0, 17, 63], w.sweeps)
+
+
+def test_c2_multispin_1000_sweeps():
+    w = c2_multispin()
+    sh = w.shapes[0]
+    _say("C2 parity: L=16 Ltau=256 W=1 R=4 nk=32, 1000 sweeps")
+    plan = tfim.Plan([sh], w.seed)
+    plan.init()
+    plan.sweep(1000)
+    plan.sync()
+    _compare(plan, 0, sh, w.seed, [0, 37], 1000)
+
+
+def test_c3_full_shape_slice():
+    w = c3_large()
+    sh = w.shapes[0]
+    _say("C3 parity: L=24 Ltau=2048 W=16 R=4 nk=32 (19.3 GB), 4 sweeps, 2 lanes")
+    plan = tfim.Plan([sh], w.seed)
+    plan.init()
+    plan.sweep(4)
+    plan.sync()
+    _compare(plan, 0, sh, w.seed, [0, 999], 4)
+    plan.close()
+
+
+def test_checkpoint_resume_bitwise():
+    sh = Shape(8, 64, 1, 2, ladder(0.2, 0.4, 5), pt_every=2)
+    seed = 31
+    _say("resume parity L=8 Lt=64")
+    a = tfim.Plan([sh], seed)
+    a.init()
+    a.sweep(7)
+    S = a.export_spins(0)
+    kidx, _ = a.get_state(0)
+    t, m = a.counters()
+    a.sweep(9)
+    b = tfim.Plan([sh], seed)
+    b.init_couplings(0)
+    b.set_state(0, S, kidx, t, m)
+    b.sweep(9)
+    assert np.array_equal(a.export_spins(0), b.export_spins(0))
+    assert all(np.array_equal(x, y) for x, y in zip(a.get_state(0), b.get_state(0)))
+
+
+def test_word_offset_shards_equal_whole():
+    k = ladder(0.2, 0.4, 4)
+    whole = Shape(8, 32, 2, 2, k, pt_every=1)
+    s0 = Shape(8, 32, 1, 2, k, pt_every=1, word_offset=0)
+    s1 = Shape(8, 32, 1, 2, k, pt_every=1, word_offset=1)
+    seed = 9
+    _say("shard parity")
+    plans = [tfim.Plan([x], seed) for x in (whole, s0, s1)]
+    for p in plans:
+        p.init()
+        p.sweep(5)
+    Sw = plans[0].export_spins(0)
+    assert np.array_equal(Sw[:, :, 0:1], plans[1].export_spins(0))
+    assert np.array_equal(Sw[:, :, 1:2], plans[2].export_spins(0))
+
+
+def test_multi_shape_plan_equals_single_shape_plans():
+    shapes = [Shape(8, 32, 1, 2, ladder(0.25, 0.3, 4), stream_id=0),
+              Shape(12, 16, 2, 2, ladder(0.2, 0.35, 5), stream_id=1, pt_every=2)]
+    seed = 12
+    _say("multi-shape plan parity")
+    both = tfim.Plan(shapes, seed)
+    both.init()
+    both.sweep(6)
+    for i, s in enumerate(shapes):
+        one = tfim.Plan([s], seed)
+        one.init()
+        one.sweep(6)
+        assert np.array_equal(both.export_spins(i), one.export_spins(0))
+        assert all(np.array_equal(x, y) for x, y in zip(both.get_state(i), one.get_state(0)))

@@ -1,4 +1,10 @@
-"""Compile libtfim.so (HIP, gfx950) in-tree with hipcc."""
+"""Compile libtfim.so (HIP, gfx950) in-tree.
+
+The kernels and host runtime are compiled with hipcc; the shared library is
+linked against the HIP runtime that PyTorch loads (torch/lib/libamdhip64.so),
+so libtfim, torch's allocator and torch's streams share one HIP runtime and
+one device context in the process.
+"""
 from __future__ import annotations
 
 import glob
@@ -12,11 +18,24 @@ LIB = os.path.join(HERE, "libtfim.so")
 ARCH = os.environ.get("TFIM_OFFLOAD_ARCH", "gfx950")
 
 HIP_FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
+    "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+    "-mcode-object-version=5",
     # keep hipcc from forming packed-FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
 ]
+
+
+def torch_lib_dir() -> str:
+    """Directory of the HIP runtime torch uses (found without importing torch)."""
+    import importlib.util
+    spec = importlib.util.find_spec("torch")
+    if spec is None or not spec.submodule_search_locations:
+        raise RuntimeError("torch (ROCm build) is required: libtfim shares its HIP runtime")
+    d = os.path.join(list(spec.submodule_search_locations)[0], "lib")
+    if not os.path.exists(os.path.join(d, "libamdhip64.so")):
+        raise RuntimeError(f"no libamdhip64.so under {d}")
+    return d
 
 
 def sources():
@@ -26,11 +45,24 @@ def sources():
 def build(verbose: bool = False) -> str:
     """Always recompiles (this is the build check); returns the library path."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    inc = os.path.join(HERE, "..", "include")
+    objs = []
+    for src in sources():
+        obj = os.path.join(objdir, os.path.basename(src) + ".o")
+        cmd = [hipcc, *HIP_FLAGS, "-I", inc, "-c", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+        objs.append(obj)
+    tdir = torch_lib_dir()
     tmp = LIB + ".tmp"
-    cmd = [hipcc, *HIP_FLAGS, "-I", os.path.join(HERE, "..", "include"), "-o", tmp, *sources()]
+    link = ["g++", "-shared", "-o", tmp, *objs, f"-L{tdir}", "-l:libamdhip64.so",
+            f"-Wl,-rpath,{tdir}", "-Wl,--no-undefined", "-Wl,--no-as-needed"]
     if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
+        print(" ".join(link), flush=True)
+    subprocess.check_call(link)
     os.replace(tmp, LIB)
     return LIB
 

@@ -69,6 +69,11 @@ def lib():
     """Load libtfim.so (raises if it has not been built)."""
     global _lib
     if _lib is None:
+        # torch's HIP runtime must be the one in the process before libtfim is
+        # loaded: libtfim's libamdhip64.so.7 dependency then resolves to it by
+        # soname, so the library, torch's allocator and torch's streams share
+        # one runtime and one device context.
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"libtfim.so not built at {LIB_PATH}; run __graft_entry__.build()")
         L = ctypes.CDLL(LIB_PATH)

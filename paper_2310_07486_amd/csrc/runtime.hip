@@ -34,9 +34,11 @@ struct ShapeHost {
     std::vector<uint32_t> dmax;     // [nk]  (last entry 0)
     std::vector<uint32_t> tpt_off;  // [nk]
     std::vector<uint32_t> Tpt;      // concatenated
+    std::vector<uint64_t> btab;     // threshold bucket tables, all u
+    int bsh[3] = {0, 0, 0}, bnb[3] = {-1, -1, -1}, boff[3] = {0, 0, 0};
     // arena offsets
     size_t oS = 0, oJ = 0, oK = 0, oWinv = 0, oU = 0, oMask = 0, oTu = 0, oTpt = 0, oTptOff = 0,
-           oDmax = 0, oRec = 0, oBuck = 0;
+           oDmax = 0, oRec = 0, oBuck = 0, oBtab = 0;
     size_t nS = 0, nJ = 0, nLab = 0, nMask = 0, nRec = 0, nBuck = 0;
     bool J_ready = false, S_ready = false;
     int P = 0;
@@ -88,6 +90,12 @@ tfim::ShapeDev dev_of(const tfim_plan* pl, int i) {
     d.dmax = (const uint32_t*)(a + h.oDmax);
     d.rec = (int64_t*)(a + h.oRec);
     d.buckets = (int64_t*)(a + h.oBuck);
+    d.btab = (const uint64_t*)(a + h.oBtab);
+    for (int u = 0; u < 3; ++u) {
+        d.bsh[u] = h.bsh[u];
+        d.bnb[u] = h.bnb[u];
+        d.boff[u] = h.boff[u];
+    }
     return d;
 }
 
@@ -142,6 +150,57 @@ void build_tables(ShapeHost& h) {
         h.dmax[i] = d;
     }
     if (h.Tpt.empty()) h.Tpt.push_back(0);
+}
+
+// Bucket tables for the per-lane threshold count K_u(R) (see ShapeDev).
+// For each u, the largest shift such that every bucket [a 2^sh, (a+1) 2^sh)
+// holds at most one distinct threshold strictly inside it, with at most
+// kMaxBuckets buckets; bnb[u] = -1 if no such shift exists.
+constexpr int kMaxBuckets = 1024;
+
+void build_buckets(ShapeHost& h) {
+    const int nk = (int)h.s.n_k;
+    h.btab.clear();
+    for (int u = 0; u < 3; ++u) {
+        std::vector<uint64_t> T(nk);
+        for (int i = 0; i < nk; ++i) T[i] = h.Tu[(size_t)i * 3 + u];
+        const uint64_t Tmax = *std::max_element(T.begin(), T.end());
+        int chosen = -1;
+        for (int sh = 31; sh >= 0; --sh) {
+            const uint64_t nb = (Tmax >> sh) + 1;
+            if (nb > (uint64_t)kMaxBuckets) break;
+            bool ok = true;
+            for (uint64_t a = 0; a <= nb && ok; ++a) {
+                const uint64_t lo = a << sh, hi = (a + 1) << sh;
+                uint64_t v = UINT64_MAX;
+                for (int i = 0; i < nk; ++i)
+                    if (T[i] > lo && T[i] < hi) {
+                        if (v == UINT64_MAX) v = T[i];
+                        else if (v != T[i]) { ok = false; break; }
+                    }
+            }
+            if (ok) { chosen = sh; break; }
+        }
+        h.boff[u] = (int)h.btab.size();
+        if (chosen < 0) {
+            h.bnb[u] = -1;
+            h.bsh[u] = 0;
+            continue;
+        }
+        const uint64_t nb = (Tmax >> chosen) + 1;
+        h.bsh[u] = chosen;
+        h.bnb[u] = (int)nb;
+        for (uint64_t a = 0; a <= nb; ++a) {
+            const uint64_t lo = a << chosen, hi = (a + 1) << chosen;
+            uint64_t kbase = 0, mult = 0, tstar = 0;
+            for (int i = 0; i < nk; ++i) {
+                if (T[i] >= hi) ++kbase;
+                else if (T[i] > lo) { tstar = T[i]; ++mult; }
+            }
+            h.btab.push_back(tstar | (kbase << 32) | (mult << 48));
+        }
+    }
+    if (h.btab.empty()) h.btab.push_back(0);
 }
 
 tfim_status validate(const tfim_shape* s, uint32_t n) {
@@ -214,6 +273,7 @@ tfim_status tfim_plan_create(const tfim_shape* shapes, uint32_t n_shapes, uint64
         h.s.k = nullptr;
         h.P = (int)(h.s.n_replicas * (h.s.n_replicas - 1) / 2);
         build_tables(h);
+        build_buckets(h);
         const size_t L2 = (size_t)h.s.L * h.s.L, nk = h.s.n_k, W = h.s.n_words,
                      R = h.s.n_replicas, Lt = h.s.Ltau, S = 64 * W;
         h.nS = R * nk * W * Lt * L2 * 8;
@@ -233,7 +293,8 @@ tfim_status tfim_plan_create(const tfim_shape* shapes, uint32_t n_shapes, uint64
         h.oTpt = off; off = align256(off + h.Tpt.size() * 4);
         h.oTptOff = off; off = align256(off + nk * 4);
         h.oDmax = off; off = align256(off + nk * 4);
-        tot_tab += (h.Tu.size() + h.Tpt.size() + 2 * nk) * 4;
+        h.oBtab = off; off = align256(off + h.btab.size() * 8);
+        tot_tab += (h.Tu.size() + h.Tpt.size() + 2 * nk) * 4 + h.btab.size() * 8;
         h.oRec = off; off = align256(off + h.nRec);
         h.oBuck = off; off = align256(off + h.nBuck);
         tot_meas += h.nRec + h.nBuck;
@@ -286,6 +347,8 @@ tfim_status tfim_bind(tfim_plan* pl, void* arena, size_t bytes, void* stream) {
             e = hipMemcpyAsync(pl->arena + h.oTptOff, h.tpt_off.data(), h.tpt_off.size() * 4, hipMemcpyHostToDevice, pl->stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(pl->arena + h.oDmax, h.dmax.data(), h.dmax.size() * 4, hipMemcpyHostToDevice, pl->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(pl->arena + h.oBtab, h.btab.data(), h.btab.size() * 8, hipMemcpyHostToDevice, pl->stream);
         h.J_ready = h.S_ready = false;
     }
     std::vector<tfim::Counters> c(pl->shapes.size());

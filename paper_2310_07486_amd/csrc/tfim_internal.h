@@ -26,6 +26,12 @@ struct ShapeDev {
     const uint32_t* dmax;
     int64_t* rec;           // measurement records [nk][W*64][P][2L+3]
     int64_t* buckets;       // [nk][2][L]
+    // Bucket tables for K_u(R) = #{i : Tu[i][u] > R}: for u, R falls in
+    // bucket a = min(R >> bsh[u], bnb[u]); entry (btab + boff[u])[a] packs
+    // Tstar (bits 0..31), Kbase (32..47), mult (48..63) so that
+    // K_u(R) = Kbase + (R < Tstar ? mult : 0).  bnb[u] = -1: no table.
+    const uint64_t* btab;
+    int bsh[3], bnb[3], boff[3];
 };
 
 // Plan-wide device counters.

@@ -201,6 +201,18 @@ tfim_status tfim_set_schedule(tfim_plan *plan, uint32_t schedule);
 tfim_status tfim_autotune(tfim_plan *plan, uint32_t sweeps_per_trial);
 tfim_status tfim_get_tuning(const tfim_plan *plan, uint32_t *config_id, double *ms_per_sweep);
 
+/* Sweep kernel variant (all give bit-identical chains):
+ * 0 = streaming (one barrier per two tau planes; default),
+ * 1 = chunked (eight tau planes per step).  Host-only. */
+tfim_status tfim_set_variant(tfim_plan *plan, uint32_t variant);
+
+/* Kernel timing: while enabled, tfim_sweep records a pair of HIP events on
+ * the bound stream around every sweep-kernel launch.  tfim_get_timing
+ * synchronises the stream, returns the summed kernel time in ms and the
+ * number of timed launches since the last call, and resets them. */
+tfim_status tfim_set_timing(tfim_plan *plan, uint32_t enable);
+tfim_status tfim_get_timing(tfim_plan *plan, double *kernel_ms, uint64_t *launches);
+
 /* Wait for the bound stream; asynchronous device faults surface here as
  * TFIM_EDEVICE. */
 tfim_status tfim_sync(tfim_plan *plan);

@@ -38,8 +38,9 @@ struct ShapeHost {
     int bsh[3] = {0, 0, 0}, bnb[3] = {-1, -1, -1}, boff[3] = {0, 0, 0};
     // arena offsets
     size_t oS = 0, oJ = 0, oK = 0, oWinv = 0, oU = 0, oMask = 0, oTu = 0, oTpt = 0, oTptOff = 0,
-           oDmax = 0, oRec = 0, oBuck = 0, oBtab = 0;
-    size_t nS = 0, nJ = 0, nLab = 0, nMask = 0, nRec = 0, nBuck = 0;
+           oDmax = 0, oRec = 0, oBuck = 0, oBtab = 0, oPt = 0, oPx = 0, oDump = 0;
+    size_t nS = 0, nJ = 0, nLab = 0, nMask = 0, nRec = 0, nBuck = 0, nPt = 0, nPx = 0, nDump = 0;
+    int nc = 0, nx = 0;
     bool J_ready = false, S_ready = false;
     int P = 0;
 };
@@ -60,6 +61,9 @@ struct tfim_plan {
     int variant = 0;
     double tuned_ms = 0.0;
     std::map<uint64_t, hipGraphExec_t> graphs;  // keyed by (n, t phase) for the per-shape schedule
+    // HIP-event timing of sweep-kernel launches (tfim_set_timing)
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used, ev_free;
 };
 
 namespace {
@@ -91,6 +95,12 @@ tfim::ShapeDev dev_of(const tfim_plan* pl, int i) {
     d.rec = (int64_t*)(a + h.oRec);
     d.buckets = (int64_t*)(a + h.oBuck);
     d.btab = (const uint64_t*)(a + h.oBtab);
+    d.Pt = (uint64_t*)(a + h.oPt);
+    d.Px = (uint64_t*)(a + h.oPx);
+    d.dump = (int32_t*)(a + h.oDump);
+    d.nc = h.nc;
+    d.nx = h.nx;
+    d.nxp = 64 * h.nx;
     for (int u = 0; u < 3; ++u) {
         d.bsh[u] = h.bsh[u];
         d.bnb[u] = h.bnb[u];
@@ -282,6 +292,11 @@ tfim_status tfim_plan_create(const tfim_shape* shapes, uint32_t n_shapes, uint64
         h.nMask = R * W * nk * (nk + 1) * 8;
         h.nRec = h.P ? nk * S * h.P * (2 * h.s.L + 3) * 8 : 0;
         h.nBuck = nk * 2 * h.s.L * 8;
+        h.nc = (int)((Lt + 63) / 64);
+        h.nx = (int)((L2 + 63) / 64);
+        h.nPt = h.P ? nk * S * R * (size_t)h.nc * 64 * h.nx * 8 : 0;
+        h.nPx = h.P ? nk * S * R * (size_t)h.nx * Lt * 8 : 0;
+        h.nDump = h.P ? (2 * L2 * L2 + Lt * Lt) * 4 : 0;
         h.oS = off; off = align256(off + h.nS); tot_S += h.nS;
         h.oJ = off; off = align256(off + h.nJ); tot_J += h.nJ;
         h.oK = off; off = align256(off + h.nLab);
@@ -297,7 +312,10 @@ tfim_status tfim_plan_create(const tfim_shape* shapes, uint32_t n_shapes, uint64
         tot_tab += (h.Tu.size() + h.Tpt.size() + 2 * nk) * 4 + h.btab.size() * 8;
         h.oRec = off; off = align256(off + h.nRec);
         h.oBuck = off; off = align256(off + h.nBuck);
-        tot_meas += h.nRec + h.nBuck;
+        h.oPt = off; off = align256(off + h.nPt);
+        h.oPx = off; off = align256(off + h.nPx);
+        h.oDump = off; off = align256(off + h.nDump);
+        tot_meas += h.nRec + h.nBuck + h.nPt + h.nPx + h.nDump;
         pl->shapes.push_back(std::move(h));
     }
     pl->oCounters = off;
@@ -315,8 +333,19 @@ tfim_status tfim_plan_create(const tfim_shape* shapes, uint32_t n_shapes, uint64
     return TFIM_OK;
 }
 
+static void drop_events(tfim_plan* pl) {
+    for (auto* v : {&pl->ev_used, &pl->ev_free})
+        for (auto& e : *v) {
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+    pl->ev_used.clear();
+    pl->ev_free.clear();
+}
+
 void tfim_plan_destroy(tfim_plan* pl) {
     if (!pl) return;
+    drop_events(pl);
     for (auto& kv : pl->graphs) (void)hipGraphExecDestroy(kv.second);
     delete pl;
 }
@@ -434,13 +463,41 @@ static tfim_status all_ready(tfim_plan* pl) {
     return TFIM_OK;
 }
 
+static hipError_t timed_sweep(tfim_plan* pl, int i, bool energy) {
+    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+    hipError_t e = hipSuccess;
+    if (pl->timing) {
+        if (pl->ev_free.empty()) {
+            e = hipEventCreate(&ev.first);
+            if (e == hipSuccess) e = hipEventCreate(&ev.second);
+            if (e != hipSuccess) return e;
+        } else {
+            ev = pl->ev_free.back();
+            pl->ev_free.pop_back();
+        }
+        e = hipEventRecord(ev.first, pl->stream);
+    }
+    if (e == hipSuccess)
+        e = tfim::launch_sweep(dev_of(pl, i), pl->seed, counters_of(pl, i), pl->variant, energy,
+                               pl->stream);
+    if (pl->timing) {
+        if (e == hipSuccess) e = hipEventRecord(ev.second, pl->stream);
+        pl->ev_used.push_back(ev);
+    }
+    return e;
+}
+
 // Enqueue one sweep of every shape (plus due tempering) with the per-shape
-// schedule; the host mirrors pl->t hold each shape's sweep counter.
-static hipError_t enqueue_sweep(tfim_plan* pl) {
+// schedule; the host mirrors pl->t hold each shape's sweep counter.  U is
+// recounted when a tempering step follows or when the caller will see it.
+static hipError_t enqueue_sweep(tfim_plan* pl, bool last) {
     hipError_t e = hipSuccess;
     const int ns = (int)pl->shapes.size();
-    for (int i = 0; i < ns && e == hipSuccess; ++i)
-        e = tfim::launch_sweep(dev_of(pl, i), pl->seed, counters_of(pl, i), pl->variant, pl->stream);
+    for (int i = 0; i < ns && e == hipSuccess; ++i) {
+        const uint32_t pe = pl->shapes[i].s.pt_every;
+        const bool due = pe > 0 && ((pl->t[i] + 1) % pe) == 0;
+        e = timed_sweep(pl, i, due || last);
+    }
     for (int i = 0; i < ns && e == hipSuccess; ++i) {
         const uint32_t pe = pl->shapes[i].s.pt_every;
         const bool due = pe > 0 && ((pl->t[i] + 1) % pe) == 0;
@@ -459,7 +516,7 @@ tfim_status tfim_sweep(tfim_plan* pl, uint64_t n) {
         if (pl->t[i] + n > 0xFFFFFFFFull) return fail(TFIM_EOVERFLOW, "sweep counter would pass 2^32-1");
     hipError_t e = hipSuccess;
     for (uint64_t s = 0; s < n && e == hipSuccess; ++s) {
-        e = enqueue_sweep(pl);
+        e = enqueue_sweep(pl, s + 1 == n);
         if (e != hipSuccess) break;
         for (size_t i = 0; i < pl->shapes.size(); ++i) {
             const uint32_t pe = pl->shapes[i].s.pt_every;
@@ -612,6 +669,37 @@ tfim_status tfim_xi2(const int64_t* A, uint32_t L, uint32_t n_k, double* xi) {
         const double ratio = chi / F;
         xi[i] = ratio < 1.0 ? NAN : std::sqrt(ratio - 1.0) / s;
     }
+    return TFIM_OK;
+}
+
+tfim_status tfim_set_timing(tfim_plan* pl, uint32_t enable) {
+    if (!pl) return fail(TFIM_EINVAL, "null plan");
+    pl->timing = enable != 0;
+    return TFIM_OK;
+}
+
+tfim_status tfim_get_timing(tfim_plan* pl, double* ms_total, uint64_t* launches) {
+    tfim_status st = usable(pl);
+    if (st != TFIM_OK) return st;
+    double tot = 0.0;
+    hipError_t e = hipStreamSynchronize(pl->stream);
+    for (auto& ev : pl->ev_used) {
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev.first, ev.second);
+        tot += ms;
+        pl->ev_free.push_back(ev);
+    }
+    const uint64_t n = pl->ev_used.size();
+    pl->ev_used.clear();
+    if (ms_total) *ms_total = tot;
+    if (launches) *launches = n;
+    return check_hip(pl, e, "timing");
+}
+
+tfim_status tfim_set_variant(tfim_plan* pl, uint32_t variant) {
+    if (!pl) return fail(TFIM_EINVAL, "null plan");
+    if (variant >= (uint32_t)tfim::sweep_variants()) return fail(TFIM_EINVAL, "unknown sweep variant");
+    pl->variant = (int)variant;
     return TFIM_OK;
 }
 

@@ -405,12 +405,20 @@ int block_for(const ShapeDev& sh) { return ((sh.L2 + 63) / 64) * 64; }
 
 }  // namespace
 
-int sweep_variants() { return 1; }
-const char* sweep_variant_name(int v) { return v == 0 ? "fused-wavefront-v1" : "?"; }
+int sweep_variants() { return 3; }
+const char* sweep_variant_name(int v) {
+    switch (v) {
+        case 0: return "stream";
+        case 1: return "chunk8";
+        case 2: return "stream-occ5";
+        default: return "?";
+    }
+}
 
 hipError_t launch_sweep(const ShapeDev& sh, uint64_t seed, const Counters* ctr, int variant,
-                        hipStream_t st) {
-    (void)variant;
+                        bool energy, hipStream_t st) {
+    if ((variant == 0 || variant == 2) && sweep_stream_ok(sh))
+        return launch_sweep_stream(sh, seed, ctr, energy, variant == 2 ? 5 : 1, st);
     const int nblk = sh.R * sh.nk * sh.W;
     hipLaunchKernelGGL(k_sweep_fused, dim3(nblk), dim3(block_for(sh)), sweep_lds_bytes(sh), st, sh,
                        (uint32_t)seed, (uint32_t)(seed >> 32), ctr);

@@ -31,6 +31,8 @@
 // The colour-1 update also yields, per lane, the number of unsatisfied bonds
 // of its site in the final state; summing it over the colour-1 sites gives U
 // exactly (every bond joins a colour-0 and a colour-1 site).
+#include <type_traits>
+
 #include "tfim_internal.h"
 
 namespace tfim {
@@ -154,54 +156,62 @@ __device__ __forceinline__ void add3v(uint64_t (&a)[5], uint64_t f0, uint64_t f1
     a[4] ^= k3;
 }
 
-constexpr int kDeep = 12;          // per-thread counter bits
+constexpr int kDeep = 12;          // per-thread counter bits (kept in LDS)
 constexpr int kFlushMacros = 128;  // 128 * 24 < 2^12
 
-__device__ __forceinline__ void add_deep(uint64_t (&d)[kDeep], uint64_t (&a)[5]) {
+// deep += small (5 bits), ripple carry; deep lives in LDS, plane k of
+// thread t at d[k * stride + t].
+__device__ __forceinline__ void add_deep(uint64_t* d, int stride, uint64_t (&a)[5]) {
     uint64_t k = 0;
 #pragma unroll
     for (int i = 0; i < kDeep; ++i) {
+        const uint64_t v = d[i * stride];
         if (i < 5) {
-            const uint64_t nk = b3<kMaj>(d[i], a[i], k);
-            d[i] = b3<kXor3>(d[i], a[i], k);
+            const uint64_t nk = b3<kMaj>(v, a[i], k);
+            d[i * stride] = b3<kXor3>(v, a[i], k);
             k = nk;
             a[i] = 0;
         } else {
-            const uint64_t nk = d[i] & k;
-            d[i] ^= k;
-            k = nk;
+            d[i * stride] = v ^ k;
+            k = v & k;
         }
     }
 }
 
 // Per-lane sums of the workgroup's vertical counters into Ublk[64].
-__device__ void flush_deep(uint64_t (&d)[kDeep], uint32_t* Ublk) {
+__device__ void flush_deep(uint64_t* d, int stride, uint32_t* Ublk) {
     const int lane = threadIdx.x & 63;
     uint32_t acc = 0;
-#pragma unroll
     for (int k = 0; k < kDeep; ++k) {
+        const uint64_t v = d[k * stride];
         for (int b = 0; b < 64; ++b) {
-            const uint32_t cnt = (uint32_t)__popcll(__ballot((d[k] >> b) & 1ull));
+            const uint32_t cnt = (uint32_t)__popcll(__ballot((v >> b) & 1ull));
             acc += (lane == b) ? (cnt << k) : 0u;
         }
-        d[k] = 0;
+        d[k * stride] = 0;
     }
     atomicAdd(&Ublk[lane], acc);
 }
 
-template <bool kE>
-__global__ void __launch_bounds__(kMaxCols) k_sweep_stream(ShapeDev sh, uint32_t key0,
+// kOcc: minimum waves per SIMD the register allocation must allow (1 = no
+// constraint); a tuning knob, the results do not depend on it.
+template <bool kE, int kOcc>
+__global__ void __launch_bounds__(kMaxCols) __attribute__((amdgpu_waves_per_eu(kOcc)))
+k_sweep_stream(ShapeDev sh, uint32_t key0,
                                                            uint32_t key1,
                                                            const Counters* __restrict__ ctr) {
     extern __shared__ uint64_t lds[];
     const int L = sh.L, L2 = sh.L2, Lt = sh.Lt, nk = sh.nk, W = sh.W;
-    const int H = L2 >> 1;
-    uint64_t* X = lds;           // [2][H] colour-1 words (old) for the colour-0 step
-    uint64_t* Y = lds + 2 * H;   // [2][H] colour-0 words (new) for the colour-1 step
+    // X, Y: one word per column (each column publishes the word at its own,
+    // parity-dependent plane; its four neighbours have the other parity).
+    const int H = L2;
+    uint64_t* X = lds;           // [2][L2] colour-1 words (old) for the colour-0 step
+    uint64_t* Y = lds + 2 * H;   // [2][L2] colour-0 words (new) for the colour-1 step
     uint64_t* ml = lds + 4 * H;  // [nk+1] lane masks of this walker and word
     uint64_t* MM = ml + nk + 1;  // bucket masks, all u
     const int nb0 = sh.bnb[0] + 1, nb1 = sh.bnb[1] + 1, nb2 = sh.bnb[2] + 1;
-    uint32_t* TT = (uint32_t*)(MM + 2 * (nb0 + nb1 + nb2));
+    uint64_t* DEEP = MM + 2 * (nb0 + nb1 + nb2);  // [kDeep][blockDim] energy counters
+    uint32_t* TT = (uint32_t*)(DEEP + (kE ? kDeep * blockDim.x : 0));
     uint32_t* Ublk = TT + nb0 + nb1 + nb2;
 
     const int cfg = blockIdx.x;  // ((r*nk + w)*W + j)
@@ -215,6 +225,8 @@ __global__ void __launch_bounds__(kMaxCols) k_sweep_stream(ShapeDev sh, uint32_t
     for (int i = tid; i <= nk; i += blockDim.x)
         ml[i] = sh.mask[((size_t)(r * W + j) * nk + w) * (nk + 1) + i];
     if (kE && tid < 64) Ublk[tid] = 0;
+    if (kE)
+        for (int i = 0; i < kDeep; ++i) DEEP[i * blockDim.x + tid] = 0;
     __syncthreads();
     {
         const int nbs[3] = {nb0, nb1, nb2};
@@ -245,11 +257,11 @@ __global__ void __launch_bounds__(kMaxCols) k_sweep_stream(ShapeDev sh, uint32_t
     const int xy = active ? tid : 0;
     const int x = xy % L, y = xy / L;
     const int p = (x + y) & 1;
-    const int hx = xy >> 1;
-    const int hxp = (((x + 1) % L) + L * y) >> 1;
-    const int hxm = (((x + L - 1) % L) + L * y) >> 1;
-    const int hyp = (x + L * ((y + 1) % L)) >> 1;
-    const int hym = (x + L * ((y + L - 1) % L)) >> 1;
+    const int hx = xy;
+    const int hxp = ((x + 1) % L) + L * y;
+    const int hxm = ((x + L - 1) % L) + L * y;
+    const int hyp = x + L * ((y + 1) % L);
+    const int hym = x + L * ((y + L - 1) % L);
     const uint64_t* Jb = sh.J + (size_t)j * 2 * L2;
     uint64_t jxp = 0, jxm = 0, jyp = 0, jym = 0;
     if (active) {
@@ -276,9 +288,8 @@ __global__ void __launch_bounds__(kMaxCols) k_sweep_stream(ShapeDev sh, uint32_t
     U4 G0, G1;
     uint32_t prevlast = 0;
     uint64_t sm[5] = {0, 0, 0, 0, 0};
-    uint64_t deep[kDeep];
-#pragma unroll
-    for (int i = 0; i < kDeep; ++i) deep[i] = 0;
+    uint64_t* deep = DEEP + tid;
+    const int dstride = blockDim.x;
     uint64_t f0 = 0, f1 = 0, f2 = 0;
 
     if (active) X[hx] = p ? w3 : w5;  // X(0)
@@ -310,7 +321,7 @@ __global__ void __launch_bounds__(kMaxCols) k_sweep_stream(ShapeDev sh, uint32_t
             const uint64_t* Yb = Y + ((IS + 1) & 1) * H;
             const Nb n{Yb[hxp], Yb[hxm], Yb[hyp], Yb[hym]};
             w1 = site<kE>(w1, n, jxp, jxm, jyp, jym, w2, w0, R1, tb, f0, f1, f2);
-            if (kE) add3v(sm, f0, f1, f2);
+            if (kE && active) add3v(sm, f0, f1, f2);  // padding threads count nothing
             if (active) col[(size_t)wrap(A - 3) * L2] = w1;
         }
         if (active) {
@@ -320,10 +331,10 @@ __global__ void __launch_bounds__(kMaxCols) k_sweep_stream(ShapeDev sh, uint32_t
         __syncthreads();
         w0 = w2; w1 = w3; w2 = w4; w3 = w5; w4 = pf0; w5 = pf1; pf0 = nx0; pf1 = nx1;
     };
-    struct I0 { static constexpr int value = 0; };
-    struct I1 { static constexpr int value = 1; };
-    struct I2 { static constexpr int value = 2; };
-    struct I3 { static constexpr int value = 3; };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I3 = std::integral_constant<int, 3>;
 
     for (int g = 0; g < nq; ++g) {
         const int s0 = 4 * g;
@@ -332,15 +343,15 @@ __global__ void __launch_bounds__(kMaxCols) k_sweep_stream(ShapeDev sh, uint32_t
         segment(s0 + 2, I2{}, true, true);
         segment(s0 + 3, I3{}, true, true);
         if (kE) {
-            add_deep(deep, sm);
-            if ((g % kFlushMacros) == kFlushMacros - 1) flush_deep(deep, Ublk);
+            add_deep(deep, dstride, sm);
+            if ((g % kFlushMacros) == kFlushMacros - 1) flush_deep(deep, dstride, Ublk);
         }
     }
     segment(half, I0{}, false, true);      // colour 1, step half-1
     segment(half + 1, I1{}, false, true);  // colour 1, step half == step 0 (tau wrap)
     if (kE) {
-        add_deep(deep, sm);
-        flush_deep(deep, Ublk);
+        add_deep(deep, dstride, sm);
+        flush_deep(deep, dstride, Ublk);
         __syncthreads();
         if (tid < 64) sh.U[((size_t)r * W * 64 + (size_t)j * 64 + tid) * nk + w] = Ublk[tid];
     }
@@ -350,7 +361,8 @@ __global__ void __launch_bounds__(kMaxCols) k_sweep_stream(ShapeDev sh, uint32_t
 
 size_t sweep_stream_lds_bytes(const ShapeDev& sh) {
     const size_t nb = (size_t)(sh.bnb[0] + 1) + (sh.bnb[1] + 1) + (sh.bnb[2] + 1);
-    return (size_t)(2 * sh.L2 + sh.nk + 1) * 8 + nb * 16 + nb * 4 + 64 * 4;
+    const size_t threads = ((sh.L2 + 63) / 64) * 64;
+    return (size_t)(4 * sh.L2 + sh.nk + 1) * 8 + nb * 16 + threads * kDeep * 8 + nb * 4 + 64 * 4;
 }
 
 bool sweep_stream_ok(const ShapeDev& sh) {
@@ -358,18 +370,28 @@ bool sweep_stream_ok(const ShapeDev& sh) {
            (sh.Lt % 8) == 0 && sh.Lt >= 8;
 }
 
-hipError_t launch_sweep_stream(const ShapeDev& sh, uint64_t seed, const Counters* ctr,
-                               bool energy, hipStream_t st) {
+template <bool kE, int kOcc>
+static hipError_t launch_one(const ShapeDev& sh, uint64_t seed, const Counters* ctr, hipStream_t st) {
     const int nblk = sh.R * sh.nk * sh.W;
     const int threads = ((sh.L2 + 63) / 64) * 64;
     const size_t lds = sweep_stream_lds_bytes(sh);
-    if (energy)
-        hipLaunchKernelGGL(k_sweep_stream<true>, dim3(nblk), dim3(threads), lds, st, sh,
-                           (uint32_t)seed, (uint32_t)(seed >> 32), ctr);
-    else
-        hipLaunchKernelGGL(k_sweep_stream<false>, dim3(nblk), dim3(threads), lds, st, sh,
-                           (uint32_t)seed, (uint32_t)(seed >> 32), ctr);
+    static size_t lds_set = 0;  // dynamic LDS above 64 KiB must be allowed per kernel
+    if (lds > lds_set) {
+        const hipError_t e = hipFuncSetAttribute((const void*)k_sweep_stream<kE, kOcc>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        lds_set = lds;
+    }
+    hipLaunchKernelGGL((k_sweep_stream<kE, kOcc>), dim3(nblk), dim3(threads), lds, st, sh,
+                       (uint32_t)seed, (uint32_t)(seed >> 32), ctr);
     return hipGetLastError();
+}
+
+hipError_t launch_sweep_stream(const ShapeDev& sh, uint64_t seed, const Counters* ctr,
+                               bool energy, int occ, hipStream_t st) {
+    if (occ >= 5)
+        return energy ? launch_one<true, 5>(sh, seed, ctr, st) : launch_one<false, 5>(sh, seed, ctr, st);
+    return energy ? launch_one<true, 1>(sh, seed, ctr, st) : launch_one<false, 1>(sh, seed, ctr, st);
 }
 
 }  // namespace tfim

@@ -32,6 +32,16 @@ struct ShapeDev {
     // K_u(R) = Kbase + (R < Tstar ? mult : 0).  bnb[u] = -1: no table.
     const uint64_t* btab;
     int bsh[3], bnb[3], boff[3];
+    // Measurement layouts (one bit per spin, one row per sample), written by
+    // the transpose kernel for configuration m = (i*S + s)*R + r (k-index i,
+    // sample s, replica r):
+    //   Pt[(m*nc + c)*nxp + xy]  bit t = spin bit of (tau = 64c + t, xy)
+    //   Px[(m*nx + g)*Lt + tau]  bit t = spin bit of (tau, xy = 64g + t)
+    // nc = ceil(Lt/64), nx = ceil(L2/64), nxp = 64*nx; padding bits are 0.
+    uint64_t* Pt;
+    uint64_t* Px;
+    int32_t* dump;  // [2*L2*L2 + Lt*Lt] debug matrices
+    int nc, nx, nxp;
 };
 
 // Plan-wide device counters.
@@ -85,13 +95,25 @@ hipError_t launch_init_spins(const ShapeDev& sh, uint64_t seed, hipStream_t st);
 hipError_t launch_labels_identity(const ShapeDev& sh, hipStream_t st);
 hipError_t launch_energy(const ShapeDev& sh, hipStream_t st);
 hipError_t launch_mask_rebuild(const ShapeDev& sh, hipStream_t st);
+// variant 0: streaming kernel (needs bucket tables), 1: chunked kernel,
+// 2: streaming kernel compiled for >= 5 waves per SIMD.
+// energy: also recount U (the chunked kernel always does).
 hipError_t launch_sweep(const ShapeDev& sh, uint64_t seed, const Counters* ctr, int variant,
-                        hipStream_t st);
+                        bool energy, hipStream_t st);
+hipError_t launch_sweep_stream(const ShapeDev& sh, uint64_t seed, const Counters* ctr,
+                               bool energy, int occ, hipStream_t st);
+bool sweep_stream_ok(const ShapeDev& sh);
+size_t sweep_stream_lds_bytes(const ShapeDev& sh);
 hipError_t launch_temper(const ShapeDev& sh, uint64_t seed, const Counters* ctr, hipStream_t st);
 hipError_t launch_advance(Counters* ctr, uint32_t dt, uint32_t dm, hipStream_t st);
-hipError_t launch_measure(const ShapeDev& sh, hipStream_t st);
-hipError_t launch_dump_gram(const ShapeDev& sh, int i, int s, int a, int b, int32_t* Ga,
-                            int32_t* Gb, int32_t* Q, hipStream_t st);
+// Measurement of configurations cfg0 .. cfg0+ncfg-1 (cfg = i*S + s) into the
+// records (which must be zeroed first).  mode 0: batched int8-MFMA kernels;
+// mode 1: plain per-sample VALU form, one launch per configuration.
+hipError_t launch_transpose(const ShapeDev& sh, hipStream_t st);
+hipError_t launch_measure(const ShapeDev& sh, int mode, int cfg0, int ncfg, hipStream_t st);
+hipError_t launch_buckets(const ShapeDev& sh, hipStream_t st);
+hipError_t launch_dump(const ShapeDev& sh, int cfg, int a, int b, hipStream_t st);
+bool measure_ok(const ShapeDev& sh);
 int sweep_variants();
 const char* sweep_variant_name(int v);
 }  // namespace tfim

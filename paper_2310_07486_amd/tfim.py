@@ -37,7 +37,7 @@ SYMBOLS = [
     "tfim_dump_gram", "tfim_xi2", "tfim_get_thresholds", "tfim_export_spins",
     "tfim_export_couplings", "tfim_get_state", "tfim_get_counters", "tfim_set_state",
     "tfim_set_schedule", "tfim_autotune", "tfim_get_tuning", "tfim_sync", "tfim_strerror",
-    "tfim_last_error_detail",
+    "tfim_last_error_detail", "tfim_set_variant", "tfim_set_timing", "tfim_get_timing",
 ]
 
 
@@ -100,6 +100,9 @@ def lib():
             "tfim_autotune": [P, U32],
             "tfim_get_tuning": [P, P, P],
             "tfim_sync": [P],
+            "tfim_set_variant": [P, U32],
+            "tfim_set_timing": [P, U32],
+            "tfim_get_timing": [P, P, P],
             "tfim_strerror": [ctypes.c_int32],
             "tfim_last_error_detail": [],
         }
@@ -215,6 +218,19 @@ class Plan:
 
     def sync(self):
         _check(lib().tfim_sync(self._h), "tfim_sync")
+
+    def set_variant(self, variant: int):
+        _check(lib().tfim_set_variant(self._h, variant), "tfim_set_variant")
+
+    def set_timing(self, enable: bool):
+        _check(lib().tfim_set_timing(self._h, 1 if enable else 0), "tfim_set_timing")
+
+    def get_timing(self):
+        """(summed sweep-kernel ms, number of timed launches) since last call."""
+        ms = ctypes.c_double()
+        n = ctypes.c_uint64()
+        _check(lib().tfim_get_timing(self._h, ctypes.byref(ms), ctypes.byref(n)), "tfim_get_timing")
+        return ms.value, n.value
 
     def set_schedule(self, schedule: int):
         _check(lib().tfim_set_schedule(self._h, schedule), "tfim_set_schedule")

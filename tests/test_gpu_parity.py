@@ -179,3 +179,34 @@ def test_multi_shape_plan_equals_single_shape_plans():
         one.sweep(6)
         assert np.array_equal(both.export_spins(i), one.export_spins(0))
         assert all(np.array_equal(x, y) for x, y in zip(both.get_state(i), one.get_state(0)))
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("L,Lt,W,R,nk,pt", [
+    (8, 32, 1, 2, 6, 1), (12, 24, 1, 2, 5, 2), (24, 16, 1, 1, 4, 1), (2, 8, 1, 2, 2, 1),
+    (6, 8, 1, 2, 3, 1), (20, 40, 1, 1, 3, 0),
+])
+def test_sweep_kernel_variants(variant, L, Lt, W, R, nk, pt):
+    """Every sweep-kernel variant reproduces the oracle bit for bit."""
+    sh = Shape(L, Lt, W, R, ladder(0.2, 0.45, nk), pt_every=pt)
+    seed = 4242 + L
+    _say(f"variant {variant} parity L={L} Lt={Lt} R={R} nk={nk} pt={pt}")
+    plan = tfim.Plan([sh], seed)
+    plan.set_variant(variant)
+    plan.init()
+    plan.sweep(5)
+    plan.sweep(7)
+    plan.sync()
+    lanes = list(range(64)) if L <= 8 else [0, 13, 63]
+    _compare(plan, 0, sh, seed, lanes, 12)
+
+
+def test_kernel_timing_counts_launches():
+    sh = Shape(8, 32, 1, 2, ladder(0.25, 0.3, 4))
+    plan = tfim.Plan([sh], 3)
+    plan.init()
+    plan.set_timing(True)
+    plan.get_timing()
+    plan.sweep(6)
+    ms, n = plan.get_timing()
+    assert n == 6 and ms > 0.0

@@ -18,6 +18,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -53,6 +55,77 @@ def cpu_baseline(workload, seconds: float):
     }
 
 
+def measure_ops(sh):
+    """Algorithmic integer ops of one measurement of every configuration:
+    Gram G = S S^T as a symmetric rank-Ltau update, L^2 (L^2 + 1) Ltau per
+    replica-configuration, and Q^ab = S^aT S^b, 2 Ltau^2 L^2 per pair
+    (multiply and add counted as two)."""
+    L2, Lt, R = sh.L * sh.L, sh.Ltau, sh.n_replicas
+    P = R * (R - 1) // 2
+    ncfg = len(sh.k) * sh.n_samples
+    g = L2 * (L2 + 1) * Lt * R
+    q = 2 * Lt * Lt * L2 * P
+    return ncfg, g, q
+
+
+def measure_leg(plan, sh, torch, args):
+    """Batched int8-MFMA measurement of all configurations vs the same kernels
+    launched per configuration and vs the plain per-sample form."""
+    from paper_2310_07486_amd import tfim
+    ncfg, g_ops, q_ops = measure_ops(sh)
+    per_cfg = g_ops + q_ops
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    # layouts (bit transposition) once, timed on its own
+    t_tr = timed(lambda: plan.measure_range(0, 0, 0, 1, copy=False))
+    log("bench: measure: transposition + 1 configuration %.2f ms" % t_tr)
+    t_all = timed(lambda: plan.measure_range(0, 0, 0, ncfg, flags=tfim.TFIM_MEASURE_REUSE_LAYOUT,
+                                             copy=False))
+    tops = per_cfg * ncfg / (t_all * 1e-3) / 1e12
+    log("bench: measure: batched MFMA, %d configurations: %.1f ms, %.1f TOP/s" % (ncfg, t_all, tops))
+    n_un = min(args.unbatched_cfgs, ncfg)
+
+    def unbatched():
+        for c in range(n_un):
+            plan.measure_range(0, 0, c, 1, flags=tfim.TFIM_MEASURE_REUSE_LAYOUT, copy=False)
+
+    t_un = timed(unbatched)
+    tops_un = per_cfg * n_un / (t_un * 1e-3) / 1e12
+    n_pl = min(args.plain_cfgs, ncfg)
+    t_pl = timed(lambda: plan.measure_range(0, 1, 0, n_pl, flags=tfim.TFIM_MEASURE_REUSE_LAYOUT,
+                                            copy=False))
+    tops_pl = per_cfg * n_pl / (t_pl * 1e-3) / 1e12
+    log("bench: measure: per-configuration MFMA %.3f ms/cfg (%.1f TOP/s); plain %.3f ms/cfg (%.2f TOP/s)"
+        % (t_un / n_un, tops_un, t_pl / n_pl, tops_pl))
+    # xi^(2) of every k from the buckets (FP64, host)
+    A = plan.measure(0, tfim.TFIM_MEASURE_BUCKETS)
+    xi = tfim.tfim_xi2(np.ascontiguousarray(A[:, 0]), sh.L)
+    return {
+        "configurations": ncfg, "replicas": sh.n_replicas,
+        "ops_per_configuration": per_cfg, "gram_ops": g_ops * ncfg, "overlap_ops": q_ops * ncfg,
+        "transpose_ms": round(t_tr, 3),
+        "batched_mfma": {"ms": round(t_all, 3), "int8_tops": round(tops, 2),
+                          "frac_of_int8_peak": round(tops / 5000.0, 4)},
+        "per_configuration_mfma": {"configurations": n_un, "ms_per_cfg": round(t_un / n_un, 4),
+                                    "int8_tops": round(tops_un, 2)},
+        "plain_per_sample": {"configurations": n_pl, "ms_per_cfg": round(t_pl / n_pl, 4),
+                              "int8_tops": round(tops_pl, 3)},
+        "batched_over_plain": round(tops / tops_pl, 1),
+        "batched_over_per_configuration": round(tops / tops_un, 2),
+        "xi2_over_L": [round(float(v) / sh.L, 6) for v in xi],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -61,6 +134,9 @@ def main():
     ap.add_argument("--variant", type=int, default=-1, help="sweep kernel variant (-1: tuned)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-measure", action="store_true")
+    ap.add_argument("--unbatched-cfgs", type=int, default=64)
+    ap.add_argument("--plain-cfgs", type=int, default=1)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; --gpus must be 1 "
@@ -136,6 +212,8 @@ def main():
                      "kernel": "k_sweep_stream", "kernel_ms": round(avg_kernel_ms, 4),
                      "algorithmic_bytes_per_launch": alg_bytes},
     }
+    if not args.no_measure:
+        result["measure"] = measure_leg(plan, sh, torch, args)
     plan.close()
     del plan
     torch.cuda.empty_cache()

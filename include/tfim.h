@@ -147,6 +147,22 @@ tfim_status tfim_pt_swap(tfim_plan *plan);
 tfim_status tfim_measure(tfim_plan *plan, uint32_t shape, uint32_t what, void *host_out,
                          size_t host_bytes);
 
+/* Measurement of a range of configurations cfg = i*samples + s,
+ * cfg0 .. cfg0+ncfg-1, into int64 records [ncfg][pairs][2L+3] (layout as
+ * TFIM_MEASURE_RECORDS).  mode 0: batched int8-MFMA kernels (default);
+ * mode 1: plain per-sample form (one launch per configuration, one matrix
+ * element per thread, int32 multiply-accumulate, no MFMA).  flags:
+ * TFIM_MEASURE_REUSE_LAYOUT skips the bit transposition (valid only if the
+ * state did not change since the last measurement of this shape).
+ * out == NULL: enqueue only (asynchronous, for timing); otherwise the call
+ * synchronises and copies the records. */
+#define TFIM_MEASURE_REUSE_LAYOUT 1u
+tfim_status tfim_measure_range(tfim_plan *plan, uint32_t shape, uint32_t mode, uint32_t cfg0,
+                               uint32_t ncfg, uint32_t flags, int64_t *out, size_t out_bytes);
+
+/* Measurement form used by tfim_measure (0 batched MFMA, 1 plain). */
+tfim_status tfim_set_measure_mode(tfim_plan *plan, uint32_t mode);
+
 /* Debug dump of the integer matrices of one configuration pair:
  * G^a (L^2 x L^2, int32), G^b, and Q^{ab} (Ltau x Ltau, int32) for sample s
  * at k-index i, replicas a < b.  Synchronous. */

@@ -30,6 +30,8 @@
 // The plain per-sample form (k_*_plain) computes one matrix element per
 // thread with an int32 multiply-accumulate loop over unpacked spins, one
 // launch per configuration: the reference point for the batched form.
+#include <algorithm>
+
 #include "tfim_internal.h"
 
 namespace tfim {
@@ -62,10 +64,14 @@ __device__ __forceinline__ uint64_t wave_transpose64(uint64_t v) {
     return v;
 }
 
+constexpr int kTP = 65;  // padded row pitch (words) of the transpose tiles
+constexpr size_t kTransposeLds = (size_t)2 * 64 * kTP * 8 + 64 * 4;
+
 __global__ void __launch_bounds__(256) k_transpose(ShapeDev sh, long long items) {
-    __shared__ uint64_t tile[64][65];
-    __shared__ uint64_t outw[64][65];
-    __shared__ int mrow[64];
+    extern __shared__ uint64_t tlds[];
+    uint64_t(*tile)[kTP] = (uint64_t(*)[kTP])tlds;
+    uint64_t(*outw)[kTP] = (uint64_t(*)[kTP])(tlds + 64 * kTP);
+    int* mrow = (int*)(tlds + 2 * 64 * kTP);
     const int L2 = sh.L2, Lt = sh.Lt, nk = sh.nk, W = sh.W, R = sh.R;
     const int S = 64 * W;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -116,7 +122,7 @@ __device__ __forceinline__ void unpack64(uint64_t v, uint8_t* dst) {
 #pragma unroll
     for (int d = 0; d < 16; ++d) {
         const uint32_t nib = (uint32_t)(v >> (4 * d)) & 0xFu;
-        out[d] = __builtin_amdgcn_mul_u24(nib, 0x00204081u) & 0x01010101u;
+        out[d] = __umul24(nib, 0x00204081u) & 0x01010101u;
     }
     v4i* p = (v4i*)dst;
 #pragma unroll
@@ -166,6 +172,7 @@ __global__ void __launch_bounds__(256) k_gram_mfma(ShapeDev sh, int cfg0, int nc
             for (int r = 0; r < RR; ++r)
 #pragma unroll
                 for (int q = 0; q < 16; ++q) acc[r][q] = 0;
+            __syncthreads();  // previous tile's epilogue has read nA, nB
             for (int e = tid; e < 2 * RR * 64; e += 256) nA[e] = 0;  // nA and nB
             for (int c = 0; c < sh.nc; ++c) {
                 __syncthreads();
@@ -261,6 +268,7 @@ __global__ void __launch_bounds__(256) k_overlap_mfma(ShapeDev sh, int cfg0, int
             for (int p = 0; p < PP; ++p)
 #pragma unroll
                 for (int q = 0; q < 16; ++q) acc[p][q] = 0;
+            __syncthreads();  // previous tile's epilogue has read mA, mB
             for (int e = tid; e < 2 * RR * 64; e += 256) mA[e] = 0;
             for (int g = 0; g < sh.nx; ++g) {
                 __syncthreads();
@@ -347,14 +355,12 @@ __global__ void __launch_bounds__(256) k_overlap_mfma(ShapeDev sh, int cfg0, int
 // Plain per-sample form: one configuration per launch, one matrix element
 // per thread, int32 multiply-accumulate over unpacked +-1 spins.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int spin_t(const ShapeDev& sh, size_t m, int xy, int tau) {
-    const uint64_t w = sh.Pt[(m * sh.nc + (tau >> 6)) * sh.nxp + xy];
-    return 1 - 2 * (int)((w >> (tau & 63)) & 1ull);
-}
-
-__device__ __forceinline__ int spin_x(const ShapeDev& sh, size_t m, int xy, int tau) {
-    const uint64_t w = sh.Px[(m * sh.nx + (xy >> 6)) * sh.Lt + tau];
-    return 1 - 2 * (int)((w >> (xy & 63)) & 1ull);
+// +-1 spins t = 0..63 of a 64-bit row word: 1 - 2 bit_t, 0 past n valid bits.
+__device__ __forceinline__ int dot64(uint64_t a, uint64_t b, int n) {
+    int acc = 0;
+    for (int t = 0; t < n; ++t)
+        acc += (1 - 2 * (int)((a >> t) & 1ull)) * (1 - 2 * (int)((b >> t) & 1ull));
+    return acc;
 }
 
 __global__ void __launch_bounds__(256) k_gram_plain(ShapeDev sh, int cfg) {
@@ -369,7 +375,9 @@ __global__ void __launch_bounds__(256) k_gram_plain(ShapeDev sh, int cfg) {
         for (int r = 0; r < R; ++r) {
             const size_t m = (size_t)cfg * R + r;
             int acc = 0;
-            for (int tau = 0; tau < sh.Lt; ++tau) acc += spin_t(sh, m, x, tau) * spin_t(sh, m, y, tau);
+            for (int c = 0; c < sh.nc; ++c)
+                acc += dot64(sh.Pt[(m * sh.nc + c) * sh.nxp + x], sh.Pt[(m * sh.nc + c) * sh.nxp + y],
+                             min(64, sh.Lt - 64 * c));
             G[r] = acc;
         }
         const int dx = ((x % L) - (y % L) + L) % L, dy = ((x / L) - (y / L) + L) % L;
@@ -400,7 +408,9 @@ __global__ void __launch_bounds__(256) k_overlap_plain(ShapeDev sh, int cfg) {
             for (int b = a + 1; b < R; ++b, ++p) {
                 const size_t ma = (size_t)cfg * R + a, mb = (size_t)cfg * R + b;
                 int q = 0;
-                for (int xy = 0; xy < L2; ++xy) q += spin_x(sh, ma, xy, tau) * spin_x(sh, mb, xy, tau2);
+                for (int g = 0; g < sh.nx; ++g)
+                    q += dot64(sh.Px[(ma * sh.nx + g) * Lt + tau], sh.Px[(mb * sh.nx + g) * Lt + tau2],
+                               min(64, L2 - 64 * g));
                 const long long q2 = (long long)q * q;
                 atomicAdd(&red[p * 3 + 1], (unsigned long long)q2);
                 atomicAdd(&red[p * 3 + 2], (unsigned long long)(q2 * q2));
@@ -425,12 +435,16 @@ __global__ void k_dump(ShapeDev sh, int cfg, int a, int b) {
             const long long f = e % n1;
             const int x = (int)(f / L2), y = (int)(f % L2);
             const size_t m = (size_t)cfg * R + r;
-            for (int tau = 0; tau < Lt; ++tau) acc += spin_t(sh, m, x, tau) * spin_t(sh, m, y, tau);
+            for (int c = 0; c < sh.nc; ++c)
+                acc += dot64(sh.Pt[(m * sh.nc + c) * sh.nxp + x], sh.Pt[(m * sh.nc + c) * sh.nxp + y],
+                             min(64, Lt - 64 * c));
         } else {
             const long long f = e - 2 * n1;
             const int tau = (int)(f / Lt), tau2 = (int)(f % Lt);
             const size_t ma = (size_t)cfg * R + a, mb = (size_t)cfg * R + b;
-            for (int xy = 0; xy < L2; ++xy) acc += spin_x(sh, ma, xy, tau) * spin_x(sh, mb, xy, tau2);
+            for (int g = 0; g < sh.nx; ++g)
+                acc += dot64(sh.Px[(ma * sh.nx + g) * Lt + tau], sh.Px[(mb * sh.nx + g) * Lt + tau2],
+                             min(64, L2 - 64 * g));
         }
         sh.dump[e] = acc;
     }
@@ -475,12 +489,19 @@ hipError_t launch_mfma(const ShapeDev& sh, int cfg0, int ncfg, hipStream_t st) {
 
 bool measure_ok(const ShapeDev& sh) { return sh.R >= 2 && sh.R <= kMaxR && sh.L <= 32; }
 
-hipError_t launch_transpose(const ShapeDev& sh) = delete;
 
 hipError_t launch_transpose(const ShapeDev& sh, hipStream_t st) {
     const long long items = (long long)sh.R * sh.nk * sh.W * sh.nc * sh.nx;
     const int grid = (int)std::min<long long>(items, 8192);
-    hipLaunchKernelGGL(k_transpose, dim3(grid), dim3(256), 0, st, sh, items);
+    static bool lds_set = false;  // above 64 KiB of LDS per workgroup
+    if (!lds_set) {
+        const hipError_t e = hipFuncSetAttribute((const void*)k_transpose,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)kTransposeLds);
+        if (e != hipSuccess) return e;
+        lds_set = true;
+    }
+    hipLaunchKernelGGL(k_transpose, dim3(grid), dim3(256), kTransposeLds, st, sh, items);
     return hipGetLastError();
 }
 

@@ -59,6 +59,7 @@ struct tfim_plan {
     std::vector<uint64_t> t, m;  // host mirrors per shape
     uint32_t schedule = TFIM_SCHED_PER_SHAPE;
     int variant = 0;
+    uint32_t measure_mode = 0;
     double tuned_ms = 0.0;
     std::map<uint64_t, hipGraphExec_t> graphs;  // keyed by (n, t phase) for the per-shape schedule
     // HIP-event timing of sweep-kernel launches (tfim_set_timing)
@@ -726,19 +727,91 @@ tfim_status tfim_get_tuning(const tfim_plan* pl, uint32_t* config_id, double* ms
     return TFIM_OK;
 }
 
+static tfim_status measure_core(tfim_plan* pl, uint32_t shape, uint32_t mode, uint32_t cfg0,
+                                uint32_t ncfg, uint32_t flags) {
+    ShapeHost& h = pl->shapes[shape];
+    if (!h.S_ready) return fail(TFIM_ESTATE, "spins of this shape are not initialised");
+    const tfim::ShapeDev d = dev_of(pl, shape);
+    if (!tfim::measure_ok(d)) return fail(TFIM_EUNSUPPORTED, "measurement needs 2..4 replicas");
+    const uint64_t ncfg_all = (uint64_t)h.s.n_k * 64 * h.s.n_words;
+    if ((uint64_t)cfg0 + ncfg > ncfg_all) return fail(TFIM_EINVAL, "configuration range out of bounds");
+    if (mode > 1) return fail(TFIM_EINVAL, "unknown measurement mode");
+    const size_t rl = (size_t)(2 * h.s.L + 3) * h.P * 8;
+    hipError_t e = hipMemsetAsync(pl->arena + h.oRec + (size_t)cfg0 * rl, 0, (size_t)ncfg * rl, pl->stream);
+    if (e == hipSuccess && !(flags & TFIM_MEASURE_REUSE_LAYOUT)) e = tfim::launch_transpose(d, pl->stream);
+    if (e == hipSuccess) e = tfim::launch_measure(d, (int)mode, (int)cfg0, (int)ncfg, pl->stream);
+    return check_hip(pl, e, "measure");
+}
+
 tfim_status tfim_measure(tfim_plan* pl, uint32_t shape, uint32_t what, void* out, size_t bytes) {
     tfim_status st = shape_ok(pl, shape);
     if (st != TFIM_OK) return st;
-    (void)what; (void)out; (void)bytes;
-    return fail(TFIM_EUNSUPPORTED, "measurement not built yet");
+    ShapeHost& h = pl->shapes[shape];
+    if (!out) return fail(TFIM_EINVAL, "null host pointer");
+    const size_t S = 64 * (size_t)h.s.n_words, nk = h.s.n_k, R = h.s.n_replicas;
+    if (what == TFIM_MEASURE_ENERGY) {
+        if (bytes < R * S * nk * 4) return fail(TFIM_EINVAL, "output buffer too small");
+        std::vector<uint8_t> winv(h.nLab);
+        std::vector<uint32_t> U(h.nLab);
+        if ((st = copy_back(pl, winv.data(), pl->arena + h.oWinv, h.nLab, "get winv")) != TFIM_OK) return st;
+        if ((st = copy_back(pl, U.data(), pl->arena + h.oU, h.nLab * 4, "get U")) != TFIM_OK) return st;
+        uint32_t* o = (uint32_t*)out;
+        for (size_t g = 0; g < R * S; ++g)
+            for (size_t i = 0; i < nk; ++i) o[g * nk + i] = U[g * nk + winv[g * nk + i]];
+        return TFIM_OK;
+    }
+    if (what != TFIM_MEASURE_RECORDS && what != TFIM_MEASURE_BUCKETS)
+        return fail(TFIM_EINVAL, "unknown measurement");
+    const size_t need = what == TFIM_MEASURE_RECORDS ? h.nRec : h.nBuck;
+    if (bytes < need) return fail(TFIM_EINVAL, "output buffer too small");
+    if ((st = measure_core(pl, shape, pl->measure_mode, 0, (uint32_t)(nk * S), 0)) != TFIM_OK) return st;
+    if (what == TFIM_MEASURE_BUCKETS) {
+        const hipError_t e = tfim::launch_buckets(dev_of(pl, (int)shape), pl->stream);
+        if ((st = check_hip(pl, e, "buckets")) != TFIM_OK) return st;
+        return copy_back(pl, out, pl->arena + h.oBuck, h.nBuck, "copy buckets");
+    }
+    return copy_back(pl, out, pl->arena + h.oRec, h.nRec, "copy records");
+}
+
+tfim_status tfim_measure_range(tfim_plan* pl, uint32_t shape, uint32_t mode, uint32_t cfg0,
+                               uint32_t ncfg, uint32_t flags, int64_t* out, size_t bytes) {
+    tfim_status st = shape_ok(pl, shape);
+    if (st != TFIM_OK) return st;
+    ShapeHost& h = pl->shapes[shape];
+    const size_t rl = (size_t)(2 * h.s.L + 3) * h.P * 8;
+    if (out && bytes < (size_t)ncfg * rl) return fail(TFIM_EINVAL, "output buffer too small");
+    if ((st = measure_core(pl, shape, mode, cfg0, ncfg, flags)) != TFIM_OK) return st;
+    if (!out) return TFIM_OK;
+    return copy_back(pl, out, pl->arena + h.oRec + (size_t)cfg0 * rl, (size_t)ncfg * rl, "copy records");
+}
+
+tfim_status tfim_set_measure_mode(tfim_plan* pl, uint32_t mode) {
+    if (!pl) return fail(TFIM_EINVAL, "null plan");
+    if (mode > 1) return fail(TFIM_EINVAL, "unknown measurement mode");
+    pl->measure_mode = mode;
+    return TFIM_OK;
 }
 
 tfim_status tfim_dump_gram(tfim_plan* pl, uint32_t shape, uint32_t i, uint32_t s, uint32_t a,
                            uint32_t b, int32_t* Ga, int32_t* Gb, int32_t* Q) {
     tfim_status st = shape_ok(pl, shape);
     if (st != TFIM_OK) return st;
-    (void)i; (void)s; (void)a; (void)b; (void)Ga; (void)Gb; (void)Q;
-    return fail(TFIM_EUNSUPPORTED, "measurement not built yet");
+    ShapeHost& h = pl->shapes[shape];
+    if (!h.S_ready) return fail(TFIM_ESTATE, "spins of this shape are not initialised");
+    const size_t S = 64 * (size_t)h.s.n_words;
+    if (i >= h.s.n_k || s >= S || a >= h.s.n_replicas || b >= h.s.n_replicas)
+        return fail(TFIM_EINVAL, "index out of range");
+    if (h.P == 0) return fail(TFIM_EUNSUPPORTED, "needs at least two replicas");
+    const tfim::ShapeDev d = dev_of(pl, shape);
+    hipError_t e = tfim::launch_transpose(d, pl->stream);
+    if (e == hipSuccess) e = tfim::launch_dump(d, (int)(i * S + s), (int)a, (int)b, pl->stream);
+    if ((st = check_hip(pl, e, "dump")) != TFIM_OK) return st;
+    const size_t n1 = (size_t)d.L2 * d.L2 * 4, n2 = (size_t)d.Lt * d.Lt * 4;
+    char* base = pl->arena + h.oDump;
+    if (Ga && (st = copy_back(pl, Ga, base, n1, "dump Ga")) != TFIM_OK) return st;
+    if (Gb && (st = copy_back(pl, Gb, base + n1, n1, "dump Gb")) != TFIM_OK) return st;
+    if (Q && (st = copy_back(pl, Q, base + 2 * n1, n2, "dump Q")) != TFIM_OK) return st;
+    return TFIM_OK;
 }
 
 }  // extern "C"

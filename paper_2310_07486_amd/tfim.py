@@ -38,7 +38,9 @@ SYMBOLS = [
     "tfim_export_couplings", "tfim_get_state", "tfim_get_counters", "tfim_set_state",
     "tfim_set_schedule", "tfim_autotune", "tfim_get_tuning", "tfim_sync", "tfim_strerror",
     "tfim_last_error_detail", "tfim_set_variant", "tfim_set_timing", "tfim_get_timing",
+    "tfim_measure_range", "tfim_set_measure_mode",
 ]
+TFIM_MEASURE_REUSE_LAYOUT = 1
 
 
 class TfimError(RuntimeError):
@@ -103,6 +105,8 @@ def lib():
             "tfim_set_variant": [P, U32],
             "tfim_set_timing": [P, U32],
             "tfim_get_timing": [P, P, P],
+            "tfim_measure_range": [P, U32, U32, U32, U32, U32, P, SZ],
+            "tfim_set_measure_mode": [P, U32],
             "tfim_strerror": [ctypes.c_int32],
             "tfim_last_error_detail": [],
         }
@@ -300,6 +304,24 @@ class Plan:
             raise ValueError("unknown measurement")
         _check(lib().tfim_measure(self._h, shape, what, _ptr(out), out.nbytes), "tfim_measure")
         return out
+
+    def measure_range(self, shape: int, mode: int, cfg0: int, ncfg: int, flags: int = 0,
+                      copy: bool = True):
+        """Records [ncfg][pairs][2L+3] of configurations cfg = i*S + s
+        (mode 0 batched MFMA, 1 plain per-sample); copy=False only enqueues."""
+        L, Lt, W, R, nk = self._dims(shape)
+        P = R * (R - 1) // 2
+        if not copy:
+            _check(lib().tfim_measure_range(self._h, shape, mode, cfg0, ncfg, flags, None, 0),
+                   "tfim_measure_range")
+            return None
+        out = np.zeros((ncfg, P, 2 * L + 3), dtype=np.int64)
+        _check(lib().tfim_measure_range(self._h, shape, mode, cfg0, ncfg, flags, _ptr(out),
+                                        out.nbytes), "tfim_measure_range")
+        return out
+
+    def set_measure_mode(self, mode: int):
+        _check(lib().tfim_set_measure_mode(self._h, mode), "tfim_set_measure_mode")
 
     def dump_gram(self, shape: int, i: int, s: int, a: int, b: int):
         L, Lt, W, R, nk = self._dims(shape)

@@ -25,10 +25,27 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_WORD = 16  # each spin word read once and written once per sweep
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_stream_L24_Lt2048_traffic.json")
+SWEEP_SOURCE = os.path.join(ROOT, "paper_2310_07486_amd", "csrc", "sweep_stream.hip")
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def measured_traffic(workload_name: str):
+    """HBM bytes per launch of the streaming sweep from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary (copy-kernel calibrated), only
+    while the kernel source is the one the counters were taken on."""
+    import hashlib
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+        sha = hashlib.sha256(open(SWEEP_SOURCE, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != sha or workload_name != "large-L24-Lt2048":
+        return None
+    return t["per_launch"]
 
 
 def cpu_baseline(workload, seconds: float):
@@ -126,6 +143,50 @@ def measure_leg(plan, sh, torch, args):
     }
 
 
+def batched_leg(torch, args):
+    """Five uneven sizes (L, Ltau) = (8,256) .. (24,2048), 512 samples each:
+    the per-shape schedule (five sweep launches per sweep, one per size)
+    against the batched schedule (one persistent launch for all sizes,
+    replayed from a HIP graph), same seed and sweep count; then the
+    autotuner's choice on the same plan."""
+    from paper_2310_07486_amd import tfim
+    from paper_2310_07486_amd.workloads import c4_batched
+    w = c4_batched()
+    upd = sum(s.updates_per_sweep() for s in w.shapes)
+    stream = torch.cuda.current_stream()
+    out = {"workload": w.name, "shapes": [[s.L, s.Ltau] for s in w.shapes],
+           "updates_per_sweep": upd}
+    for name, sched in (("per_shape", tfim.TFIM_SCHED_PER_SHAPE), ("batched", tfim.TFIM_SCHED_BATCHED)):
+        plan = tfim.Plan(w.shapes, w.seed)
+        plan.init()
+        plan.set_schedule(sched)
+        plan.sweep(args.warmup)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        plan.sweep(args.c4_steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.c4_steps
+        out[name] = {"ms_per_sweep": round(ms, 4), "spin_updates_per_ns": round(upd / (ms * 1e6), 1)}
+        if name == "batched":
+            t = plan.tuning()
+            out[name].update(threads=t["batch_threads"], blocks=t["batch_blocks"], items=t["batch_items"])
+            done = plan.autotune(2)
+            t = plan.tuning()
+            out["autotuned"] = {"schedule": "batched" if t["schedule"] == tfim.TFIM_SCHED_BATCHED
+                                else "per_shape", "variant": t["variant"],
+                                "threads": t["batch_threads"], "ms_per_sweep": round(t["ms_per_sweep"], 4),
+                                "trial_sweeps": done}
+        log(f"bench: sizes x5 {name}: {ms:.3f} ms/sweep ({upd / (ms * 1e6):.1f} spin-updates/ns)")
+        plan.close()
+        del plan
+        torch.cuda.empty_cache()
+    out["batched_over_per_shape"] = round(out["per_shape"]["ms_per_sweep"] / out["batched"]["ms_per_sweep"], 3)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -137,6 +198,10 @@ def main():
     ap.add_argument("--no-measure", action="store_true")
     ap.add_argument("--unbatched-cfgs", type=int, default=64)
     ap.add_argument("--plain-cfgs", type=int, default=1)
+    ap.add_argument("--no-batched", action="store_true", help="skip the five-size batched leg")
+    ap.add_argument("--c4-steps", type=int, default=10)
+    ap.add_argument("--copy-gb", type=float, default=0.0,
+                    help="first run a plain device copy of this many GB (calibrates HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; --gpus must be 1 "
@@ -150,6 +215,20 @@ def main():
     w = c3_large()
     sh = w.shapes[0]
     torch.cuda.set_device(0)
+    if args.copy_gb > 0:
+        # plain elementwise copy of known size for counter calibration: int64
+        # views one element off 16-byte alignment, so every lane moves 8
+        # bytes, the access width of the sweep
+        n = int(args.copy_gb * 1e9) // 8
+        src = torch.empty(n + 1, dtype=torch.int64, device="cuda").fill_(1)[1:]
+        dst = torch.empty(n + 1, dtype=torch.int64, device="cuda")[1:]
+        for _ in range(2):
+            torch.bitwise_not(src, out=dst)
+        torch.cuda.synchronize()
+        log(f"bench: copy calibration: bitwise_not over {8 * n} bytes (read) -> {8 * n} bytes (written), "
+            f"2 launches")
+        del src, dst
+        torch.cuda.empty_cache()
     log(f"bench: plan {w.name} ({sh.L}x{sh.L}x{sh.Ltau}, {sh.n_samples} samples, "
         f"{sh.n_replicas} replicas, {len(sh.k)} k)")
     plan = tfim.Plan([sh], w.seed)
@@ -212,11 +291,18 @@ def main():
                      "kernel": "k_sweep_stream", "kernel_ms": round(avg_kernel_ms, 4),
                      "algorithmic_bytes_per_launch": alg_bytes},
     }
+    tr = measured_traffic(w.name) if variant in (0, 2) else None
+    if tr is not None:
+        result["roofline"]["traffic"] = tr["traffic_bytes"]
+        result["roofline"]["traffic_unit"] = "HBM bytes per launch (rocprofv3, copy-calibrated)"
+        result["roofline"]["traffic_over_algorithmic"] = tr["traffic_over_algorithmic"]
     if not args.no_measure:
         result["measure"] = measure_leg(plan, sh, torch, args)
     plan.close()
     del plan
     torch.cuda.empty_cache()
+    if not args.no_batched:
+        result["batched"] = batched_leg(torch, args)
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

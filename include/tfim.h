@@ -199,33 +199,70 @@ tfim_status tfim_get_counters(const tfim_plan *plan, uint32_t shape, uint64_t *t
 tfim_status tfim_set_state(tfim_plan *plan, uint32_t shape, const uint64_t *S_host,
                            const uint8_t *kidx_host, uint64_t t, uint64_t m);
 
-/* Launch schedule of tfim_sweep.
- * TFIM_SCHED_BATCHED: one persistent kernel covers all shapes and all n
- *   sweeps (work items handed out in order, tempering done by the last
- *   walker of each group), captured in a HIP graph.
- * TFIM_SCHED_PER_SHAPE: one sweep launch per shape and sweep, one
- *   tempering launch per shape and step (the plain form).
- * Both give bit-identical results. */
+/* Launch schedules of tfim_sweep (both give bit-identical spins, labels,
+ * energies and counters).
+ * TFIM_SCHED_PER_SHAPE (default): per sweep, one sweep-kernel launch per
+ *   shape (one workgroup per configuration), then per shape a tempering
+ *   launch when due and the counter advance: the plain form.
+ * TFIM_SCHED_BATCHED: per sweep, ONE launch of a persistent kernel for all
+ *   shapes.  Its workgroups take work items (shape, run of configurations)
+ *   from a device queue in longest-first order, and pack several
+ *   configurations of a small shape into one workgroup.  Then one tempering
+ *   launch covers every shape; a shape whose tempering is not due skips
+ *   itself.  One counter advance follows.  Runs of up to 16 sweeps are
+ *   captured once in a HIP graph and replayed from it.  Needs a bound plan.
+ *   Whether a sweep recounts U is decided on the device from the counters. */
 #define TFIM_SCHED_BATCHED 0u
 #define TFIM_SCHED_PER_SHAPE 1u
 tfim_status tfim_set_schedule(tfim_plan *plan, uint32_t schedule);
 
-/* Autotuner: times each candidate launch configuration of the sweep on the
- * bound state (the state is saved and restored around the trials, so the
- * chain is unchanged) and keeps the fastest.  Synchronous.
- * tfim_get_tuning reports the chosen configuration id and its time. */
-tfim_status tfim_autotune(tfim_plan *plan, uint32_t sweeps_per_trial);
-tfim_status tfim_get_tuning(const tfim_plan *plan, uint32_t *config_id, double *ms_per_sweep);
+/* Geometry of the batched launch.  threads: threads per workgroup, a
+ * multiple of 64, at least the largest shape's L^2 rounded up to 64, at
+ * most 576.  blocks_per_cu: resident workgroups per compute unit (0 = as
+ * many as fit).  A configuration needs the shape's L^2 (rounded up to 64)
+ * threads, and a workgroup sweeps as many configurations of one shape at
+ * once as fit in its threads and LDS.  Bound plan only; TFIM_EINVAL for a
+ * geometry that does not fit. */
+tfim_status tfim_set_batch(tfim_plan *plan, uint32_t threads, uint32_t blocks_per_cu);
 
-/* Sweep kernel variant (all give bit-identical chains):
- * 0 = streaming (one barrier per two tau planes; default),
- * 1 = chunked (eight tau planes per step).  Host-only. */
+typedef struct {
+    uint32_t schedule;             /* TFIM_SCHED_* in use */
+    uint32_t variant;              /* sweep-kernel variant of the per-shape schedule */
+    uint32_t batch_threads;        /* batched geometry (0 if never set up) */
+    uint32_t batch_blocks_per_cu;
+    uint32_t batch_blocks;         /* workgroups of one batched launch */
+    uint32_t batch_items;          /* work items of one batched sweep */
+    double ms_per_sweep;           /* best trial of the last tfim_autotune, 0 if none */
+} tfim_tuning;
+
+/* Autotuner.  Under each candidate (per-shape schedule with streaming
+ * variants 0 and 2; batched schedule with every workgroup size from the
+ * smallest legal one up to 576 in steps of the largest shape's column
+ * count) it runs one untimed sweep, then `sweeps_per_trial` sweeps timed
+ * with HIP events, and keeps the fastest.  The trial sweeps are ordinary
+ * sweeps of the chain and every candidate gives the same bits, so the
+ * state afterwards equals that after the same number of tfim_sweep calls
+ * of one sweep; *sweeps_done (may be NULL) returns that number.
+ * cache_path (may be NULL): a choice stored there for the same device and
+ * shapes is applied without trials (*sweeps_done = 0); a new choice is
+ * written back (one line per key).  Synchronous.  Bound plan only. */
+tfim_status tfim_autotune(tfim_plan *plan, uint32_t sweeps_per_trial, const char *cache_path,
+                          uint64_t *sweeps_done);
+tfim_status tfim_get_tuning(const tfim_plan *plan, tfim_tuning *out);
+
+/* Sweep kernel variant of the per-shape schedule (all give bit-identical
+ * chains): 0 = streaming (one barrier per two tau planes; default),
+ * 1 = chunked (eight tau planes per step), 2 = streaming compiled for at
+ * least five waves per SIMD.  Host-only. */
 tfim_status tfim_set_variant(tfim_plan *plan, uint32_t variant);
 
 /* Kernel timing: while enabled, tfim_sweep records a pair of HIP events on
- * the bound stream around every sweep-kernel launch.  tfim_get_timing
- * synchronises the stream, returns the summed kernel time in ms and the
- * number of timed launches since the last call, and resets them. */
+ * the bound stream around every sweep-kernel launch (per-shape schedule:
+ * one launch per shape and sweep) or around every graph replay (batched
+ * schedule: the span covers the sweeps, tempering and counter advances of
+ * the replay, and counts as that many launches).  tfim_get_timing
+ * synchronises the stream, returns the summed time in ms and the number of
+ * timed launches since the last call, and resets them. */
 tfim_status tfim_set_timing(tfim_plan *plan, uint32_t enable);
 tfim_status tfim_get_timing(tfim_plan *plan, double *kernel_ms, uint64_t *launches);
 

@@ -61,10 +61,20 @@ struct tfim_plan {
     int variant = 0;
     uint32_t measure_mode = 0;
     double tuned_ms = 0.0;
-    std::map<uint64_t, hipGraphExec_t> graphs;  // keyed by (n, t phase) for the per-shape schedule
-    // HIP-event timing of sweep-kernel launches (tfim_set_timing)
+    // batched schedule: arena region (ShapeDev[ns], first[ns+1], queue,
+    // items[]), geometry, and the graphs of 1..kGraphSweeps sweeps
+    size_t oBatch = 0, oFirst = 0, oQueue = 0, oItems = 0, max_items = 0;
+    uint32_t batch_threads = 0, batch_bpc = 0, batch_blocks = 0, temper_blocks = 0;
+    size_t batch_lds = 0;
+    std::vector<uint64_t> items;
+    int max_nk = 0, n_cu = 0;
+    bool any_pt = false;
+    hipStream_t cap_stream = nullptr;
+    std::map<uint32_t, hipGraphExec_t> graphs;  // sweeps per replay -> graph
+    // HIP-event timing (tfim_set_timing): event pairs and the launches each covers
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used, ev_free;
+    std::vector<uint32_t> ev_n;
 };
 
 namespace {
@@ -322,6 +332,14 @@ tfim_status tfim_plan_create(const tfim_shape* shapes, uint32_t n_shapes, uint64
     pl->oCounters = off;
     off = align256(off + sizeof(tfim::Counters) * n_shapes);
     tot_tab += sizeof(tfim::Counters) * n_shapes;
+    size_t nitems = 0;
+    for (auto& h : pl->shapes) nitems += (size_t)h.s.n_replicas * h.s.n_k * h.s.n_words;
+    pl->oBatch = off; off = align256(off + sizeof(tfim::ShapeDev) * n_shapes);
+    pl->oFirst = off; off = align256(off + 4 * (size_t)(n_shapes + 1));
+    pl->oQueue = off; off = align256(off + sizeof(tfim::BatchQueue));
+    pl->oItems = off; off = align256(off + 8 * nitems);
+    pl->max_items = nitems;
+    tot_tab += sizeof(tfim::ShapeDev) * n_shapes + 4 * (n_shapes + 1) + sizeof(tfim::BatchQueue) + 8 * nitems;
     pl->sizes.total = off;
     pl->sizes.spins = tot_S;
     pl->sizes.couplings = tot_J;
@@ -342,12 +360,19 @@ static void drop_events(tfim_plan* pl) {
         }
     pl->ev_used.clear();
     pl->ev_free.clear();
+    pl->ev_n.clear();
+}
+
+static void drop_graphs(tfim_plan* pl) {
+    for (auto& kv : pl->graphs) (void)hipGraphExecDestroy(kv.second);
+    pl->graphs.clear();
 }
 
 void tfim_plan_destroy(tfim_plan* pl) {
     if (!pl) return;
     drop_events(pl);
-    for (auto& kv : pl->graphs) (void)hipGraphExecDestroy(kv.second);
+    drop_graphs(pl);
+    if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
     delete pl;
 }
 
@@ -365,9 +390,15 @@ tfim_status tfim_bind(tfim_plan* pl, void* arena, size_t bytes, void* stream) {
     pl->stream = (hipStream_t)stream;
     pl->bound = true;
     pl->poisoned = false;
-    for (auto& kv : pl->graphs) (void)hipGraphExecDestroy(kv.second);
-    pl->graphs.clear();
-    hipError_t e = hipSuccess;
+    drop_graphs(pl);
+    pl->batch_threads = pl->batch_bpc = pl->batch_blocks = 0;
+    pl->schedule = TFIM_SCHED_PER_SHAPE;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&pl->n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess && !pl->cap_stream) e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(pl->arena + pl->oQueue, 0, sizeof(tfim::BatchQueue), pl->stream);
     for (size_t i = 0; i < pl->shapes.size() && e == hipSuccess; ++i) {
         ShapeHost& h = pl->shapes[i];
         e = hipMemcpyAsync(pl->arena + h.oTu, h.Tu.data(), h.Tu.size() * 4, hipMemcpyHostToDevice, pl->stream);
@@ -464,28 +495,39 @@ static tfim_status all_ready(tfim_plan* pl) {
     return TFIM_OK;
 }
 
-static hipError_t timed_sweep(tfim_plan* pl, int i, bool energy) {
-    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+// A pair of timing events around one launch (or graph replay) covering n
+// sweep launches, when timing is on.
+static hipError_t timing_begin(tfim_plan* pl, std::pair<hipEvent_t, hipEvent_t>& ev) {
+    ev = {nullptr, nullptr};
+    if (!pl->timing) return hipSuccess;
     hipError_t e = hipSuccess;
-    if (pl->timing) {
-        if (pl->ev_free.empty()) {
-            e = hipEventCreate(&ev.first);
-            if (e == hipSuccess) e = hipEventCreate(&ev.second);
-            if (e != hipSuccess) return e;
-        } else {
-            ev = pl->ev_free.back();
-            pl->ev_free.pop_back();
-        }
-        e = hipEventRecord(ev.first, pl->stream);
+    if (pl->ev_free.empty()) {
+        e = hipEventCreate(&ev.first);
+        if (e == hipSuccess) e = hipEventCreate(&ev.second);
+        if (e != hipSuccess) return e;
+    } else {
+        ev = pl->ev_free.back();
+        pl->ev_free.pop_back();
     }
+    return hipEventRecord(ev.first, pl->stream);
+}
+
+static hipError_t timing_end(tfim_plan* pl, std::pair<hipEvent_t, hipEvent_t>& ev, uint32_t n,
+                             hipError_t e) {
+    if (!pl->timing) return e;
+    if (e == hipSuccess) e = hipEventRecord(ev.second, pl->stream);
+    pl->ev_used.push_back(ev);
+    pl->ev_n.push_back(n);
+    return e;
+}
+
+static hipError_t timed_sweep(tfim_plan* pl, int i, bool energy) {
+    std::pair<hipEvent_t, hipEvent_t> ev;
+    hipError_t e = timing_begin(pl, ev);
     if (e == hipSuccess)
         e = tfim::launch_sweep(dev_of(pl, i), pl->seed, counters_of(pl, i), pl->variant, energy,
                                pl->stream);
-    if (pl->timing) {
-        if (e == hipSuccess) e = hipEventRecord(ev.second, pl->stream);
-        pl->ev_used.push_back(ev);
-    }
-    return e;
+    return timing_end(pl, ev, 1, e);
 }
 
 // Enqueue one sweep of every shape (plus due tempering) with the per-shape
@@ -508,25 +550,190 @@ static hipError_t enqueue_sweep(tfim_plan* pl, bool last) {
     return e;
 }
 
-tfim_status tfim_sweep(tfim_plan* pl, uint64_t n) {
+// ---------------------------------------------------------------------------
+// Batched schedule
+// ---------------------------------------------------------------------------
+constexpr uint32_t kGraphSweeps = 16;        // sweeps captured per graph
+constexpr uint32_t kMaxBatchThreads = 576;   // launch bound of the batched kernel
+constexpr size_t kLdsLimit = 160 * 1024 - 256;
+
+static tfim::BatchArgs batch_args(const tfim_plan* pl) {
+    tfim::BatchArgs a{};
+    a.shapes = (const tfim::ShapeDev*)(pl->arena + pl->oBatch);
+    a.items = (const uint64_t*)(pl->arena + pl->oItems);
+    a.q = (tfim::BatchQueue*)(pl->arena + pl->oQueue);
+    a.ctr = counters_of(pl, 0);
+    a.n_items = (uint32_t)pl->items.size();
+    a.key0 = (uint32_t)pl->seed;
+    a.key1 = (uint32_t)(pl->seed >> 32);
+    a.force_energy = 0;
+    return a;
+}
+
+static tfim::TemperBatchArgs temper_args(const tfim_plan* pl) {
+    tfim::TemperBatchArgs a{};
+    a.shapes = (const tfim::ShapeDev*)(pl->arena + pl->oBatch);
+    a.first = (const uint32_t*)(pl->arena + pl->oFirst);
+    a.ctr = counters_of(pl, 0);
+    a.n_shapes = (uint32_t)pl->shapes.size();
+    a.key0 = (uint32_t)pl->seed;
+    a.key1 = (uint32_t)(pl->seed >> 32);
+    return a;
+}
+
+// Work items and geometry of the batched launch; uploads the shape table,
+// the tempering block ranges and the items, rewinds the queue.
+static tfim_status batch_setup(tfim_plan* pl, uint32_t threads, uint32_t bpc) {
+    const int ns = (int)pl->shapes.size();
+    int maxcols = 0;
+    for (int i = 0; i < ns; ++i) {
+        const tfim::ShapeDev d = dev_of(pl, i);
+        if (!tfim::sweep_stream_ok(d))
+            return fail(TFIM_EUNSUPPORTED, "batched schedule needs every shape on the streaming sweep");
+        maxcols = std::max(maxcols, tfim::sweep_stream_cols(d));
+    }
+    if (threads == 0) threads = (uint32_t)maxcols;
+    if (threads % 64 || threads < (uint32_t)maxcols || threads > kMaxBatchThreads)
+        return fail(TFIM_EINVAL, "batch threads must be a multiple of 64 in [largest L^2 rounded to 64, 576]");
+    struct Item { uint64_t e; int Lt; size_t order; };
+    std::vector<Item> it;
+    size_t lds = 0;
+    std::vector<tfim::ShapeDev> devs(ns);
+    std::vector<uint32_t> first(ns + 1, 0);
+    int max_nk = 0;
+    bool any_pt = false;
+    for (int i = 0; i < ns; ++i) {
+        const tfim::ShapeDev d = dev_of(pl, i);
+        devs[i] = d;
+        const int cols = tfim::sweep_stream_cols(d);
+        int g = std::min<int>((int)threads / cols, 255);
+        while (g > 1 && tfim::sweep_stream_lds_bytes(d, g, (int)threads) > kLdsLimit) --g;
+        if (tfim::sweep_stream_lds_bytes(d, g, (int)threads) > kLdsLimit)
+            return fail(TFIM_EUNSUPPORTED, "batched workgroup does not fit in LDS");
+        lds = std::max(lds, tfim::sweep_stream_lds_bytes(d, g, (int)threads));
+        const int ncfg = d.R * d.nk * d.W;
+        for (int c0 = 0; c0 < ncfg; c0 += g) {
+            const uint64_t live = (uint64_t)std::min(g, ncfg - c0);
+            it.push_back({(uint64_t)i | ((uint64_t)g << 8) | (live << 16) | ((uint64_t)c0 << 32), d.Lt,
+                          it.size()});
+        }
+        first[i + 1] = first[i] + (uint32_t)(d.R * d.W);
+        max_nk = std::max(max_nk, d.nk);
+        any_pt = any_pt || d.pt_every != 0;
+    }
+    // longest items first (a sweep of a configuration takes time ~ Ltau)
+    std::stable_sort(it.begin(), it.end(), [](const Item& a, const Item& b) { return a.Lt > b.Lt; });
+    int per_cu = 0;
+    hipError_t e = tfim::sweep_batch_prepare(1, lds, (int)threads, &per_cu);
+    if (e != hipSuccess) return check_hip(pl, e, "batch prepare");
+    if (per_cu <= 0) return fail(TFIM_EUNSUPPORTED, "batched workgroup cannot be resident");
+    if (bpc) per_cu = std::min<int>(per_cu, (int)bpc);
+    std::vector<uint64_t> items(it.size());
+    for (size_t k = 0; k < it.size(); ++k) items[k] = it[k].e;
+    e = hipMemcpyAsync(pl->arena + pl->oBatch, devs.data(), sizeof(tfim::ShapeDev) * ns,
+                       hipMemcpyHostToDevice, pl->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(pl->arena + pl->oFirst, first.data(), 4 * first.size(), hipMemcpyHostToDevice,
+                           pl->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(pl->arena + pl->oItems, items.data(), 8 * items.size(), hipMemcpyHostToDevice,
+                           pl->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(pl->arena + pl->oQueue, 0, sizeof(tfim::BatchQueue), pl->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(pl->stream);
+    if (e != hipSuccess) return check_hip(pl, e, "batch upload");
+    drop_graphs(pl);
+    pl->items = std::move(items);
+    pl->batch_threads = threads;
+    pl->batch_bpc = bpc;
+    pl->batch_blocks = (uint32_t)std::min<size_t>((size_t)pl->n_cu * per_cu, pl->items.size());
+    pl->batch_lds = lds;
+    pl->temper_blocks = first[ns];
+    pl->max_nk = max_nk;
+    pl->any_pt = any_pt;
+    return TFIM_OK;
+}
+
+// The graph of g batched sweeps (captured once on the private stream).
+static hipError_t batch_graph(tfim_plan* pl, uint32_t g, hipGraphExec_t* out) {
+    auto f = pl->graphs.find(g);
+    if (f != pl->graphs.end()) {
+        *out = f->second;
+        return hipSuccess;
+    }
+    tfim::BatchArgs a = batch_args(pl);
+    const tfim::TemperBatchArgs ta = temper_args(pl);
+    hipError_t e = hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t le = hipSuccess;
+    for (uint32_t s = 0; s < g && le == hipSuccess; ++s) {
+        a.force_energy = (s + 1 == g) ? 1u : 0u;  // U is exact after the last sweep of a replay
+        le = tfim::launch_sweep_batch(a, 1, (int)pl->batch_blocks, (int)pl->batch_threads, pl->batch_lds,
+                                      pl->cap_stream);
+        if (le == hipSuccess && pl->any_pt)
+            le = tfim::launch_temper_batch(ta, (int)pl->temper_blocks, pl->max_nk, pl->cap_stream);
+        if (le == hipSuccess) le = tfim::launch_advance_batch(ta, pl->cap_stream);
+    }
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(pl->cap_stream, &graph);
+    if (le != hipSuccess || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return le != hipSuccess ? le : e;
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return e;
+    pl->graphs[g] = exec;
+    *out = exec;
+    return hipSuccess;
+}
+
+static hipError_t enqueue_batched(tfim_plan* pl, uint64_t n) {
+    hipError_t e = hipSuccess;
+    while (n > 0 && e == hipSuccess) {
+        const uint32_t g = (uint32_t)std::min<uint64_t>(n, kGraphSweeps);
+        hipGraphExec_t ex = nullptr;
+        e = batch_graph(pl, g, &ex);
+        if (e != hipSuccess) break;
+        std::pair<hipEvent_t, hipEvent_t> ev;
+        e = timing_begin(pl, ev);
+        if (e == hipSuccess) e = hipGraphLaunch(ex, pl->stream);
+        e = timing_end(pl, ev, g, e);
+        n -= g;
+    }
+    return e;
+}
+
+static tfim_status sweep_impl(tfim_plan* pl, uint64_t n) {
     tfim_status st = usable(pl);
     if (st != TFIM_OK) return st;
     if ((st = all_ready(pl)) != TFIM_OK) return st;
     if (n == 0) return TFIM_OK;
     for (size_t i = 0; i < pl->shapes.size(); ++i)
         if (pl->t[i] + n > 0xFFFFFFFFull) return fail(TFIM_EOVERFLOW, "sweep counter would pass 2^32-1");
-    hipError_t e = hipSuccess;
-    for (uint64_t s = 0; s < n && e == hipSuccess; ++s) {
-        e = enqueue_sweep(pl, s + 1 == n);
-        if (e != hipSuccess) break;
+    // host mirrors of the counters: tempering after sweeps t+1 .. t+n that
+    // are multiples of pt_every
+    auto advance = [pl](uint64_t k) {
         for (size_t i = 0; i < pl->shapes.size(); ++i) {
-            const uint32_t pe = pl->shapes[i].s.pt_every;
-            if (pe > 0 && ((pl->t[i] + 1) % pe) == 0) pl->m[i] += 1;
-            pl->t[i] += 1;
+            const uint64_t pe = pl->shapes[i].s.pt_every;
+            if (pe > 0) pl->m[i] += (pl->t[i] + k) / pe - pl->t[i] / pe;
+            pl->t[i] += k;
+        }
+    };
+    hipError_t e = hipSuccess;
+    if (pl->schedule == TFIM_SCHED_BATCHED) {
+        e = enqueue_batched(pl, n);
+        if (e == hipSuccess) advance(n);
+    } else {
+        for (uint64_t s = 0; s < n && e == hipSuccess; ++s) {
+            e = enqueue_sweep(pl, s + 1 == n);  // reads the mirrors of this sweep
+            if (e == hipSuccess) advance(1);
         }
     }
     return check_hip(pl, e, "sweep");
 }
+
+tfim_status tfim_sweep(tfim_plan* pl, uint64_t n) { return sweep_impl(pl, n); }
 
 tfim_status tfim_pt_swap(tfim_plan* pl) {
     tfim_status st = usable(pl);
@@ -690,8 +897,10 @@ tfim_status tfim_get_timing(tfim_plan* pl, double* ms_total, uint64_t* launches)
         tot += ms;
         pl->ev_free.push_back(ev);
     }
-    const uint64_t n = pl->ev_used.size();
+    uint64_t n = 0;
+    for (uint32_t c : pl->ev_n) n += c;
     pl->ev_used.clear();
+    pl->ev_n.clear();
     if (ms_total) *ms_total = tot;
     if (launches) *launches = n;
     return check_hip(pl, e, "timing");
@@ -708,22 +917,202 @@ tfim_status tfim_set_schedule(tfim_plan* pl, uint32_t schedule) {
     if (!pl) return fail(TFIM_EINVAL, "null plan");
     if (schedule != TFIM_SCHED_PER_SHAPE && schedule != TFIM_SCHED_BATCHED)
         return fail(TFIM_EINVAL, "unknown schedule");
-    if (schedule == TFIM_SCHED_BATCHED) return fail(TFIM_EUNSUPPORTED, "batched schedule not built yet");
+    if (schedule == TFIM_SCHED_BATCHED) {
+        tfim_status st = usable(pl);
+        if (st != TFIM_OK) return st;
+        if (pl->batch_threads == 0 && (st = batch_setup(pl, 0, 0)) != TFIM_OK) return st;
+    }
     pl->schedule = schedule;
     return TFIM_OK;
 }
 
-tfim_status tfim_autotune(tfim_plan* pl, uint32_t sweeps_per_trial) {
-    (void)sweeps_per_trial;
+tfim_status tfim_set_batch(tfim_plan* pl, uint32_t threads, uint32_t blocks_per_cu) {
     tfim_status st = usable(pl);
     if (st != TFIM_OK) return st;
-    return fail(TFIM_EUNSUPPORTED, "autotuner not built yet");
+    return batch_setup(pl, threads, blocks_per_cu);
 }
 
-tfim_status tfim_get_tuning(const tfim_plan* pl, uint32_t* config_id, double* ms) {
-    if (!pl) return fail(TFIM_EINVAL, "null plan");
-    if (config_id) *config_id = (uint32_t)pl->variant;
-    if (ms) *ms = pl->tuned_ms;
+namespace {
+
+struct Choice {
+    uint32_t schedule = TFIM_SCHED_PER_SHAPE, variant = 0, threads = 0, bpc = 0;
+    double ms = 0.0;
+};
+
+// Cache key: device and every shape's geometry (results never depend on it).
+std::string tune_key(const tfim_plan* pl) {
+    std::string k;
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        k = std::string(prop.gcnArchName) + "/" + std::to_string(prop.multiProcessorCount) + "cu";
+    for (auto& h : pl->shapes) {
+        char b[128];
+        snprintf(b, sizeof b, "|%u,%u,%u,%u,%u,%u", h.s.L, h.s.Ltau, h.s.n_words, h.s.n_replicas, h.s.n_k,
+                 h.s.pt_every);
+        k += b;
+    }
+    return k;
+}
+
+// One JSON object per line: {"key": "...", "schedule": S, "variant": V,
+// "threads": T, "blocks_per_cu": B, "ms_per_sweep": M}
+bool read_field(const std::string& line, const char* name, double* v) {
+    const std::string pat = std::string("\"") + name + "\":";
+    const size_t p = line.find(pat);
+    if (p == std::string::npos) return false;
+    return sscanf(line.c_str() + p + pat.size(), " %lf", v) == 1;
+}
+
+bool cache_lookup(const char* path, const std::string& key, Choice* c) {
+    FILE* f = fopen(path, "r");
+    if (!f) return false;
+    const std::string want = "{\"key\": \"" + key + "\",";
+    char buf[4096];
+    bool found = false;
+    while (fgets(buf, sizeof buf, f)) {
+        const std::string line(buf);
+        if (line.compare(0, want.size(), want) != 0) continue;
+        double s, v, t, b, m;
+        if (read_field(line, "schedule", &s) && read_field(line, "variant", &v) &&
+            read_field(line, "threads", &t) && read_field(line, "blocks_per_cu", &b) &&
+            read_field(line, "ms_per_sweep", &m)) {
+            c->schedule = (uint32_t)s; c->variant = (uint32_t)v; c->threads = (uint32_t)t;
+            c->bpc = (uint32_t)b; c->ms = m;
+            found = true;
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+bool cache_store(const char* path, const std::string& key, const Choice& c) {
+    std::vector<std::string> keep;
+    const std::string mine = "{\"key\": \"" + key + "\",";
+    if (FILE* f = fopen(path, "r")) {
+        char buf[4096];
+        while (fgets(buf, sizeof buf, f)) {
+            std::string line(buf);
+            if (line.compare(0, mine.size(), mine) != 0 && line.size() > 1) keep.push_back(line);
+        }
+        fclose(f);
+    }
+    char b[256];
+    snprintf(b, sizeof b, " \"schedule\": %u, \"variant\": %u, \"threads\": %u, \"blocks_per_cu\": %u, "
+             "\"ms_per_sweep\": %.6f}\n", c.schedule, c.variant, c.threads, c.bpc, c.ms);
+    keep.push_back(mine + b);
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = fopen(tmp.c_str(), "w");
+    if (!f) return false;
+    for (auto& l : keep) fputs(l.c_str(), f);
+    const bool ok = fclose(f) == 0;
+    return ok && rename(tmp.c_str(), path) == 0;
+}
+
+}  // namespace
+
+static tfim_status apply_choice(tfim_plan* pl, const Choice& c) {
+    if (c.schedule == TFIM_SCHED_BATCHED) {
+        tfim_status st = batch_setup(pl, c.threads, c.bpc);
+        if (st != TFIM_OK) return st;
+    } else if (c.variant >= (uint32_t)tfim::sweep_variants()) {
+        return fail(TFIM_EINVAL, "unknown sweep variant");
+    }
+    pl->schedule = c.schedule;
+    pl->variant = (int)c.variant;
+    return TFIM_OK;
+}
+
+tfim_status tfim_autotune(tfim_plan* pl, uint32_t sweeps_per_trial, const char* cache_path,
+                          uint64_t* sweeps_done) {
+    tfim_status st = usable(pl);
+    if (st != TFIM_OK) return st;
+    if ((st = all_ready(pl)) != TFIM_OK) return st;
+    if (sweeps_per_trial == 0) return fail(TFIM_EINVAL, "sweeps_per_trial must be >= 1");
+    if (sweeps_done) *sweeps_done = 0;
+    const std::string key = tune_key(pl);
+    Choice c;
+    if (cache_path && cache_lookup(cache_path, key, &c)) {
+        if ((st = apply_choice(pl, c)) != TFIM_OK) return st;
+        pl->tuned_ms = c.ms;
+        return TFIM_OK;
+    }
+    // candidates
+    std::vector<Choice> cand;
+    bool stream_all = true;
+    int maxcols = 0;
+    for (int i = 0; i < (int)pl->shapes.size(); ++i) {
+        const tfim::ShapeDev d = dev_of(pl, i);
+        stream_all = stream_all && tfim::sweep_stream_ok(d);
+        maxcols = std::max(maxcols, tfim::sweep_stream_cols(d));
+    }
+    for (uint32_t v : {0u, 2u}) {
+        Choice p;
+        p.schedule = TFIM_SCHED_PER_SHAPE;
+        p.variant = v;
+        cand.push_back(p);
+        if (!stream_all) break;  // the other variants fall back to the same kernel
+    }
+    if (stream_all)
+        for (uint32_t t = (uint32_t)maxcols; t <= kMaxBatchThreads; t += (uint32_t)maxcols) {
+            Choice b;
+            b.schedule = TFIM_SCHED_BATCHED;
+            b.threads = t;
+            cand.push_back(b);
+        }
+    const bool timing = pl->timing;
+    pl->timing = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    uint64_t done = 0;
+    double best = -1.0;
+    Choice pick;
+    for (auto& cd : cand) {
+        if (e != hipSuccess) break;
+        st = apply_choice(pl, cd);
+        if (st == TFIM_EUNSUPPORTED) continue;  // geometry does not fit: not a candidate
+        if (st != TFIM_OK) break;
+        if ((st = sweep_impl(pl, 1)) != TFIM_OK) break;
+        done += 1;
+        e = hipEventRecord(e0, pl->stream);
+        if (e != hipSuccess) break;
+        if ((st = sweep_impl(pl, sweeps_per_trial)) != TFIM_OK) break;
+        done += sweeps_per_trial;
+        e = hipEventRecord(e1, pl->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) break;
+        cd.ms = ms / sweeps_per_trial;
+        if (best < 0.0 || cd.ms < best) {
+            best = cd.ms;
+            pick = cd;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    pl->timing = timing;
+    if (sweeps_done) *sweeps_done = done;
+    if (e != hipSuccess) return check_hip(pl, e, "autotune");
+    if (st != TFIM_OK && st != TFIM_EUNSUPPORTED) return st;
+    if (best < 0.0) return fail(TFIM_EUNSUPPORTED, "no launch configuration fits these shapes");
+    if ((st = apply_choice(pl, pick)) != TFIM_OK) return st;
+    pl->tuned_ms = best;
+    if (cache_path && !cache_store(cache_path, key, pick))
+        return fail(TFIM_EINVAL, std::string("cannot write tuning cache ") + cache_path);
+    return TFIM_OK;
+}
+
+tfim_status tfim_get_tuning(const tfim_plan* pl, tfim_tuning* out) {
+    if (!pl || !out) return fail(TFIM_EINVAL, "null argument");
+    out->schedule = pl->schedule;
+    out->variant = (uint32_t)pl->variant;
+    out->batch_threads = pl->batch_threads;
+    out->batch_blocks_per_cu = pl->batch_bpc;
+    out->batch_blocks = pl->batch_blocks;
+    out->batch_items = (uint32_t)pl->items.size();
+    out->ms_per_sweep = pl->tuned_ms;
     return TFIM_OK;
 }
 

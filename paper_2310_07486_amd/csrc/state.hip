@@ -82,10 +82,8 @@ __global__ void __launch_bounds__(64) k_mask_rebuild(ShapeDev sh) {
 // with d = U_a - U_b the swap of labels is accepted iff d <= 0 or
 // R < floor(2^32 exp(-(k_{i+1} - k_i) 2d)) (the exchange ratio of the two
 // Boltzmann weights, E = 2U - 3N).  One uniform per lane.
-__global__ void __launch_bounds__(64) k_temper(ShapeDev sh, uint32_t key0, uint32_t key1,
-                                               const Counters* __restrict__ ctr) {
-    extern __shared__ uint8_t kl[];  // [64][nk] labels, then [64][nk] inverse
-    const int r = blockIdx.x / sh.W, j = blockIdx.x % sh.W;
+__device__ void temper_group(const ShapeDev& sh, int r, int j, uint32_t key0, uint32_t key1,
+                             uint32_t m, uint8_t* kl /*[2][64][nk]*/) {
     const int lane = threadIdx.x, nk = sh.nk;
     uint8_t* ki = kl + lane * nk;
     uint8_t* wi = kl + 64 * nk + lane * nk;
@@ -94,7 +92,6 @@ __global__ void __launch_bounds__(64) k_temper(ShapeDev sh, uint32_t key0, uint3
         ki[w] = sh.kidx[base + w];
         wi[w] = sh.winv[base + w];
     }
-    const uint32_t m = ctr->m;
     const uint32_t c3 = ctr_word3(sh.word_offset + (uint32_t)j, sh.sid, kTagTemper);
     for (int i = (int)(m & 1u); i + 1 < nk; i += 2) {
         const int wa = wi[i], wb = wi[i + 1];
@@ -117,6 +114,39 @@ __global__ void __launch_bounds__(64) k_temper(ShapeDev sh, uint32_t key0, uint3
     }
     __syncthreads();
     rebuild_masks(sh, r, j, kl);
+}
+
+__global__ void __launch_bounds__(64) k_temper(ShapeDev sh, uint32_t key0, uint32_t key1,
+                                               const Counters* __restrict__ ctr) {
+    extern __shared__ uint8_t kl[];  // [64][nk] labels, then [64][nk] inverse
+    temper_group(sh, (int)blockIdx.x / sh.W, (int)blockIdx.x % sh.W, key0, key1, ctr->m, kl);
+}
+
+__device__ __forceinline__ bool pt_due(const ShapeDev& sh, uint32_t t) {
+    return sh.pt_every != 0 && ((t + 1) % sh.pt_every) == 0;
+}
+
+// Every shape's (r, j) groups in one launch; a shape whose tempering is not
+// due after this sweep is skipped.
+__global__ void __launch_bounds__(64) k_temper_batch(TemperBatchArgs a) {
+    extern __shared__ uint8_t kl[];
+    const uint32_t b = blockIdx.x;
+    uint32_t s = 0;
+    while (s + 1 < a.n_shapes && b >= a.first[s + 1]) ++s;
+    const ShapeDev sh = a.shapes[s];
+    if (!pt_due(sh, a.ctr[s].t)) return;
+    const int loc = (int)(b - a.first[s]);
+    temper_group(sh, loc / sh.W, loc % sh.W, a.key0, a.key1, a.ctr[s].m, kl);
+}
+
+__global__ void k_advance_batch(TemperBatchArgs a) {
+    const uint32_t s = threadIdx.x;
+    if (blockIdx.x == 0 && s < a.n_shapes) {
+        const uint32_t t = a.ctr[s].t;
+        const bool due = pt_due(a.shapes[s], t);
+        a.ctr[s].t = t + 1;
+        a.ctr[s].m += due ? 1u : 0u;
+    }
 }
 
 __global__ void k_advance(Counters* ctr, uint32_t dt, uint32_t dm) {
@@ -163,6 +193,16 @@ hipError_t launch_mask_rebuild(const ShapeDev& sh, hipStream_t st) {
 hipError_t launch_temper(const ShapeDev& sh, uint64_t seed, const Counters* ctr, hipStream_t st) {
     hipLaunchKernelGGL(k_temper, dim3(sh.R * sh.W), dim3(64), (size_t)128 * sh.nk, st, sh,
                        (uint32_t)seed, (uint32_t)(seed >> 32), ctr);
+    return hipGetLastError();
+}
+
+hipError_t launch_temper_batch(const TemperBatchArgs& a, int blocks, int max_nk, hipStream_t st) {
+    hipLaunchKernelGGL(k_temper_batch, dim3(blocks), dim3(64), (size_t)128 * max_nk, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance_batch(const TemperBatchArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL(k_advance_batch, dim3(1), dim3(64), 0, st, a);
     return hipGetLastError();
 }
 

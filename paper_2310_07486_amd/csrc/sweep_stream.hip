@@ -178,8 +178,10 @@ __device__ __forceinline__ void add_deep(uint64_t* d, int stride, uint64_t (&a)[
     }
 }
 
-// Per-lane sums of the workgroup's vertical counters into Ublk[64].
-__device__ void flush_deep(uint64_t* d, int stride, uint32_t* Ublk) {
+// Per-lane sums of the wave's vertical counters added into Ublk[64] (the
+// counters are cleared).  Every lane of the wave takes part in the ballots;
+// only waves of a team (add) contribute.
+__device__ void flush_deep(uint64_t* d, int stride, uint32_t* Ublk, bool add) {
     const int lane = threadIdx.x & 63;
     uint32_t acc = 0;
     for (int k = 0; k < kDeep; ++k) {
@@ -190,71 +192,86 @@ __device__ void flush_deep(uint64_t* d, int stride, uint32_t* Ublk) {
         }
         d[k * stride] = 0;
     }
-    atomicAdd(&Ublk[lane], acc);
+    if (add) atomicAdd(&Ublk[lane], acc);
 }
 
-// kOcc: minimum waves per SIMD the register allocation must allow (1 = no
-// constraint); a tuning knob, the results do not depend on it.
-template <bool kE, int kOcc>
-__global__ void __launch_bounds__(kMaxCols) __attribute__((amdgpu_waves_per_eu(kOcc)))
-k_sweep_stream(ShapeDev sh, uint32_t key0,
-                                                           uint32_t key1,
-                                                           const Counters* __restrict__ ctr) {
-    extern __shared__ uint64_t lds[];
-    const int L = sh.L, L2 = sh.L2, Lt = sh.Lt, nk = sh.nk, W = sh.W;
-    // X, Y: one word per column (each column publishes the word at its own,
-    // parity-dependent plane; its four neighbours have the other parity).
-    const int H = L2;
-    uint64_t* X = lds;           // [2][L2] colour-1 words (old) for the colour-0 step
-    uint64_t* Y = lds + 2 * H;   // [2][L2] colour-0 words (new) for the colour-1 step
-    uint64_t* ml = lds + 4 * H;  // [nk+1] lane masks of this walker and word
-    uint64_t* MM = ml + nk + 1;  // bucket masks, all u
-    const int nb0 = sh.bnb[0] + 1, nb1 = sh.bnb[1] + 1, nb2 = sh.bnb[2] + 1;
-    uint64_t* DEEP = MM + 2 * (nb0 + nb1 + nb2);  // [kDeep][blockDim] energy counters
-    uint32_t* TT = (uint32_t*)(DEEP + (kE ? kDeep * blockDim.x : 0));
-    uint32_t* Ublk = TT + nb0 + nb1 + nb2;
+// LDS of a block (64-bit words): TT, the bucket thresholds of the shape
+// (uint32, shared by the block); DEEP[kDeep][threads], the energy counters;
+// then one region per team: X[2 L2], Y[2 L2], ml[nk+1], MM[2 nbt] (the two
+// candidate lane masks of every bucket), Ublk[64] (uint32).
+__host__ __device__ inline int stream_nbt(const ShapeDev& sh) {
+    return sh.bnb[0] + sh.bnb[1] + sh.bnb[2] + 3;
+}
+__host__ __device__ inline int stream_team_words(const ShapeDev& sh) {
+    return 4 * sh.L2 + sh.nk + 1 + 2 * stream_nbt(sh) + 32;
+}
+__host__ __device__ inline int stream_cols(const ShapeDev& sh) { return ((sh.L2 + 63) / 64) * 64; }
 
-    const int cfg = blockIdx.x;  // ((r*nk + w)*W + j)
+// Sweep of g configurations cfg0 .. cfg0+g-1 of one shape by one block: a
+// team of `cols` threads (a multiple of 64) per configuration, all teams in
+// lockstep along tau (one barrier per segment).  Teams at or past `nlive`
+// and threads past the last team run the same barriers and touch no global
+// memory.  Segment sigma updates the colour-0 site at plane A = 2 sigma + p
+// and the colour-1 site of the previous step at A - 3.
+template <bool kE>
+__device__ __forceinline__ void sweep_teams(const ShapeDev& sh, const int cfg0, const int g,
+                                            const int nlive, const int cols, uint64_t* lds,
+                                            const uint32_t key0, const uint32_t key1,
+                                            const uint32_t t) {
+    const int L = sh.L, L2 = sh.L2, Lt = sh.Lt, nk = sh.nk, W = sh.W;
+    const int nb0 = sh.bnb[0] + 1, nb1 = sh.bnb[1] + 1, nb2 = sh.bnb[2] + 1;
+    const int nbt = nb0 + nb1 + nb2;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int team = __builtin_amdgcn_readfirstlane(tid / cols);  // cols % 64 == 0: wave-uniform
+    const int ttid = tid - team * cols;
+    const bool member = team < g;
+    const int lteam = member ? team : g - 1;
+    const bool live = member && team < nlive;
+    const bool active = live && ttid < L2;
+
+    uint32_t* TT = (uint32_t*)lds;
+    uint64_t* DEEP = lds + ((nbt + 1) >> 1);
+    uint64_t* X = DEEP + kDeep * nthr + (size_t)lteam * stream_team_words(sh);
+    uint64_t* Y = X + 2 * L2;
+    uint64_t* ml = X + 4 * L2;
+    uint64_t* MM = ml + nk + 1;
+    uint32_t* Ublk = (uint32_t*)(MM + 2 * nbt);
+    const int H = L2;
+
+    const int cfg = cfg0 + lteam;  // ((r*nk + w)*W + j)
     const int j = cfg % W;
     const int rw = cfg / W;
     const int w = rw % nk;
     const int r = rw / nk;
-    const int tid = threadIdx.x;
-    const bool active = tid < L2;
 
-    for (int i = tid; i <= nk; i += blockDim.x)
-        ml[i] = sh.mask[((size_t)(r * W + j) * nk + w) * (nk + 1) + i];
-    if (kE && tid < 64) Ublk[tid] = 0;
+    if (member)
+        for (int i = ttid; i <= nk; i += cols)
+            ml[i] = live ? sh.mask[((size_t)(r * W + j) * nk + w) * (nk + 1) + i] : 0ull;
+    if (kE && member && ttid < 64) Ublk[ttid] = 0;
     if (kE)
-        for (int i = 0; i < kDeep; ++i) DEEP[i * blockDim.x + tid] = 0;
+        for (int i = 0; i < kDeep; ++i) DEEP[i * nthr + tid] = 0;
     __syncthreads();
-    {
-        const int nbs[3] = {nb0, nb1, nb2};
-        int base = 0;
-        for (int u = 0; u < 3; ++u) {
-            for (int a = tid; a < nbs[u]; a += blockDim.x) {
-                const uint64_t e = sh.btab[sh.boff[u] + a];
-                const uint32_t kb = (uint32_t)(e >> 32) & 0xFFFFu, mu = (uint32_t)(e >> 48);
-                TT[base + a] = (uint32_t)e;
-                MM[2 * (base + a)] = ml[kb];
-                MM[2 * (base + a) + 1] = ml[kb + mu];
-            }
-            base += nbs[u];
+    // entry a of the concatenated tables (u = 0, 1, 2) sits at btab[a + shift(u)]
+    const int bo0 = sh.boff[0], bo1 = sh.boff[1] - nb0, bo2 = sh.boff[2] - nb0 - nb1;
+    for (int a = tid; a < nbt; a += nthr)
+        TT[a] = (uint32_t)sh.btab[a + (a < nb0 ? bo0 : (a < nb0 + nb1 ? bo1 : bo2))];
+    if (member)
+        for (int a = ttid; a < nbt; a += cols) {
+            const uint64_t e = sh.btab[a + (a < nb0 ? bo0 : (a < nb0 + nb1 ? bo1 : bo2))];
+            const uint32_t kb = (uint32_t)(e >> 32) & 0xFFFFu, mu = (uint32_t)(e >> 48);
+            MM[2 * a] = ml[kb];
+            MM[2 * a + 1] = ml[kb + mu];
         }
-    }
     Tables tb;
     tb.T[0] = TT; tb.T[1] = TT + nb0; tb.T[2] = TT + nb0 + nb1;
     tb.M[0] = MM; tb.M[1] = MM + 2 * nb0; tb.M[2] = MM + 2 * (nb0 + nb1);
-    for (int u = 0; u < 3; ++u) {
-        tb.sh[u] = (uint32_t)sh.bsh[u];
-        tb.nb[u] = (uint32_t)sh.bnb[u];
-    }
+    tb.sh[0] = (uint32_t)sh.bsh[0]; tb.sh[1] = (uint32_t)sh.bsh[1]; tb.sh[2] = (uint32_t)sh.bsh[2];
+    tb.nb[0] = (uint32_t)sh.bnb[0]; tb.nb[1] = (uint32_t)sh.bnb[1]; tb.nb[2] = (uint32_t)sh.bnb[2];
 
-    const uint32_t t = ctr->t;
     const uint32_t c3 = ctr_word3(sh.word_offset + (uint32_t)j, sh.sid, kTagMetro);
     const uint32_t c2_0 = (uint32_t)rw << 1, c2_1 = c2_0 | 1u;
 
-    const int xy = active ? tid : 0;
+    const int xy = active ? ttid : 0;
     const int x = xy % L, y = xy / L;
     const int p = (x + y) & 1;
     const int hx = xy;
@@ -285,11 +302,12 @@ k_sweep_stream(ShapeDev sh, uint32_t key0,
     w5 = ld(p + 1);
     pf0 = ld(p + 2);
     pf1 = ld(p + 3);
+    uint64_t pu1 = ld(4);  // plane 2 sigma + 4 of the next segment for parity 0
     U4 G0, G1;
     uint32_t prevlast = 0;
     uint64_t sm[5] = {0, 0, 0, 0, 0};
     uint64_t* deep = DEEP + tid;
-    const int dstride = blockDim.x;
+    const int dstride = nthr;
     uint64_t f0 = 0, f1 = 0, f2 = 0;
 
     if (active) X[hx] = p ? w3 : w5;  // X(0)
@@ -299,15 +317,19 @@ k_sweep_stream(ShapeDev sh, uint32_t key0,
     auto segment = [&](const int sigma, const auto ISc, const bool do_c0, const bool do_c1) {
         constexpr int IS = decltype(ISc)::value;
         const int A = 2 * sigma + p;
-        nx0 = ld(A + 4);
-        nx1 = ld(A + 5);
+        // every load instruction reads whole planes 2 sigma + 5 and 2 sigma + 6
+        // (all columns, full cache lines); a thread keeps the two planes of
+        // its parity, A + 4 and A + 5
+        const uint64_t u0 = ld(2 * sigma + 5), u1 = ld(2 * sigma + 6);
+        nx0 = p ? u0 : pu1;
+        nx1 = p ? u1 : u0;
+        pu1 = u1;
         if (do_c0) {
             if (IS == 0) G0 = philox_dev((uint32_t)(xy + L2 * (sigma >> 2)), t, c2_0, c3, key0, key1);
             const uint64_t* Xb = X + (IS & 1) * H;
             const Nb n{Xb[hxp], Xb[hxm], Xb[hyp], Xb[hym]};
             uint64_t d0, d1, d2;
             w4 = site<false>(w4, n, jxp, jxm, jyp, jym, w5, w3, G0.v[IS], tb, d0, d1, d2);
-            if (active) col[(size_t)A * L2] = w4;
         }
         if (IS == 1) {  // colour-1 Philox group of step s = sigma - 1 (s % 4 == 0)
             prevlast = G1.v[3];
@@ -322,8 +344,13 @@ k_sweep_stream(ShapeDev sh, uint32_t key0,
             const Nb n{Yb[hxp], Yb[hxm], Yb[hyp], Yb[hym]};
             w1 = site<kE>(w1, n, jxp, jxm, jyp, jym, w2, w0, R1, tb, f0, f1, f2);
             if (kE && active) add3v(sm, f0, f1, f2);  // padding threads count nothing
-            if (active) col[(size_t)wrap(A - 3) * L2] = w1;
         }
+        // every store instruction writes whole planes 2 sigma - 3 and 2 sigma - 2:
+        // parity 0 holds colour 1 (just updated) and colour 0 (one segment
+        // old) there, parity 1 colour 0 (two segments old) and colour 1
+        const int P1 = 2 * sigma - 3, P2 = 2 * sigma - 2;
+        if (active && P1 >= 0) col[(size_t)wrap(P1) * L2] = p ? w0 : w1;
+        if (active && P2 >= 0) col[(size_t)wrap(P2) * L2] = p ? w1 : w2;
         if (active) {
             Y[(IS & 1) * H + hx] = p ? w2 : w4;
             X[((IS + 1) & 1) * H + hx] = p ? w5 : pf1;
@@ -336,52 +363,107 @@ k_sweep_stream(ShapeDev sh, uint32_t key0,
     using I2 = std::integral_constant<int, 2>;
     using I3 = std::integral_constant<int, 3>;
 
-    for (int g = 0; g < nq; ++g) {
-        const int s0 = 4 * g;
-        segment(s0 + 0, I0{}, true, g > 0);
-        segment(s0 + 1, I1{}, true, g > 0);
+    for (int gq = 0; gq < nq; ++gq) {
+        const int s0 = 4 * gq;
+        segment(s0 + 0, I0{}, true, gq > 0);
+        segment(s0 + 1, I1{}, true, gq > 0);
         segment(s0 + 2, I2{}, true, true);
         segment(s0 + 3, I3{}, true, true);
         if (kE) {
             add_deep(deep, dstride, sm);
-            if ((g % kFlushMacros) == kFlushMacros - 1) flush_deep(deep, dstride, Ublk);
+            if ((gq % kFlushMacros) == kFlushMacros - 1) flush_deep(deep, dstride, Ublk, member);
         }
     }
     segment(half, I0{}, false, true);      // colour 1, step half-1
     segment(half + 1, I1{}, false, true);  // colour 1, step half == step 0 (tau wrap)
     if (kE) {
         add_deep(deep, dstride, sm);
-        flush_deep(deep, dstride, Ublk);
+        flush_deep(deep, dstride, Ublk, member);
         __syncthreads();
-        if (tid < 64) sh.U[((size_t)r * W * 64 + (size_t)j * 64 + tid) * nk + w] = Ublk[tid];
+        if (live && ttid < 64) sh.U[((size_t)r * W * 64 + (size_t)j * 64 + ttid) * nk + w] = Ublk[ttid];
+    }
+}
+
+// One configuration per workgroup (r, w, j) = blockIdx.x.
+// kOcc: minimum waves per SIMD the register allocation must allow (1 = no
+// constraint); a tuning knob, the results do not depend on it.
+template <bool kE, int kOcc>
+__global__ void __launch_bounds__(kMaxCols) __attribute__((amdgpu_waves_per_eu(kOcc)))
+k_sweep_stream(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __restrict__ ctr) {
+    extern __shared__ uint64_t lds[];
+    sweep_teams<kE>(sh, (int)blockIdx.x, 1, 1, (int)blockDim.x, lds, key0, key1, ctr->t);
+}
+
+// Persistent sweep of every shape of a plan in one launch.  Work items
+// (shape, teams g, live teams, first configuration) are taken from a queue
+// in the order the host sorted them (longest first); a block sweeps the
+// item's configurations with g teams, then takes the next item.  Whether a
+// shape's energy is recounted (tempering due after this sweep, or the caller
+// asks for it) is read from the device counters, so one captured graph
+// serves every sweep.  The last block to finish rewinds the queue for the
+// next launch on the stream.
+template <int kOcc>
+__global__ void __launch_bounds__(kMaxCols) __attribute__((amdgpu_waves_per_eu(kOcc)))
+k_sweep_batch(BatchArgs a) {
+    extern __shared__ uint64_t lds[];
+    __shared__ uint32_t s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(&a.q->next, 1u);
+        __syncthreads();
+        const uint32_t it = __builtin_amdgcn_readfirstlane(s_item);
+        __syncthreads();
+        if (it >= a.n_items) break;
+        const uint64_t e = a.items[it];
+        const int s = (int)(e & 0xFFu), g = (int)((e >> 8) & 0xFFu), nlive = (int)((e >> 16) & 0xFFu);
+        const int cfg0 = (int)(e >> 32);
+        const ShapeDev& sh = a.shapes[s];
+        const uint32_t t = a.ctr[s].t;
+        const bool due = sh.pt_every != 0 && ((t + 1) % sh.pt_every) == 0;
+        const int cols = stream_cols(sh);
+        if (due || a.force_energy)
+            sweep_teams<true>(sh, cfg0, g, nlive, cols, lds, a.key0, a.key1, t);
+        else
+            sweep_teams<false>(sh, cfg0, g, nlive, cols, lds, a.key0, a.key1, t);
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&a.q->done, 1u) == gridDim.x - 1) {
+            atomicExch(&a.q->next, 0u);
+            atomicExch(&a.q->done, 0u);
+        }
     }
 }
 
 }  // namespace
 
-size_t sweep_stream_lds_bytes(const ShapeDev& sh) {
-    const size_t nb = (size_t)(sh.bnb[0] + 1) + (sh.bnb[1] + 1) + (sh.bnb[2] + 1);
-    const size_t threads = ((sh.L2 + 63) / 64) * 64;
-    return (size_t)(4 * sh.L2 + sh.nk + 1) * 8 + nb * 16 + threads * kDeep * 8 + nb * 4 + 64 * 4;
+size_t sweep_stream_lds_bytes(const ShapeDev& sh, int teams, int threads) {
+    const size_t nbt = (size_t)stream_nbt(sh);
+    return ((nbt + 1) / 2 + (size_t)kDeep * threads + (size_t)teams * stream_team_words(sh)) * 8;
 }
+
+int sweep_stream_cols(const ShapeDev& sh) { return stream_cols(sh); }
 
 bool sweep_stream_ok(const ShapeDev& sh) {
     return sh.bnb[0] >= 0 && sh.bnb[1] >= 0 && sh.bnb[2] >= 0 && sh.L2 <= kMaxCols &&
-           (sh.Lt % 8) == 0 && sh.Lt >= 8;
+           (sh.Lt % 8) == 0 && sh.Lt >= 16;
+}
+
+// Dynamic LDS above 64 KiB must be allowed per kernel, once.
+static hipError_t allow_lds(const void* fn, size_t bytes, size_t& done) {
+    if (bytes <= done) return hipSuccess;
+    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e == hipSuccess) done = bytes;
+    return e;
 }
 
 template <bool kE, int kOcc>
 static hipError_t launch_one(const ShapeDev& sh, uint64_t seed, const Counters* ctr, hipStream_t st) {
     const int nblk = sh.R * sh.nk * sh.W;
-    const int threads = ((sh.L2 + 63) / 64) * 64;
-    const size_t lds = sweep_stream_lds_bytes(sh);
-    static size_t lds_set = 0;  // dynamic LDS above 64 KiB must be allowed per kernel
-    if (lds > lds_set) {
-        const hipError_t e = hipFuncSetAttribute((const void*)k_sweep_stream<kE, kOcc>,
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        lds_set = lds;
-    }
+    const int threads = stream_cols(sh);
+    const size_t lds = sweep_stream_lds_bytes(sh, 1, threads);
+    static size_t lds_set = 0;
+    hipError_t e = allow_lds((const void*)k_sweep_stream<kE, kOcc>, lds, lds_set);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_sweep_stream<kE, kOcc>), dim3(nblk), dim3(threads), lds, st, sh,
                        (uint32_t)seed, (uint32_t)(seed >> 32), ctr);
     return hipGetLastError();
@@ -392,6 +474,29 @@ hipError_t launch_sweep_stream(const ShapeDev& sh, uint64_t seed, const Counters
     if (occ >= 5)
         return energy ? launch_one<true, 5>(sh, seed, ctr, st) : launch_one<false, 5>(sh, seed, ctr, st);
     return energy ? launch_one<true, 1>(sh, seed, ctr, st) : launch_one<false, 1>(sh, seed, ctr, st);
+}
+
+static const void* batch_fn(int occ) {
+    return occ >= 2 ? (const void*)k_sweep_batch<2> : (const void*)k_sweep_batch<1>;
+}
+
+hipError_t sweep_batch_prepare(int occ, size_t lds_bytes, int threads, int* blocks_per_cu) {
+    static size_t set1 = 0, set2 = 0;
+    hipError_t e = allow_lds(batch_fn(occ), lds_bytes, occ >= 2 ? set2 : set1);
+    if (e != hipSuccess || !blocks_per_cu) return e;
+    int nb = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_fn(occ), threads, lds_bytes);
+    *blocks_per_cu = nb;
+    return e;
+}
+
+hipError_t launch_sweep_batch(const BatchArgs& a, int occ, int blocks, int threads, size_t lds_bytes,
+                              hipStream_t st) {
+    if (occ >= 2)
+        hipLaunchKernelGGL((k_sweep_batch<2>), dim3(blocks), dim3(threads), lds_bytes, st, a);
+    else
+        hipLaunchKernelGGL((k_sweep_batch<1>), dim3(blocks), dim3(threads), lds_bytes, st, a);
+    return hipGetLastError();
 }
 
 }  // namespace tfim

@@ -52,6 +52,28 @@ struct Counters {
     uint32_t pad;
 };
 
+// Work queue of the persistent batched sweep; zero between launches.
+struct BatchQueue {
+    uint32_t next;  // next work item to hand out
+    uint32_t done;  // blocks that found the queue empty
+};
+
+// Arguments of the batched sweep and tempering kernels (device pointers).
+struct BatchArgs {
+    const ShapeDev* shapes;  // [n_shapes]
+    const uint64_t* items;   // shape | teams << 8 | live teams << 16 | first cfg << 32
+    BatchQueue* q;
+    const Counters* ctr;     // [n_shapes]
+    uint32_t n_items, key0, key1, force_energy;
+};
+
+struct TemperBatchArgs {
+    const ShapeDev* shapes;  // [n_shapes]
+    const uint32_t* first;   // [n_shapes + 1] first block of each shape, (r, j) groups
+    Counters* ctr;           // [n_shapes]
+    uint32_t n_shapes, key0, key1, pad;
+};
+
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the
 // two-multiplier S-box; the key advances by the Weyl increments each round.
@@ -103,7 +125,19 @@ hipError_t launch_sweep(const ShapeDev& sh, uint64_t seed, const Counters* ctr, 
 hipError_t launch_sweep_stream(const ShapeDev& sh, uint64_t seed, const Counters* ctr,
                                bool energy, int occ, hipStream_t st);
 bool sweep_stream_ok(const ShapeDev& sh);
-size_t sweep_stream_lds_bytes(const ShapeDev& sh);
+// LDS of a streaming-sweep block of `teams` configurations and `threads`
+// threads; threads per configuration (L^2 rounded up to whole waves).
+size_t sweep_stream_lds_bytes(const ShapeDev& sh, int teams, int threads);
+int sweep_stream_cols(const ShapeDev& sh);
+// Batched persistent sweep: allow its LDS and report resident blocks per CU
+// (occ: 1 or 2 = minimum waves per SIMD the kernel was compiled for).
+hipError_t sweep_batch_prepare(int occ, size_t lds_bytes, int threads, int* blocks_per_cu);
+hipError_t launch_sweep_batch(const BatchArgs& a, int occ, int blocks, int threads, size_t lds_bytes,
+                              hipStream_t st);
+// Tempering (when due, read from the counters) of every shape, then the
+// counter advance t += 1, m += due.
+hipError_t launch_temper_batch(const TemperBatchArgs& a, int blocks, int max_nk, hipStream_t st);
+hipError_t launch_advance_batch(const TemperBatchArgs& a, hipStream_t st);
 hipError_t launch_temper(const ShapeDev& sh, uint64_t seed, const Counters* ctr, hipStream_t st);
 hipError_t launch_advance(Counters* ctr, uint32_t dt, uint32_t dm, hipStream_t st);
 // Measurement of configurations cfg0 .. cfg0+ncfg-1 (cfg = i*S + s) into the

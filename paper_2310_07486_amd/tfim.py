@@ -38,7 +38,7 @@ SYMBOLS = [
     "tfim_export_couplings", "tfim_get_state", "tfim_get_counters", "tfim_set_state",
     "tfim_set_schedule", "tfim_autotune", "tfim_get_tuning", "tfim_sync", "tfim_strerror",
     "tfim_last_error_detail", "tfim_set_variant", "tfim_set_timing", "tfim_get_timing",
-    "tfim_measure_range", "tfim_set_measure_mode",
+    "tfim_measure_range", "tfim_set_measure_mode", "tfim_set_batch",
 ]
 TFIM_MEASURE_REUSE_LAYOUT = 1
 
@@ -56,6 +56,15 @@ class tfim_shape(ctypes.Structure):
         ("n_k", ctypes.c_uint32), ("k", ctypes.POINTER(ctypes.c_double)),
         ("bc_tau", ctypes.c_uint32), ("pt_every", ctypes.c_uint32),
         ("stream_id", ctypes.c_uint32),
+    ]
+
+
+class tfim_tuning(ctypes.Structure):
+    _fields_ = [
+        ("schedule", ctypes.c_uint32), ("variant", ctypes.c_uint32),
+        ("batch_threads", ctypes.c_uint32), ("batch_blocks_per_cu", ctypes.c_uint32),
+        ("batch_blocks", ctypes.c_uint32), ("batch_items", ctypes.c_uint32),
+        ("ms_per_sweep", ctypes.c_double),
     ]
 
 
@@ -99,8 +108,9 @@ def lib():
             "tfim_get_counters": [P, U32, P, P],
             "tfim_set_state": [P, U32, P, P, U64, U64],
             "tfim_set_schedule": [P, U32],
-            "tfim_autotune": [P, U32],
-            "tfim_get_tuning": [P, P, P],
+            "tfim_autotune": [P, U32, ctypes.c_char_p, P],
+            "tfim_get_tuning": [P, P],
+            "tfim_set_batch": [P, U32, U32],
             "tfim_sync": [P],
             "tfim_set_variant": [P, U32],
             "tfim_set_timing": [P, U32],
@@ -239,14 +249,21 @@ class Plan:
     def set_schedule(self, schedule: int):
         _check(lib().tfim_set_schedule(self._h, schedule), "tfim_set_schedule")
 
-    def autotune(self, sweeps_per_trial: int = 2):
-        _check(lib().tfim_autotune(self._h, sweeps_per_trial), "tfim_autotune")
+    def set_batch(self, threads: int = 0, blocks_per_cu: int = 0):
+        _check(lib().tfim_set_batch(self._h, threads, blocks_per_cu), "tfim_set_batch")
 
-    def tuning(self):
-        cid = ctypes.c_uint32()
-        ms = ctypes.c_double()
-        _check(lib().tfim_get_tuning(self._h, ctypes.byref(cid), ctypes.byref(ms)), "tfim_get_tuning")
-        return cid.value, ms.value
+    def autotune(self, sweeps_per_trial: int = 2, cache_path: Optional[str] = None) -> int:
+        """Returns the number of sweeps the trials advanced the chain by."""
+        done = ctypes.c_uint64()
+        path = cache_path.encode() if cache_path else None
+        _check(lib().tfim_autotune(self._h, sweeps_per_trial, path, ctypes.byref(done)),
+               "tfim_autotune")
+        return done.value
+
+    def tuning(self) -> dict:
+        t = tfim_tuning()
+        _check(lib().tfim_get_tuning(self._h, ctypes.byref(t)), "tfim_get_tuning")
+        return {n: getattr(t, n) for n, _ in tfim_tuning._fields_}
 
     def export_spins(self, shape: int = 0) -> np.ndarray:
         L, Lt, W, R, nk = self._dims(shape)

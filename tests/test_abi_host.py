@@ -73,6 +73,22 @@ def test_unbound_plan_refuses_device_calls():
     assert e.value.status == tfim.TFIM_ESTATE
 
 
+def test_unbound_plan_refuses_schedule_and_tuning():
+    p = _plan([Shape(8, 32, 1, 2, [0.2, 0.3])])
+    for call in (lambda: p.set_batch(64, 0), lambda: p.set_schedule(tfim.TFIM_SCHED_BATCHED),
+                 lambda: p.autotune(1)):
+        with pytest.raises(tfim.TfimError) as e:
+            call()
+        assert e.value.status == tfim.TFIM_ESTATE
+    with pytest.raises(tfim.TfimError) as e:
+        p.set_schedule(7)
+    assert e.value.status == tfim.TFIM_EINVAL
+    t = p.tuning()
+    assert t["schedule"] == tfim.TFIM_SCHED_PER_SHAPE and t["batch_threads"] == 0
+    assert t["ms_per_sweep"] == 0.0
+    p.set_schedule(tfim.TFIM_SCHED_PER_SHAPE)  # host-only, always allowed
+
+
 def test_thresholds_equal_oracle(oracle_lib):
     for w in (c2_multispin(), c3_large()):
         s = w.shapes[0]

@@ -44,26 +44,6 @@ constexpr int kRowPitch = 80;  // bytes per unpacked 64-element row in LDS (16-b
 constexpr int kMaxR = 4;       // replicas handled by the MFMA kernels
 constexpr int kMaxP = kMaxR * (kMaxR - 1) / 2;
 
-// ---------------------------------------------------------------------------
-// 64x64 bit transpose across a wavefront: lane t holds row t (bit u is
-// element (t, u)); afterwards lane u holds column u (bit t is element (t, u)).
-// Level k swaps the off-diagonal k x k blocks of every 2k x 2k block.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t wave_transpose64(uint64_t v) {
-    const int lane = threadIdx.x & 63;
-    const uint64_t masks[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull,
-                               0x00FF00FF00FF00FFull, 0x0F0F0F0F0F0F0F0Full,
-                               0x3333333333333333ull, 0x5555555555555555ull};
-#pragma unroll
-    for (int lv = 0; lv < 6; ++lv) {
-        const int k = 32 >> lv;
-        const uint64_t mk = masks[lv];
-        const uint64_t o = (uint64_t)__shfl_xor((long long)v, k, 64);
-        v = (lane & k) ? (((o >> k) & mk) | (v & ~mk)) : ((v & mk) | ((o & mk) << k));
-    }
-    return v;
-}
-
 constexpr int kTP = 65;  // padded row pitch (words) of the transpose tiles
 constexpr size_t kTransposeLds = (size_t)2 * 64 * kTP * 8 + 64 * 4;
 

@@ -559,14 +559,13 @@ constexpr size_t kLdsLimit = 160 * 1024 - 256;
 
 static tfim::BatchArgs batch_args(const tfim_plan* pl) {
     tfim::BatchArgs a{};
-    a.shapes = (const tfim::ShapeDev*)(pl->arena + pl->oBatch);
+    for (int i = 0; i < (int)pl->shapes.size() && i < tfim::kMaxBatchShapes; ++i) a.shapes[i] = dev_of(pl, i);
     a.items = (const uint64_t*)(pl->arena + pl->oItems);
     a.q = (tfim::BatchQueue*)(pl->arena + pl->oQueue);
     a.ctr = counters_of(pl, 0);
     a.n_items = (uint32_t)pl->items.size();
     a.key0 = (uint32_t)pl->seed;
     a.key1 = (uint32_t)(pl->seed >> 32);
-    a.force_energy = 0;
     return a;
 }
 
@@ -585,6 +584,7 @@ static tfim::TemperBatchArgs temper_args(const tfim_plan* pl) {
 // the tempering block ranges and the items, rewinds the queue.
 static tfim_status batch_setup(tfim_plan* pl, uint32_t threads, uint32_t bpc) {
     const int ns = (int)pl->shapes.size();
+    if (ns > tfim::kMaxBatchShapes) return fail(TFIM_EUNSUPPORTED, "batched schedule takes at most 8 shapes");
     int maxcols = 0;
     for (int i = 0; i < ns; ++i) {
         const tfim::ShapeDev d = dev_of(pl, i);
@@ -666,7 +666,6 @@ static hipError_t batch_graph(tfim_plan* pl, uint32_t g, hipGraphExec_t* out) {
     if (e != hipSuccess) return e;
     hipError_t le = hipSuccess;
     for (uint32_t s = 0; s < g && le == hipSuccess; ++s) {
-        a.force_energy = (s + 1 == g) ? 1u : 0u;  // U is exact after the last sweep of a replay
         le = tfim::launch_sweep_batch(a, 1, (int)pl->batch_blocks, (int)pl->batch_threads, pl->batch_lds,
                                       pl->cap_stream);
         if (le == hipSuccess && pl->any_pt)

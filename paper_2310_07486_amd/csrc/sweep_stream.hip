@@ -40,6 +40,24 @@ namespace {
 
 constexpr int kMaxCols = 576;  // one thread per column, L <= 24
 
+// Raw buffer access to one configuration's spin words: the descriptor covers
+// exactly its bytes (0 for a team without a configuration: loads return 0
+// and stores are dropped), the plane offset is a scalar.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr int kBufferWord3 = 0x00020000;
+
+__device__ __forceinline__ uint64_t buf_load(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+    return ((uint64_t)v.y << 32) | v.x;
+}
+
+__device__ __forceinline__ void buf_store(uint64_t x, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    u32x2 v;
+    v.x = (unsigned)x;
+    v.y = (unsigned)(x >> 32);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, 0);
+}
+
 // v_bitop3: bit i of the immediate is f(a_i, b_i, c_i) with the operands
 // weighted 0xF0 (a), 0xCC (b), 0xAA (c).
 constexpr uint32_t kA = 0xF0, kB = 0xCC, kC = 0xAA;
@@ -179,17 +197,15 @@ __device__ __forceinline__ void add_deep(uint64_t* d, int stride, uint64_t (&a)[
 }
 
 // Per-lane sums of the wave's vertical counters added into Ublk[64] (the
-// counters are cleared).  Every lane of the wave takes part in the ballots;
-// only waves of a team (add) contribute.
+// counters are cleared).  Plane k is transposed across the wave, so lane b
+// holds bit b of every thread's plane and popcounts it.  Every lane of the
+// wave takes part; only waves of a team (add) contribute.
 __device__ void flush_deep(uint64_t* d, int stride, uint32_t* Ublk, bool add) {
     const int lane = threadIdx.x & 63;
     uint32_t acc = 0;
+#pragma unroll
     for (int k = 0; k < kDeep; ++k) {
-        const uint64_t v = d[k * stride];
-        for (int b = 0; b < 64; ++b) {
-            const uint32_t cnt = (uint32_t)__popcll(__ballot((v >> b) & 1ull));
-            acc += (lane == b) ? (cnt << k) : 0u;
-        }
+        acc += (uint32_t)__popcll(wave_transpose64(d[k * stride])) << k;
         d[k * stride] = 0;
     }
     if (add) atomicAdd(&Ublk[lane], acc);
@@ -238,7 +254,7 @@ __device__ __forceinline__ void sweep_teams(const ShapeDev& sh, const int cfg0, 
     uint32_t* Ublk = (uint32_t*)(MM + 2 * nbt);
     const int H = L2;
 
-    const int cfg = cfg0 + lteam;  // ((r*nk + w)*W + j)
+    const int cfg = __builtin_amdgcn_readfirstlane(cfg0 + lteam);  // ((r*nk + w)*W + j), uniform
     const int j = cfg % W;
     const int rw = cfg / W;
     const int w = rw % nk;
@@ -287,21 +303,32 @@ __device__ __forceinline__ void sweep_teams(const ShapeDev& sh, const int cfg0, 
         jyp = Jb[L2 + xy];
         jym = Jb[L2 + x + L * ((y + L - 1) % L)];
     }
-    uint64_t* col = sh.S + (size_t)cfg * Lt * L2 + xy;
+    // descriptor fields are uniform: make that explicit (a vector descriptor
+    // would turn every access into a loop over lanes)
+    const uint64_t base = (uint64_t)(sh.S + (size_t)cfg * Lt * L2);
+    const uint32_t base_lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
+    const uint32_t base_hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
+    const int nbytes = __builtin_amdgcn_readfirstlane(live ? Lt * L2 * 8 : 0);
+    const __amdgpu_buffer_rsrc_t spins = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(((uint64_t)base_hi << 32) | base_lo), (short)0, nbytes, kBufferWord3);
+    const int voff = 8 * xy;
+    const int plane = 8 * L2;      // bytes per tau plane
     const int half = Lt >> 1;      // colour-0 steps
     const int nq = Lt >> 3;        // Philox groups per colour and column
     auto wrap = [Lt](int P) { return P >= Lt ? P - Lt : (P < 0 ? P + Lt : P); };
-    auto ld = [&](int P) -> uint64_t {
-        return (active && P <= Lt + 1) ? col[(size_t)wrap(P) * L2] : 0ull;
-    };
+    // uniform plane P; planes past Lt + 1 are never used: the load is
+    // clamped, not skipped
+    auto ld = [&](int P) -> uint64_t { return buf_load(spins, voff, wrap(min(P, Lt + 1)) * plane); };
+    // per-lane plane P (prologue): the plane offset goes in the vector offset
+    auto ld_lane = [&](int P) -> uint64_t { return buf_load(spins, voff + wrap(P) * plane, 0); };
 
     // window: w0..w5 = planes A-4 .. A+1, pf = A+2, A+3, nx = A+4, A+5
     uint64_t w0 = 0, w1 = 0, w2 = 0, w3, w4, w5, pf0, pf1, nx0, nx1;
-    w3 = ld(p - 1);
-    w4 = ld(p);
-    w5 = ld(p + 1);
-    pf0 = ld(p + 2);
-    pf1 = ld(p + 3);
+    w3 = ld_lane(p - 1);
+    w4 = ld_lane(p);
+    w5 = ld_lane(p + 1);
+    pf0 = ld_lane(min(p + 2, Lt + 1));
+    pf1 = ld_lane(min(p + 3, Lt + 1));
     uint64_t pu1 = ld(4);  // plane 2 sigma + 4 of the next segment for parity 0
     U4 G0, G1;
     uint32_t prevlast = 0;
@@ -349,8 +376,8 @@ __device__ __forceinline__ void sweep_teams(const ShapeDev& sh, const int cfg0, 
         // parity 0 holds colour 1 (just updated) and colour 0 (one segment
         // old) there, parity 1 colour 0 (two segments old) and colour 1
         const int P1 = 2 * sigma - 3, P2 = 2 * sigma - 2;
-        if (active && P1 >= 0) col[(size_t)wrap(P1) * L2] = p ? w0 : w1;
-        if (active && P2 >= 0) col[(size_t)wrap(P2) * L2] = p ? w1 : w2;
+        if (active && P1 >= 0) buf_store(p ? w0 : w1, spins, voff, wrap(P1) * plane);
+        if (active && P2 >= 0) buf_store(p ? w1 : w2, spins, voff, wrap(P2) * plane);
         if (active) {
             Y[(IS & 1) * H + hx] = p ? w2 : w4;
             X[((IS + 1) & 1) * H + hx] = p ? w5 : pf1;
@@ -397,11 +424,10 @@ k_sweep_stream(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __rest
 // Persistent sweep of every shape of a plan in one launch.  Work items
 // (shape, teams g, live teams, first configuration) are taken from a queue
 // in the order the host sorted them (longest first); a block sweeps the
-// item's configurations with g teams, then takes the next item.  Whether a
-// shape's energy is recounted (tempering due after this sweep, or the caller
-// asks for it) is read from the device counters, so one captured graph
-// serves every sweep.  The last block to finish rewinds the queue for the
-// next launch on the stream.
+// item's configurations with g teams, then takes the next item.  U is
+// recounted in every sweep (it is exact whichever sweep last counted it), so
+// one captured graph serves every sweep.  The last block to finish rewinds
+// the queue for the next launch on the stream.
 template <int kOcc>
 __global__ void __launch_bounds__(kMaxCols) __attribute__((amdgpu_waves_per_eu(kOcc)))
 k_sweep_batch(BatchArgs a) {
@@ -414,16 +440,12 @@ k_sweep_batch(BatchArgs a) {
         __syncthreads();
         if (it >= a.n_items) break;
         const uint64_t e = a.items[it];
-        const int s = (int)(e & 0xFFu), g = (int)((e >> 8) & 0xFFu), nlive = (int)((e >> 16) & 0xFFu);
-        const int cfg0 = (int)(e >> 32);
+        const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)e);
+        const int cfg0 = (int)__builtin_amdgcn_readfirstlane((uint32_t)(e >> 32));
+        const int s = (int)(lo & 0xFFu), g = (int)((lo >> 8) & 0xFFu), nlive = (int)((lo >> 16) & 0xFFu);
         const ShapeDev& sh = a.shapes[s];
-        const uint32_t t = a.ctr[s].t;
-        const bool due = sh.pt_every != 0 && ((t + 1) % sh.pt_every) == 0;
-        const int cols = stream_cols(sh);
-        if (due || a.force_energy)
-            sweep_teams<true>(sh, cfg0, g, nlive, cols, lds, a.key0, a.key1, t);
-        else
-            sweep_teams<false>(sh, cfg0, g, nlive, cols, lds, a.key0, a.key1, t);
+        const uint32_t t = __builtin_amdgcn_readfirstlane(a.ctr[s].t);
+        sweep_teams<true>(sh, cfg0, g, nlive, stream_cols(sh), lds, a.key0, a.key1, t);
     }
     if (threadIdx.x == 0) {
         __threadfence();

@@ -58,13 +58,15 @@ struct BatchQueue {
     uint32_t done;  // blocks that found the queue empty
 };
 
-// Arguments of the batched sweep and tempering kernels (device pointers).
+// Arguments of the batched sweep kernel.  The shapes travel by value in the
+// kernel arguments (scalar loads, provably uniform in the kernel).
+constexpr int kMaxBatchShapes = 8;
 struct BatchArgs {
-    const ShapeDev* shapes;  // [n_shapes]
+    ShapeDev shapes[kMaxBatchShapes];
     const uint64_t* items;   // shape | teams << 8 | live teams << 16 | first cfg << 32
     BatchQueue* q;
     const Counters* ctr;     // [n_shapes]
-    uint32_t n_items, key0, key1, force_energy;
+    uint32_t n_items, key0, key1, pad;
 };
 
 struct TemperBatchArgs {
@@ -106,6 +108,24 @@ __host__ __device__ inline U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, ui
 
 __host__ __device__ inline uint32_t ctr_word3(uint32_t j_global, uint32_t sid, uint32_t tag) {
     return (j_global & 0xFFFFFu) | ((sid & 0xFFu) << 20) | (tag << 28);
+}
+
+// 64x64 bit transpose across a wavefront: lane t holds row t (bit u is
+// element (t, u)); afterwards lane u holds column u (bit t is element (t, u)).
+// Level k swaps the off-diagonal k x k blocks of every 2k x 2k block.
+__device__ __forceinline__ uint64_t wave_transpose64(uint64_t v) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t masks[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull,
+                               0x00FF00FF00FF00FFull, 0x0F0F0F0F0F0F0F0Full,
+                               0x3333333333333333ull, 0x5555555555555555ull};
+#pragma unroll
+    for (int lv = 0; lv < 6; ++lv) {
+        const int k = 32 >> lv;
+        const uint64_t mk = masks[lv];
+        const uint64_t o = (uint64_t)__shfl_xor((long long)v, k, 64);
+        v = (lane & k) ? (((o >> k) & mk) | (v & ~mk)) : ((v & mk) | ((o & mk) << k));
+    }
+    return v;
 }
 
 }  // namespace tfim

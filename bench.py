@@ -156,10 +156,7 @@ def batched_leg(torch, args):
     stream = torch.cuda.current_stream()
     out = {"workload": w.name, "shapes": [[s.L, s.Ltau] for s in w.shapes],
            "updates_per_sweep": upd}
-    for name, sched in (("per_shape", tfim.TFIM_SCHED_PER_SHAPE), ("batched", tfim.TFIM_SCHED_BATCHED)):
-        plan = tfim.Plan(w.shapes, w.seed)
-        plan.init()
-        plan.set_schedule(sched)
+    def timed_sweeps(plan):
         plan.sweep(args.warmup)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
@@ -168,15 +165,33 @@ def batched_leg(torch, args):
         plan.sweep(args.c4_steps)
         e1.record(stream)
         torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / args.c4_steps
-        out[name] = {"ms_per_sweep": round(ms, 4), "spin_updates_per_ns": round(upd / (ms * 1e6), 1)}
-        if name == "batched":
-            t = plan.tuning()
-            out[name].update(threads=t["batch_threads"], blocks=t["batch_blocks"], items=t["batch_items"])
+        return e0.elapsed_time(e1) / args.c4_steps
+
+    for name in ("per_shape", "concurrent", "batched"):
+        plan = tfim.Plan(w.shapes, w.seed)
+        plan.init()
+        if name != "batched":
+            if name == "concurrent":
+                plan.set_schedule(tfim.TFIM_SCHED_CONCURRENT)
+            ms = timed_sweeps(plan)
+            out[name] = {"ms_per_sweep": round(ms, 4), "spin_updates_per_ns": round(upd / (ms * 1e6), 1)}
+        else:
+            plan.set_schedule(tfim.TFIM_SCHED_BATCHED)
+            geo = {}
+            for threads in (576, 640, 704, 768):
+                plan.set_batch(threads, 0)
+                t = plan.tuning()
+                geo[threads] = (timed_sweeps(plan), t["batch_blocks"], t["batch_items"])
+            best = min(geo, key=lambda k: geo[k][0])
+            ms = geo[best][0]
+            out[name] = {"ms_per_sweep": round(ms, 4), "spin_updates_per_ns": round(upd / (ms * 1e6), 1),
+                         "threads": best, "blocks": geo[best][1], "items": geo[best][2],
+                         "by_threads": {str(k): round(v[0], 4) for k, v in geo.items()}}
             done = plan.autotune(2)
             t = plan.tuning()
-            out["autotuned"] = {"schedule": "batched" if t["schedule"] == tfim.TFIM_SCHED_BATCHED
-                                else "per_shape", "variant": t["variant"],
+            names = {tfim.TFIM_SCHED_BATCHED: "batched", tfim.TFIM_SCHED_PER_SHAPE: "per_shape",
+                     tfim.TFIM_SCHED_CONCURRENT: "concurrent"}
+            out["autotuned"] = {"schedule": names[t["schedule"]], "variant": t["variant"],
                                 "threads": t["batch_threads"], "ms_per_sweep": round(t["ms_per_sweep"], 4),
                                 "trial_sweeps": done}
         log(f"bench: sizes x5 {name}: {ms:.3f} ms/sweep ({upd / (ms * 1e6):.1f} spin-updates/ns)")
@@ -184,6 +199,7 @@ def batched_leg(torch, args):
         del plan
         torch.cuda.empty_cache()
     out["batched_over_per_shape"] = round(out["per_shape"]["ms_per_sweep"] / out["batched"]["ms_per_sweep"], 3)
+    out["concurrent_over_per_shape"] = round(out["per_shape"]["ms_per_sweep"] / out["concurrent"]["ms_per_sweep"], 3)
     return out
 
 

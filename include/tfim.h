@@ -30,9 +30,10 @@
  *
  * Ownership: the caller allocates ONE device arena of the size reported by
  * tfim_plan_sizes and keeps it alive while the plan is bound; the library
- * never allocates or frees device memory of its own except HIP graph
- * objects.  The plan (an opaque host object) owns its copies of the shapes,
- * the threshold tables, the tuner choice and the graph cache.
+ * never allocates or frees device memory of its own (it creates HIP graph,
+ * stream and event objects only).  The plan (an opaque host object) owns
+ * its copies of the shapes, the threshold tables, the tuner choice and the
+ * graph cache.
  *
  * Errors: every call returns a tfim_status and never throws.  Argument
  * errors return before anything is enqueued and leave the state unchanged.
@@ -214,11 +215,19 @@ tfim_status tfim_set_state(tfim_plan *plan, uint32_t shape, const uint64_t *S_ho
  *   Whether a sweep recounts U is decided on the device from the counters. */
 #define TFIM_SCHED_BATCHED 0u
 #define TFIM_SCHED_PER_SHAPE 1u
+/* TFIM_SCHED_CONCURRENT: per sweep, the per-shape sweep launches run on
+ *   parallel branches of one HIP graph (fork from the plan's stream, one
+ *   branch per shape, join), then one tempering launch for all shapes and
+ *   one counter advance, as in the batched schedule.  Each shape keeps its
+ *   own workgroup size, and workgroups of different shapes may share a
+ *   compute unit.  Runs of up to 16 sweeps are captured once and replayed.
+ *   Needs a bound plan. */
+#define TFIM_SCHED_CONCURRENT 2u
 tfim_status tfim_set_schedule(tfim_plan *plan, uint32_t schedule);
 
 /* Geometry of the batched launch.  threads: threads per workgroup, a
  * multiple of 64, at least the largest shape's L^2 rounded up to 64, at
- * most 576.  blocks_per_cu: resident workgroups per compute unit (0 = as
+ * most 768.  blocks_per_cu: resident workgroups per compute unit (0 = as
  * many as fit).  A configuration needs the shape's L^2 (rounded up to 64)
  * threads, and a workgroup sweeps as many configurations of one shape at
  * once as fit in its threads and LDS.  Bound plan only; TFIM_EINVAL for a
@@ -235,14 +244,15 @@ typedef struct {
     double ms_per_sweep;           /* best trial of the last tfim_autotune, 0 if none */
 } tfim_tuning;
 
-/* Autotuner.  Under each candidate (per-shape schedule with streaming
- * variants 0 and 2; batched schedule with every workgroup size from the
- * smallest legal one up to 576 in steps of the largest shape's column
- * count) it runs one untimed sweep, then `sweeps_per_trial` sweeps timed
- * with HIP events, and keeps the fastest.  The trial sweeps are ordinary
- * sweeps of the chain and every candidate gives the same bits, so the
- * state afterwards equals that after the same number of tfim_sweep calls
- * of one sweep; *sweeps_done (may be NULL) returns that number.
+/* Autotuner.  Under each candidate (per-shape and concurrent schedules with
+ * streaming variants 0 and 2; batched schedule with every workgroup size
+ * from the largest team up to 768 threads that packs the shapes' teams
+ * differently)
+ * it runs one untimed sweep, then `sweeps_per_trial` sweeps timed with HIP
+ * events, and keeps the fastest.  The trial sweeps are ordinary sweeps of
+ * the chain and every candidate gives the same bits, so the state
+ * afterwards equals that after the same number of tfim_sweep calls of one
+ * sweep; *sweeps_done (may be NULL) returns that number.
  * cache_path (may be NULL): a choice stored there for the same device and
  * shapes is applied without trials (*sweeps_done = 0); a new choice is
  * written back (one line per key).  Synchronous.  Bound plan only. */

@@ -70,7 +70,11 @@ struct tfim_plan {
     int max_nk = 0, n_cu = 0;
     bool any_pt = false;
     hipStream_t cap_stream = nullptr;
-    std::map<uint32_t, hipGraphExec_t> graphs;  // sweeps per replay -> graph
+    std::vector<hipStream_t> side;                // concurrent schedule: one branch per shape
+    hipEvent_t ev_fork = nullptr;
+    std::vector<hipEvent_t> ev_join;
+    bool tables_up = false;                       // shape table and tempering ranges uploaded
+    std::map<uint32_t, hipGraphExec_t> graphs;  // (schedule, sweeps per replay) -> graph
     // HIP-event timing (tfim_set_timing): event pairs and the launches each covers
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used, ev_free;
@@ -373,6 +377,9 @@ void tfim_plan_destroy(tfim_plan* pl) {
     drop_events(pl);
     drop_graphs(pl);
     if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
+    for (auto st : pl->side) (void)hipStreamDestroy(st);
+    if (pl->ev_fork) (void)hipEventDestroy(pl->ev_fork);
+    for (auto ev : pl->ev_join) (void)hipEventDestroy(ev);
     delete pl;
 }
 
@@ -392,6 +399,7 @@ tfim_status tfim_bind(tfim_plan* pl, void* arena, size_t bytes, void* stream) {
     pl->poisoned = false;
     drop_graphs(pl);
     pl->batch_threads = pl->batch_bpc = pl->batch_blocks = 0;
+    pl->tables_up = false;
     pl->schedule = TFIM_SCHED_PER_SHAPE;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -554,7 +562,7 @@ static hipError_t enqueue_sweep(tfim_plan* pl, bool last) {
 // Batched schedule
 // ---------------------------------------------------------------------------
 constexpr uint32_t kGraphSweeps = 16;        // sweeps captured per graph
-constexpr uint32_t kMaxBatchThreads = 576;   // launch bound of the batched kernel
+constexpr uint32_t kMaxBatchThreads = 768;   // launch bound of the batched kernel
 constexpr size_t kLdsLimit = 160 * 1024 - 256;
 
 static tfim::BatchArgs batch_args(const tfim_plan* pl) {
@@ -580,6 +588,56 @@ static tfim::TemperBatchArgs temper_args(const tfim_plan* pl) {
     return a;
 }
 
+// The device shape table and the first tempering block of each shape, used
+// by the all-shape tempering and counter-advance launches of the batched and
+// concurrent schedules.
+static tfim_status upload_tables(tfim_plan* pl) {
+    const int ns = (int)pl->shapes.size();
+    std::vector<tfim::ShapeDev> devs(ns);
+    std::vector<uint32_t> first(ns + 1, 0);
+    int max_nk = 0;
+    bool any_pt = false;
+    for (int i = 0; i < ns; ++i) {
+        devs[i] = dev_of(pl, i);
+        first[i + 1] = first[i] + (uint32_t)(devs[i].R * devs[i].W);
+        max_nk = std::max(max_nk, devs[i].nk);
+        any_pt = any_pt || devs[i].pt_every != 0;
+    }
+    hipError_t e = hipMemcpyAsync(pl->arena + pl->oBatch, devs.data(), sizeof(tfim::ShapeDev) * ns,
+                                  hipMemcpyHostToDevice, pl->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(pl->arena + pl->oFirst, first.data(), 4 * first.size(), hipMemcpyHostToDevice,
+                           pl->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(pl->stream);
+    if (e != hipSuccess) return check_hip(pl, e, "shape table upload");
+    pl->temper_blocks = first[ns];
+    pl->max_nk = max_nk;
+    pl->any_pt = any_pt;
+    pl->tables_up = true;
+    return TFIM_OK;
+}
+
+// Branch streams and fork/join events of the concurrent schedule, and the
+// kernel attributes its captured launches need.
+static tfim_status concurrent_setup(tfim_plan* pl) {
+    const int ns = (int)pl->shapes.size();
+    hipError_t e = hipSuccess;
+    while ((int)pl->side.size() < ns && e == hipSuccess) {
+        hipStream_t st = nullptr;
+        e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (e == hipSuccess) pl->side.push_back(st);
+    }
+    if (e == hipSuccess && !pl->ev_fork) e = hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming);
+    while (e == hipSuccess && (int)pl->ev_join.size() < ns) {
+        hipEvent_t ev = nullptr;
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess) pl->ev_join.push_back(ev);
+    }
+    for (int i = 0; i < ns && e == hipSuccess; ++i) e = tfim::prepare_sweep(dev_of(pl, i), pl->variant, true);
+    if (e != hipSuccess) return check_hip(pl, e, "concurrent setup");
+    return pl->tables_up ? TFIM_OK : upload_tables(pl);
+}
+
 // Work items and geometry of the batched launch; uploads the shape table,
 // the tempering block ranges and the items, rewinds the queue.
 static tfim_status batch_setup(tfim_plan* pl, uint32_t threads, uint32_t bpc) {
@@ -594,7 +652,7 @@ static tfim_status batch_setup(tfim_plan* pl, uint32_t threads, uint32_t bpc) {
     }
     if (threads == 0) threads = (uint32_t)maxcols;
     if (threads % 64 || threads < (uint32_t)maxcols || threads > kMaxBatchThreads)
-        return fail(TFIM_EINVAL, "batch threads must be a multiple of 64 in [largest L^2 rounded to 64, 576]");
+        return fail(TFIM_EINVAL, "batch threads must be a multiple of 64 in [largest L^2 rounded to 64, 768]");
     struct Item { uint64_t e; int Lt; size_t order; };
     std::vector<Item> it;
     size_t lds = 0;
@@ -630,14 +688,10 @@ static tfim_status batch_setup(tfim_plan* pl, uint32_t threads, uint32_t bpc) {
     if (bpc) per_cu = std::min<int>(per_cu, (int)bpc);
     std::vector<uint64_t> items(it.size());
     for (size_t k = 0; k < it.size(); ++k) items[k] = it[k].e;
-    e = hipMemcpyAsync(pl->arena + pl->oBatch, devs.data(), sizeof(tfim::ShapeDev) * ns,
-                       hipMemcpyHostToDevice, pl->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(pl->arena + pl->oFirst, first.data(), 4 * first.size(), hipMemcpyHostToDevice,
-                           pl->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(pl->arena + pl->oItems, items.data(), 8 * items.size(), hipMemcpyHostToDevice,
-                           pl->stream);
+    tfim_status ts = upload_tables(pl);
+    if (ts != TFIM_OK) return ts;
+    e = hipMemcpyAsync(pl->arena + pl->oItems, items.data(), 8 * items.size(), hipMemcpyHostToDevice,
+                       pl->stream);
     if (e == hipSuccess) e = hipMemsetAsync(pl->arena + pl->oQueue, 0, sizeof(tfim::BatchQueue), pl->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(pl->stream);
     if (e != hipSuccess) return check_hip(pl, e, "batch upload");
@@ -647,15 +701,17 @@ static tfim_status batch_setup(tfim_plan* pl, uint32_t threads, uint32_t bpc) {
     pl->batch_bpc = bpc;
     pl->batch_blocks = (uint32_t)std::min<size_t>((size_t)pl->n_cu * per_cu, pl->items.size());
     pl->batch_lds = lds;
-    pl->temper_blocks = first[ns];
-    pl->max_nk = max_nk;
-    pl->any_pt = any_pt;
+    (void)first;
+    (void)max_nk;
+    (void)any_pt;
     return TFIM_OK;
 }
 
-// The graph of g batched sweeps (captured once on the private stream).
+// The graph of g sweeps of the batched or concurrent schedule (captured
+// once on the private stream).
 static hipError_t batch_graph(tfim_plan* pl, uint32_t g, hipGraphExec_t* out) {
-    auto f = pl->graphs.find(g);
+    const uint32_t key = g + 1000u * pl->schedule + 100000u * (uint32_t)pl->variant;
+    auto f = pl->graphs.find(key);
     if (f != pl->graphs.end()) {
         *out = f->second;
         return hipSuccess;
@@ -665,9 +721,23 @@ static hipError_t batch_graph(tfim_plan* pl, uint32_t g, hipGraphExec_t* out) {
     hipError_t e = hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
     hipError_t le = hipSuccess;
+    const int ns = (int)pl->shapes.size();
     for (uint32_t s = 0; s < g && le == hipSuccess; ++s) {
-        le = tfim::launch_sweep_batch(a, 1, (int)pl->batch_blocks, (int)pl->batch_threads, pl->batch_lds,
-                                      pl->cap_stream);
+        if (pl->schedule == TFIM_SCHED_CONCURRENT) {
+            // fork: every shape's sweep on its own branch; join before tempering
+            le = hipEventRecord(pl->ev_fork, pl->cap_stream);
+            for (int i = 0; i < ns && le == hipSuccess; ++i) {
+                le = hipStreamWaitEvent(pl->side[i], pl->ev_fork, 0);
+                if (le == hipSuccess)
+                    le = tfim::launch_sweep(dev_of(pl, i), pl->seed, counters_of(pl, i), pl->variant, true,
+                                            pl->side[i]);
+                if (le == hipSuccess) le = hipEventRecord(pl->ev_join[i], pl->side[i]);
+                if (le == hipSuccess) le = hipStreamWaitEvent(pl->cap_stream, pl->ev_join[i], 0);
+            }
+        } else {
+            le = tfim::launch_sweep_batch(a, 1, (int)pl->batch_blocks, (int)pl->batch_threads, pl->batch_lds,
+                                          pl->cap_stream);
+        }
         if (le == hipSuccess && pl->any_pt)
             le = tfim::launch_temper_batch(ta, (int)pl->temper_blocks, pl->max_nk, pl->cap_stream);
         if (le == hipSuccess) le = tfim::launch_advance_batch(ta, pl->cap_stream);
@@ -682,7 +752,7 @@ static hipError_t batch_graph(tfim_plan* pl, uint32_t g, hipGraphExec_t* out) {
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return e;
-    pl->graphs[g] = exec;
+    pl->graphs[key] = exec;
     *out = exec;
     return hipSuccess;
 }
@@ -720,7 +790,7 @@ static tfim_status sweep_impl(tfim_plan* pl, uint64_t n) {
         }
     };
     hipError_t e = hipSuccess;
-    if (pl->schedule == TFIM_SCHED_BATCHED) {
+    if (pl->schedule == TFIM_SCHED_BATCHED || pl->schedule == TFIM_SCHED_CONCURRENT) {
         e = enqueue_batched(pl, n);
         if (e == hipSuccess) advance(n);
     } else {
@@ -914,12 +984,18 @@ tfim_status tfim_set_variant(tfim_plan* pl, uint32_t variant) {
 
 tfim_status tfim_set_schedule(tfim_plan* pl, uint32_t schedule) {
     if (!pl) return fail(TFIM_EINVAL, "null plan");
-    if (schedule != TFIM_SCHED_PER_SHAPE && schedule != TFIM_SCHED_BATCHED)
+    if (schedule != TFIM_SCHED_PER_SHAPE && schedule != TFIM_SCHED_BATCHED &&
+        schedule != TFIM_SCHED_CONCURRENT)
         return fail(TFIM_EINVAL, "unknown schedule");
     if (schedule == TFIM_SCHED_BATCHED) {
         tfim_status st = usable(pl);
         if (st != TFIM_OK) return st;
         if (pl->batch_threads == 0 && (st = batch_setup(pl, 0, 0)) != TFIM_OK) return st;
+    }
+    if (schedule == TFIM_SCHED_CONCURRENT) {
+        tfim_status st = usable(pl);
+        if (st != TFIM_OK) return st;
+        if ((st = concurrent_setup(pl)) != TFIM_OK) return st;
     }
     pl->schedule = schedule;
     return TFIM_OK;
@@ -930,6 +1006,8 @@ tfim_status tfim_set_batch(tfim_plan* pl, uint32_t threads, uint32_t blocks_per_
     if (st != TFIM_OK) return st;
     return batch_setup(pl, threads, blocks_per_cu);
 }
+
+}  // extern "C"
 
 namespace {
 
@@ -1010,15 +1088,16 @@ bool cache_store(const char* path, const std::string& key, const Choice& c) {
 
 }  // namespace
 
+extern "C" {
+
 static tfim_status apply_choice(tfim_plan* pl, const Choice& c) {
-    if (c.schedule == TFIM_SCHED_BATCHED) {
-        tfim_status st = batch_setup(pl, c.threads, c.bpc);
-        if (st != TFIM_OK) return st;
-    } else if (c.variant >= (uint32_t)tfim::sweep_variants()) {
-        return fail(TFIM_EINVAL, "unknown sweep variant");
-    }
-    pl->schedule = c.schedule;
+    if (c.variant >= (uint32_t)tfim::sweep_variants()) return fail(TFIM_EINVAL, "unknown sweep variant");
     pl->variant = (int)c.variant;
+    tfim_status st = TFIM_OK;
+    if (c.schedule == TFIM_SCHED_BATCHED) st = batch_setup(pl, c.threads, c.bpc);
+    else if (c.schedule == TFIM_SCHED_CONCURRENT) st = concurrent_setup(pl);
+    if (st != TFIM_OK) return st;
+    pl->schedule = c.schedule;
     return TFIM_OK;
 }
 
@@ -1045,20 +1124,32 @@ tfim_status tfim_autotune(tfim_plan* pl, uint32_t sweeps_per_trial, const char* 
         stream_all = stream_all && tfim::sweep_stream_ok(d);
         maxcols = std::max(maxcols, tfim::sweep_stream_cols(d));
     }
-    for (uint32_t v : {0u, 2u}) {
-        Choice p;
-        p.schedule = TFIM_SCHED_PER_SHAPE;
-        p.variant = v;
-        cand.push_back(p);
-        if (!stream_all) break;  // the other variants fall back to the same kernel
+    for (uint32_t sched : {(uint32_t)TFIM_SCHED_PER_SHAPE, (uint32_t)TFIM_SCHED_CONCURRENT}) {
+        if (sched == TFIM_SCHED_CONCURRENT && pl->shapes.size() < 2) continue;  // same as per-shape
+        for (uint32_t v : {0u, 2u}) {
+            Choice p;
+            p.schedule = sched;
+            p.variant = v;
+            cand.push_back(p);
+            if (!stream_all) break;  // the other variants fall back to the same kernel
+        }
     }
-    if (stream_all)
-        for (uint32_t t = (uint32_t)maxcols; t <= kMaxBatchThreads; t += (uint32_t)maxcols) {
+    if (stream_all) {
+        // workgroup sizes from the largest team upwards: one per distinct
+        // packing of the shapes' teams
+        std::vector<std::vector<int>> seen;
+        for (uint32_t t = (uint32_t)maxcols; t <= kMaxBatchThreads; t += 64) {
+            std::vector<int> pack;
+            for (int i = 0; i < (int)pl->shapes.size(); ++i)
+                pack.push_back((int)t / tfim::sweep_stream_cols(dev_of(pl, i)));
+            if (std::find(seen.begin(), seen.end(), pack) != seen.end()) continue;
+            seen.push_back(pack);
             Choice b;
             b.schedule = TFIM_SCHED_BATCHED;
             b.threads = t;
             cand.push_back(b);
         }
+    }
     const bool timing = pl->timing;
     pl->timing = false;
     hipEvent_t e0 = nullptr, e1 = nullptr;

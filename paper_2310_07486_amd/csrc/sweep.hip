@@ -425,6 +425,12 @@ hipError_t launch_sweep(const ShapeDev& sh, uint64_t seed, const Counters* ctr, 
     return hipGetLastError();
 }
 
+hipError_t prepare_sweep(const ShapeDev& sh, int variant, bool energy) {
+    if ((variant == 0 || variant == 2) && sweep_stream_ok(sh))
+        return prepare_sweep_stream(sh, energy, variant == 2 ? 5 : 1);
+    return hipSuccess;  // the chunked kernel stays within 64 KiB of LDS
+}
+
 hipError_t launch_energy(const ShapeDev& sh, hipStream_t st) {
     const int nblk = sh.R * sh.nk * sh.W;
     hipLaunchKernelGGL(k_energy, dim3(nblk), dim3(block_for(sh)), 64 * 4, st, sh);

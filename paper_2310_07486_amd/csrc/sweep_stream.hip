@@ -39,6 +39,7 @@ namespace tfim {
 namespace {
 
 constexpr int kMaxCols = 576;  // one thread per column, L <= 24
+constexpr int kMaxBatchThreads = 768;  // 12 waves: 3 per SIMD at up to 168 VGPRs
 
 // Raw buffer access to one configuration's spin words: the descriptor covers
 // exactly its bytes (0 for a team without a configuration: loads return 0
@@ -229,7 +230,9 @@ __host__ __device__ inline int stream_cols(const ShapeDev& sh) { return ((sh.L2 
 // and threads past the last team run the same barriers and touch no global
 // memory.  Segment sigma updates the colour-0 site at plane A = 2 sigma + p
 // and the colour-1 site of the previous step at A - 3.
-template <bool kE>
+// kPacked = false: one team filling the workgroup (g = nlive = 1,
+// cols = blockDim.x), so every wave is a live member.
+template <bool kE, bool kPacked>
 __device__ __forceinline__ void sweep_teams(const ShapeDev& sh, const int cfg0, const int g,
                                             const int nlive, const int cols, uint64_t* lds,
                                             const uint32_t key0, const uint32_t key1,
@@ -238,11 +241,11 @@ __device__ __forceinline__ void sweep_teams(const ShapeDev& sh, const int cfg0, 
     const int nb0 = sh.bnb[0] + 1, nb1 = sh.bnb[1] + 1, nb2 = sh.bnb[2] + 1;
     const int nbt = nb0 + nb1 + nb2;
     const int tid = threadIdx.x, nthr = blockDim.x;
-    const int team = __builtin_amdgcn_readfirstlane(tid / cols);  // cols % 64 == 0: wave-uniform
+    const int team = kPacked ? __builtin_amdgcn_readfirstlane(tid / cols) : 0;  // wave-uniform
     const int ttid = tid - team * cols;
-    const bool member = team < g;
+    const bool member = !kPacked || team < g;
     const int lteam = member ? team : g - 1;
-    const bool live = member && team < nlive;
+    const bool live = !kPacked || (member && team < nlive);
     const bool active = live && ttid < L2;
 
     uint32_t* TT = (uint32_t*)lds;
@@ -340,9 +343,14 @@ __device__ __forceinline__ void sweep_teams(const ShapeDev& sh, const int cfg0, 
     if (active) X[hx] = p ? w3 : w5;  // X(0)
     __syncthreads();
 
-    // one segment; IS = sigma & 3 is a compile-time constant
+    // one segment; IS = sigma & 3 is a compile-time constant.  Waves outside
+    // every team (member is wave-uniform) only take part in the barrier.
     auto segment = [&](const int sigma, const auto ISc, const bool do_c0, const bool do_c1) {
         constexpr int IS = decltype(ISc)::value;
+        if (!member) {
+            __syncthreads();
+            return;
+        }
         const int A = 2 * sigma + p;
         // every load instruction reads whole planes 2 sigma + 5 and 2 sigma + 6
         // (all columns, full cache lines); a thread keeps the two planes of
@@ -396,16 +404,18 @@ __device__ __forceinline__ void sweep_teams(const ShapeDev& sh, const int cfg0, 
         segment(s0 + 1, I1{}, true, gq > 0);
         segment(s0 + 2, I2{}, true, true);
         segment(s0 + 3, I3{}, true, true);
-        if (kE) {
+        if (kE && member) {
             add_deep(deep, dstride, sm);
-            if ((gq % kFlushMacros) == kFlushMacros - 1) flush_deep(deep, dstride, Ublk, member);
+            if ((gq % kFlushMacros) == kFlushMacros - 1) flush_deep(deep, dstride, Ublk, true);
         }
     }
     segment(half, I0{}, false, true);      // colour 1, step half-1
     segment(half + 1, I1{}, false, true);  // colour 1, step half == step 0 (tau wrap)
     if (kE) {
-        add_deep(deep, dstride, sm);
-        flush_deep(deep, dstride, Ublk, member);
+        if (member) {
+            add_deep(deep, dstride, sm);
+            flush_deep(deep, dstride, Ublk, true);
+        }
         __syncthreads();
         if (live && ttid < 64) sh.U[((size_t)r * W * 64 + (size_t)j * 64 + ttid) * nk + w] = Ublk[ttid];
     }
@@ -418,7 +428,7 @@ template <bool kE, int kOcc>
 __global__ void __launch_bounds__(kMaxCols) __attribute__((amdgpu_waves_per_eu(kOcc)))
 k_sweep_stream(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __restrict__ ctr) {
     extern __shared__ uint64_t lds[];
-    sweep_teams<kE>(sh, (int)blockIdx.x, 1, 1, (int)blockDim.x, lds, key0, key1, ctr->t);
+    sweep_teams<kE, false>(sh, (int)blockIdx.x, 1, 1, (int)blockDim.x, lds, key0, key1, ctr->t);
 }
 
 // Persistent sweep of every shape of a plan in one launch.  Work items
@@ -429,7 +439,7 @@ k_sweep_stream(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __rest
 // one captured graph serves every sweep.  The last block to finish rewinds
 // the queue for the next launch on the stream.
 template <int kOcc>
-__global__ void __launch_bounds__(kMaxCols) __attribute__((amdgpu_waves_per_eu(kOcc)))
+__global__ void __launch_bounds__(kMaxBatchThreads) __attribute__((amdgpu_waves_per_eu(kOcc)))
 k_sweep_batch(BatchArgs a) {
     extern __shared__ uint64_t lds[];
     __shared__ uint32_t s_item;
@@ -445,7 +455,7 @@ k_sweep_batch(BatchArgs a) {
         const int s = (int)(lo & 0xFFu), g = (int)((lo >> 8) & 0xFFu), nlive = (int)((lo >> 16) & 0xFFu);
         const ShapeDev& sh = a.shapes[s];
         const uint32_t t = __builtin_amdgcn_readfirstlane(a.ctr[s].t);
-        sweep_teams<true>(sh, cfg0, g, nlive, stream_cols(sh), lds, a.key0, a.key1, t);
+        sweep_teams<true, true>(sh, cfg0, g, nlive, stream_cols(sh), lds, a.key0, a.key1, t);
     }
     if (threadIdx.x == 0) {
         __threadfence();
@@ -479,12 +489,23 @@ static hipError_t allow_lds(const void* fn, size_t bytes, size_t& done) {
 }
 
 template <bool kE, int kOcc>
+static hipError_t prepare_one(const ShapeDev& sh) {
+    static size_t lds_set = 0;
+    return allow_lds((const void*)k_sweep_stream<kE, kOcc>, sweep_stream_lds_bytes(sh, 1, stream_cols(sh)),
+                     lds_set);
+}
+
+hipError_t prepare_sweep_stream(const ShapeDev& sh, bool energy, int occ) {
+    if (occ >= 5) return energy ? prepare_one<true, 5>(sh) : prepare_one<false, 5>(sh);
+    return energy ? prepare_one<true, 1>(sh) : prepare_one<false, 1>(sh);
+}
+
+template <bool kE, int kOcc>
 static hipError_t launch_one(const ShapeDev& sh, uint64_t seed, const Counters* ctr, hipStream_t st) {
     const int nblk = sh.R * sh.nk * sh.W;
     const int threads = stream_cols(sh);
     const size_t lds = sweep_stream_lds_bytes(sh, 1, threads);
-    static size_t lds_set = 0;
-    hipError_t e = allow_lds((const void*)k_sweep_stream<kE, kOcc>, lds, lds_set);
+    hipError_t e = prepare_one<kE, kOcc>(sh);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_sweep_stream<kE, kOcc>), dim3(nblk), dim3(threads), lds, st, sh,
                        (uint32_t)seed, (uint32_t)(seed >> 32), ctr);

@@ -144,6 +144,10 @@ hipError_t launch_sweep(const ShapeDev& sh, uint64_t seed, const Counters* ctr, 
                         bool energy, hipStream_t st);
 hipError_t launch_sweep_stream(const ShapeDev& sh, uint64_t seed, const Counters* ctr,
                                bool energy, int occ, hipStream_t st);
+// Kernel attributes a later launch of this shape and variant needs (dynamic
+// LDS above 64 KiB), set outside any stream capture.
+hipError_t prepare_sweep(const ShapeDev& sh, int variant, bool energy);
+hipError_t prepare_sweep_stream(const ShapeDev& sh, bool energy, int occ);
 bool sweep_stream_ok(const ShapeDev& sh);
 // LDS of a streaming-sweep block of `teams` configurations and `threads`
 // threads; threads per configuration (L^2 rounded up to whole waves).

@@ -29,6 +29,7 @@ TFIM_MEASURE_BUCKETS = 2
 TFIM_MEASURE_ENERGY = 3
 TFIM_SCHED_BATCHED = 0
 TFIM_SCHED_PER_SHAPE = 1
+TFIM_SCHED_CONCURRENT = 2
 
 # Every symbol include/tfim.h declares.
 SYMBOLS = [

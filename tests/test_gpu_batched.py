@@ -53,15 +53,18 @@ def _drive(plan):
     plan.sync()
 
 
-def test_batched_equals_per_shape_and_oracle():
+@pytest.mark.parametrize("schedule", [tfim.TFIM_SCHED_BATCHED, tfim.TFIM_SCHED_CONCURRENT])
+def test_batched_equals_per_shape_and_oracle(schedule):
     seed = 321
-    _say("batched vs per-shape: 4 shapes, 29 sweeps + 1 explicit tempering step")
+    _say(f"schedule {schedule} vs per-shape: 4 shapes, 29 sweeps + 1 explicit tempering step")
     ref = tfim.Plan(SHAPES, seed)
     _drive(ref)
     bat = tfim.Plan(SHAPES, seed)
-    bat.set_schedule(tfim.TFIM_SCHED_BATCHED)
+    bat.set_schedule(schedule)
     t = bat.tuning()
-    assert t["schedule"] == tfim.TFIM_SCHED_BATCHED and t["batch_threads"] == 256
+    assert t["schedule"] == schedule
+    if schedule == tfim.TFIM_SCHED_BATCHED:
+        assert t["batch_threads"] == 256
     _drive(bat)
     _same(_state(ref, len(SHAPES)), _state(bat, len(SHAPES)))
     # and the oracle on a few lanes of two shapes
@@ -79,7 +82,7 @@ def test_batched_equals_per_shape_and_oracle():
         assert np.array_equal(kidx[:, lanes], ch.kidx) and np.array_equal(U[:, lanes], ch.U)
 
 
-@pytest.mark.parametrize("threads,bpc", [(256, 1), (320, 0), (512, 0), (576, 2)])
+@pytest.mark.parametrize("threads,bpc", [(256, 1), (320, 0), (512, 0), (576, 2), (768, 0)])
 def test_batch_geometry_does_not_change_results(threads, bpc):
     seed = 99
     _say(f"batched geometry threads={threads} blocks_per_cu={bpc}")
@@ -95,15 +98,16 @@ def test_batch_geometry_does_not_change_results(threads, bpc):
     _same(_state(ref, len(SHAPES)), _state(bat, len(SHAPES)))
 
 
-def test_graph_replays_and_timing():
+@pytest.mark.parametrize("schedule", [tfim.TFIM_SCHED_BATCHED, tfim.TFIM_SCHED_CONCURRENT])
+def test_graph_replays_and_timing(schedule):
     seed = 5
-    _say("batched graph replays: 10 x 3 sweeps")
+    _say(f"schedule {schedule} graph replays: 10 x 3 sweeps")
     ref = tfim.Plan(SHAPES[:2], seed)
     ref.init()
     ref.sweep(30)
     bat = tfim.Plan(SHAPES[:2], seed)
     bat.init()
-    bat.set_schedule(tfim.TFIM_SCHED_BATCHED)
+    bat.set_schedule(schedule)
     bat.set_timing(True)
     bat.get_timing()
     for _ in range(10):

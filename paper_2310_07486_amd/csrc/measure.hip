@@ -221,47 +221,69 @@ __global__ void __launch_bounds__(256) k_gram_mfma(ShapeDev sh, int cfg0, int nc
 // Q tiles: trQ, sum Q^2, sum Q^4 for every pair.
 // ---------------------------------------------------------------------------
 template <int RR>
-__global__ void __launch_bounds__(256) k_overlap_mfma(ShapeDev sh, int cfg0, int ncfg) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_overlap_mfma(ShapeDev sh, int cfg0, int ncfg) {
     constexpr int PP = RR * (RR - 1) / 2;
     extern __shared__ __align__(16) uint8_t smem[];
     uint8_t* Al = smem;
     uint8_t* Bl = smem + RR * 64 * kRowPitch;
     int* mA = (int*)(Bl + RR * 64 * kRowPitch);
     int* mB = mA + RR * 64;
-    unsigned long long* red = (unsigned long long*)(mB + RR * 64);  // [PP][3]
+    unsigned long long* red = (unsigned long long*)(mB + RR * 64);  // [PP][2]: trQ, sum Q^4
     const int L2 = sh.L2, Lt = sh.Lt;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int wx = wv & 1, wy = wv >> 1;
     const int ntt = (Lt + 63) / 64;
-    for (int e = tid; e < PP * 3; e += 256) red[e] = 0;
+    constexpr int kRows = 2 * RR * 64;        // operand rows of one K chunk (A and B)
+    constexpr int kPer = (kRows + 255) / 256;  // rows per thread
+    for (int e = tid; e < PP * 2; e += 256) red[e] = 0;
     for (int cfg = cfg0 + blockIdx.x; cfg < cfg0 + ncfg; cfg += gridDim.x) {
-        long long s2[PP], s4[PP], tr[PP];
+        long long s4[PP], tr[PP];
 #pragma unroll
-        for (int p = 0; p < PP; ++p) s2[p] = s4[p] = tr[p] = 0;
+        for (int p = 0; p < PP; ++p) s4[p] = tr[p] = 0;
         for (int tt = 0; tt < ntt * ntt; ++tt) {
             const int T = tt / ntt, T2 = tt % ntt;
             const bool diag = T == T2;
             const uint8_t* Bsrc = diag ? Al : Bl;
             const int* mBsrc = diag ? mA : mB;
+            const int nrows = (diag ? 1 : 2) * RR * 64;
+            // operand rows of K chunk g: side (A: tile T, B: tile T2), replica, tau
+            auto fetch = [&](int g, uint64_t (&v)[kPer]) {
+                const uint64_t vm = low_bits(L2 - 64 * g);
+#pragma unroll
+                for (int k = 0; k < kPer; ++k) {
+                    const int e = tid + 256 * k;
+                    v[k] = 0;
+                    if (e < nrows) {
+                        const int side = e / (RR * 64), rr = (e / 64) % RR, row = e & 63;
+                        const int tau = 64 * (side ? T2 : T) + row;
+                        const size_t m = (size_t)cfg * RR + rr;
+                        v[k] = tau < Lt ? (sh.Px[(m * sh.nx + g) * Lt + tau] & vm) : 0ull;
+                    }
+                }
+            };
             v16i acc[PP];
 #pragma unroll
             for (int p = 0; p < PP; ++p)
 #pragma unroll
                 for (int q = 0; q < 16; ++q) acc[p][q] = 0;
+            uint64_t vn[kPer];
+            fetch(0, vn);
             __syncthreads();  // previous tile's epilogue has read mA, mB
             for (int e = tid; e < 2 * RR * 64; e += 256) mA[e] = 0;
             for (int g = 0; g < sh.nx; ++g) {
                 __syncthreads();
-                const uint64_t vm = low_bits(L2 - 64 * g);
-                for (int e = tid; e < (diag ? 1 : 2) * RR * 64; e += 256) {
-                    const int side = e / (RR * 64), rr = (e / 64) % RR, row = e & 63;
-                    const int tau = 64 * (side ? T2 : T) + row;
-                    const size_t m = (size_t)cfg * RR + rr;
-                    const uint64_t v = tau < Lt ? (sh.Px[(m * sh.nx + g) * Lt + tau] & vm) : 0ull;
-                    (side ? mB : mA)[rr * 64 + row] += __popcll(v);
-                    unpack64(v, (side ? Bl : Al) + (rr * 64 + row) * kRowPitch);
+#pragma unroll
+                for (int k = 0; k < kPer; ++k) {
+                    const int e = tid + 256 * k;
+                    if (e < nrows) {
+                        const int side = e / (RR * 64), rr = (e / 64) % RR, row = e & 63;
+                        (side ? mB : mA)[rr * 64 + row] += __popcll(vn[k]);
+                        unpack64(vn[k], (side ? Bl : Al) + (rr * 64 + row) * kRowPitch);
+                    }
                 }
                 __syncthreads();
+                if (g + 1 < sh.nx) fetch(g + 1, vn);  // in flight during the MFMAs
 #pragma unroll
                 for (int ks = 0; ks < 2; ++ks) {
                     const int ko = 32 * ks + 16 * (lane >> 5);
@@ -281,24 +303,30 @@ __global__ void __launch_bounds__(256) k_overlap_mfma(ShapeDev sh, int cfg0, int
                 }
             }
             __syncthreads();
+            // epilogue: Q = L^2 - 2 (m_tau + m_tau') + 4 B^aT B^b; |Q| <= L^2 fits
+            // 24-bit multiplies, Q^2 < 2^19, Q^4 < 2^38
             const int col = 32 * wy + (lane & 31);
             const int tau2 = 64 * T2 + col;
+            int cc[RR];
+#pragma unroll
+            for (int rb = 0; rb < RR; ++rb) cc[rb] = -2 * mBsrc[rb * 64 + col];
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
                 const int row = 32 * wx + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
                 const int tau = 64 * T + row;
                 if (tau >= Lt || tau2 >= Lt) continue;
+                int cr[RR];
+#pragma unroll
+                for (int ra = 0; ra < RR; ++ra) cr[ra] = L2 - 2 * mA[ra * 64 + row];
                 int p = 0;
 #pragma unroll
                 for (int ra = 0; ra < RR; ++ra)
 #pragma unroll
                     for (int rb = ra + 1; rb < RR; ++rb, ++p) {
-                        const long long qv = (long long)L2 - 2ll * (mA[ra * 64 + row] + mBsrc[rb * 64 + col]) +
-                                             4ll * acc[p][q];
-                        const long long q2 = qv * qv;
-                        s2[p] += q2;
-                        s4[p] += q2 * q2;
-                        if (tau == tau2) tr[p] += qv;
+                        const int qv = cr[ra] + cc[rb] + 4 * acc[p][q];
+                        const unsigned q2 = (unsigned)__mul24(qv, qv);
+                        s4[p] += (long long)((unsigned long long)q2 * q2);
+                        if (diag && tau == tau2) tr[p] += qv;
                     }
             }
         }
@@ -307,7 +335,6 @@ __global__ void __launch_bounds__(256) k_overlap_mfma(ShapeDev sh, int cfg0, int
         for (int p = 0; p < PP; ++p) {
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) {
-                s2[p] += __shfl_xor(s2[p], off, 64);
                 s4[p] += __shfl_xor(s4[p], off, 64);
                 tr[p] += __shfl_xor(tr[p], off, 64);
             }
@@ -315,19 +342,27 @@ __global__ void __launch_bounds__(256) k_overlap_mfma(ShapeDev sh, int cfg0, int
         if (lane == 0) {
 #pragma unroll
             for (int p = 0; p < PP; ++p) {
-                atomicAdd(&red[p * 3 + 0], (unsigned long long)tr[p]);
-                atomicAdd(&red[p * 3 + 1], (unsigned long long)s2[p]);
-                atomicAdd(&red[p * 3 + 2], (unsigned long long)s4[p]);
+                atomicAdd(&red[p * 2 + 0], (unsigned long long)tr[p]);
+                atomicAdd(&red[p * 2 + 1], (unsigned long long)s4[p]);
             }
         }
         __syncthreads();
+        // sum Q^2 = sum_xy G^a_xy G^b_xy = sum_d D_x[d]: the Gram kernel's
+        // buckets of this configuration are complete (earlier launch)
         const int rl = 2 * sh.L + 3;
         for (int e = tid; e < PP * 3; e += 256) {
             const int p = e / 3, k = e % 3;
-            atomicAdd((unsigned long long*)&sh.rec[((size_t)cfg * PP + p) * rl + 2 * sh.L + k], red[e]);
-            red[e] = 0;
+            int64_t* rp = sh.rec + ((size_t)cfg * PP + p) * rl;
+            if (k == 1) {
+                int64_t q2 = 0;
+                for (int d = 0; d < sh.L; ++d) q2 += rp[d];
+                rp[2 * sh.L + 1] = q2;
+            } else {
+                rp[2 * sh.L + k] = (int64_t)red[p * 2 + (k == 0 ? 0 : 1)];
+            }
         }
         __syncthreads();
+        for (int e = tid; e < PP * 2; e += 256) red[e] = 0;
     }
 }
 

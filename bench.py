@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_WORD = 16  # each spin word read once and written once per sweep
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_stream_L24_Lt2048_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_L24_Lt2048_traffic.json")
 SWEEP_SOURCE = os.path.join(ROOT, "paper_2310_07486_amd", "csrc", "sweep_stream.hip")
 
 
@@ -33,7 +33,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def measured_traffic(workload_name: str):
+def measured_traffic(workload_name: str, kernel: str):
     """HBM bytes per launch of the streaming sweep from the committed
     rocprofv3 FETCH_SIZE / WRITE_SIZE summary (copy-kernel calibrated), only
     while the kernel source is the one the counters were taken on."""
@@ -43,7 +43,8 @@ def measured_traffic(workload_name: str):
         sha = hashlib.sha256(open(SWEEP_SOURCE, "rb").read()).hexdigest()
     except (OSError, ValueError):
         return None
-    if t.get("source_sha256") != sha or workload_name != "large-L24-Lt2048":
+    if (t.get("source_sha256") != sha or workload_name != "large-L24-Lt2048"
+            or not t.get("kernel", "").startswith(kernel)):
         return None
     return t["per_launch"]
 
@@ -253,8 +254,9 @@ def main():
     plan.sync()
     variant = args.variant
     if variant < 0:
-        variant = 0
+        variant = 3  # the library default: helper waves at L = 24
     plan.set_variant(variant)
+    kernel = "k_sweep_helped" if (variant == 3 and sh.L == 24) else "k_sweep_stream"
     log(f"bench: warmup {args.warmup} sweeps (variant {variant})")
     plan.sweep(args.warmup)
     plan.sync()
@@ -304,10 +306,10 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None,
-                     "kernel": "k_sweep_stream", "kernel_ms": round(avg_kernel_ms, 4),
+                     "kernel": kernel, "kernel_ms": round(avg_kernel_ms, 4),
                      "algorithmic_bytes_per_launch": alg_bytes},
     }
-    tr = measured_traffic(w.name) if variant in (0, 2) else None
+    tr = measured_traffic(w.name, kernel)
     if tr is not None:
         result["roofline"]["traffic"] = tr["traffic_bytes"]
         result["roofline"]["traffic_unit"] = "HBM bytes per launch (rocprofv3, copy-calibrated)"

@@ -245,7 +245,7 @@ typedef struct {
 } tfim_tuning;
 
 /* Autotuner.  Under each candidate (per-shape and concurrent schedules with
- * streaming variants 0 and 2; batched schedule with every workgroup size
+ * sweep variants 3, 0 and 2; batched schedule with every workgroup size
  * from the largest team up to 768 threads that packs the shapes' teams
  * differently)
  * it runs one untimed sweep, then `sweeps_per_trial` sweeps timed with HIP
@@ -261,9 +261,11 @@ tfim_status tfim_autotune(tfim_plan *plan, uint32_t sweeps_per_trial, const char
 tfim_status tfim_get_tuning(const tfim_plan *plan, tfim_tuning *out);
 
 /* Sweep kernel variant of the per-shape schedule (all give bit-identical
- * chains): 0 = streaming (one barrier per two tau planes; default),
- * 1 = chunked (eight tau planes per step), 2 = streaming compiled for at
- * least five waves per SIMD.  Host-only. */
+ * chains): 0 = streaming (one barrier per two tau planes), 1 = chunked
+ * (eight tau planes per step), 2 = streaming compiled for at least five
+ * waves per SIMD, 3 (default) = streaming with three helper waves that
+ * compute the uniforms and lane masks of the three column waves sharing a
+ * SIMD (L = 24 only; other shapes run variant 0).  Host-only. */
 tfim_status tfim_set_variant(tfim_plan *plan, uint32_t variant);
 
 /* Kernel timing: while enabled, tfim_sweep records a pair of HIP events on

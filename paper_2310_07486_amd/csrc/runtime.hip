@@ -58,7 +58,7 @@ struct tfim_plan {
     bool poisoned = false;
     std::vector<uint64_t> t, m;  // host mirrors per shape
     uint32_t schedule = TFIM_SCHED_PER_SHAPE;
-    int variant = 0;
+    int variant = 3;  // helper waves where L = 24, else the streaming kernel
     uint32_t measure_mode = 0;
     double tuned_ms = 0.0;
     // batched schedule: arena region (ShapeDev[ns], first[ns+1], queue,
@@ -1126,7 +1126,7 @@ tfim_status tfim_autotune(tfim_plan* pl, uint32_t sweeps_per_trial, const char* 
     }
     for (uint32_t sched : {(uint32_t)TFIM_SCHED_PER_SHAPE, (uint32_t)TFIM_SCHED_CONCURRENT}) {
         if (sched == TFIM_SCHED_CONCURRENT && pl->shapes.size() < 2) continue;  // same as per-shape
-        for (uint32_t v : {0u, 2u}) {
+        for (uint32_t v : {3u, 0u, 2u}) {
             Choice p;
             p.schedule = sched;
             p.variant = v;

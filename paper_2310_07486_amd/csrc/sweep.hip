@@ -405,19 +405,21 @@ int block_for(const ShapeDev& sh) { return ((sh.L2 + 63) / 64) * 64; }
 
 }  // namespace
 
-int sweep_variants() { return 3; }
+int sweep_variants() { return 4; }
 const char* sweep_variant_name(int v) {
     switch (v) {
         case 0: return "stream";
         case 1: return "chunk8";
         case 2: return "stream-occ5";
+        case 3: return "stream-helped";
         default: return "?";
     }
 }
 
 hipError_t launch_sweep(const ShapeDev& sh, uint64_t seed, const Counters* ctr, int variant,
                         bool energy, hipStream_t st) {
-    if ((variant == 0 || variant == 2) && sweep_stream_ok(sh))
+    if (variant == 3 && sweep_helped_ok(sh)) return launch_sweep_helped(sh, seed, ctr, energy, st);
+    if ((variant == 0 || variant == 2 || variant == 3) && sweep_stream_ok(sh))
         return launch_sweep_stream(sh, seed, ctr, energy, variant == 2 ? 5 : 1, st);
     const int nblk = sh.R * sh.nk * sh.W;
     hipLaunchKernelGGL(k_sweep_fused, dim3(nblk), dim3(block_for(sh)), sweep_lds_bytes(sh), st, sh,
@@ -426,7 +428,8 @@ hipError_t launch_sweep(const ShapeDev& sh, uint64_t seed, const Counters* ctr, 
 }
 
 hipError_t prepare_sweep(const ShapeDev& sh, int variant, bool energy) {
-    if ((variant == 0 || variant == 2) && sweep_stream_ok(sh))
+    if (variant == 3 && sweep_helped_ok(sh)) return prepare_sweep_helped(sh, energy);
+    if ((variant == 0 || variant == 2 || variant == 3) && sweep_stream_ok(sh))
         return prepare_sweep_stream(sh, energy, variant == 2 ? 5 : 1);
     return hipSuccess;  // the chunked kernel stays within 64 KiB of LDS
 }

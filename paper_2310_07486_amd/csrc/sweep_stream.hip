@@ -120,13 +120,14 @@ __device__ __forceinline__ uint64_t lane_mask(const Tables& tb, int u, uint32_t 
     return R < T ? hi : lo;
 }
 
-// One site of 64 lanes.  Returns the new word; if kE, also the three bits of
-// the final unsatisfied-bond count (f0 + 2 f1 + 4 f2).
+// One site of 64 lanes given the three lane masks m_u = {lanes : R <
+// T[kidx][u]}.  Returns the new word; if kE, also the three bits of the
+// final unsatisfied-bond count (f0 + 2 f1 + 4 f2).
 template <bool kE>
-__device__ __forceinline__ uint64_t site(uint64_t s, const Nb& n, uint64_t jxp, uint64_t jxm,
-                                         uint64_t jyp, uint64_t jym, uint64_t up, uint64_t dn,
-                                         uint32_t R, const Tables& tb, uint64_t& f0, uint64_t& f1,
-                                         uint64_t& f2) {
+__device__ __forceinline__ uint64_t site_m(uint64_t s, const Nb& n, uint64_t jxp, uint64_t jxm,
+                                           uint64_t jyp, uint64_t jym, uint64_t up, uint64_t dn,
+                                           uint64_t m0, uint64_t m1, uint64_t m2, uint64_t& f0,
+                                           uint64_t& f1, uint64_t& f2) {
     const uint64_t p1 = b3<kXor3>(s, n.xp, jxp);
     const uint64_t p2 = b3<kXor3>(s, n.xm, jxm);
     const uint64_t p3 = b3<kXor3>(s, n.yp, jyp);
@@ -142,9 +143,6 @@ __device__ __forceinline__ uint64_t site(uint64_t s, const Nb& n, uint64_t jxp, 
     const uint64_t ge1 = so | co;                     // u >= 1
     const uint64_t ge2 = b3<kAorBandC>(co, s1, s2);   // u >= 2
     const uint64_t ge3 = b3<kMaj>(c1, c2, so);        // u >= 3
-    const uint64_t m0 = lane_mask(tb, 0, R);
-    const uint64_t m1 = lane_mask(tb, 1, R);
-    const uint64_t m2 = lane_mask(tb, 2, R);
     // masks are nested (m0 in m1 in m2): flip = ge3 | ge2&m2 | ge1&m1 | m0
     const uint64_t t1 = b3<kAandBorC>(ge2, m2, m0);
     const uint64_t t2 = b3<kAandBorC>(ge1, m1, t1);
@@ -160,6 +158,16 @@ __device__ __forceinline__ uint64_t site(uint64_t s, const Nb& n, uint64_t jxp, 
         f2 = b3<kAorBandC>(y2, x2, y1);
     }
     return b3<kAxorBorC>(s, ge3, t2);  // s ^ flip
+}
+
+// The same with the masks looked up for the uniform R.
+template <bool kE>
+__device__ __forceinline__ uint64_t site(uint64_t s, const Nb& n, uint64_t jxp, uint64_t jxm,
+                                         uint64_t jyp, uint64_t jym, uint64_t up, uint64_t dn,
+                                         uint32_t R, const Tables& tb, uint64_t& f0, uint64_t& f1,
+                                         uint64_t& f2) {
+    return site_m<kE>(s, n, jxp, jxm, jyp, jym, up, dn, lane_mask(tb, 0, R), lane_mask(tb, 1, R),
+                      lane_mask(tb, 2, R), f0, f1, f2);
 }
 
 // 5-bit per-lane counter += 3-bit value.
@@ -421,6 +429,269 @@ __device__ __forceinline__ void sweep_teams(const ShapeDev& sh, const int cfg0, 
     }
 }
 
+// Helper-wave form for L^2 = 576 (nine column waves).  Waves are placed on the
+// four SIMDs round-robin, so waves 0, 4 and 8 share one SIMD and would carry
+// half again the work of the others.  Three helper waves (9, 10, 11, one on
+// each other SIMD) take over the uniforms and the lane-mask lookups of those
+// three waves: one segment ahead, helper 9 + h runs the same Philox sequence
+// as column wave 4h would, lane for lane, and leaves the six masks of the
+// next segment's two sites in LDS.  Every role runs the same segments and
+// barriers; results are bit-identical to k_sweep_stream.
+constexpr int kHelpedThreads = 768;
+constexpr int kColWaves = 9;
+constexpr int kHelpCols = kColWaves * 64;  // 576
+
+__host__ __device__ inline int helped_words(const ShapeDev& sh) {
+    return (stream_nbt(sh) + 1) / 2 + kDeep * kHelpCols + stream_team_words(sh) + 2 * 3 * 64 * 6;
+}
+
+template <bool kE>
+__global__ void __launch_bounds__(kHelpedThreads)
+k_sweep_helped(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __restrict__ ctr) {
+    extern __shared__ uint64_t lds[];
+    const int L = sh.L, L2 = sh.L2, Lt = sh.Lt, nk = sh.nk, W = sh.W;
+    const int nb0 = sh.bnb[0] + 1, nb1 = sh.bnb[1] + 1, nb2 = sh.bnb[2] + 1;
+    const int nbt = nb0 + nb1 + nb2;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const bool helper = wave >= kColWaves;
+    const int h = helper ? wave - kColWaves : (wave >> 2);  // helper slot of a served wave
+
+    uint32_t* TT = (uint32_t*)lds;
+    uint64_t* DEEP = lds + ((nbt + 1) >> 1);
+    uint64_t* X = DEEP + kDeep * kHelpCols;
+    uint64_t* Y = X + 2 * L2;
+    uint64_t* ml = X + 4 * L2;
+    uint64_t* MM = ml + nk + 1;
+    uint32_t* Ublk = (uint32_t*)(MM + 2 * nbt);
+    uint64_t* HM = MM + 2 * nbt + 32;  // [2][3][64][6] masks of the served waves
+    const int H = L2;
+
+    const int cfg = blockIdx.x;  // ((r*nk + w)*W + j)
+    const int j = cfg % W;
+    const int rw = cfg / W;
+    const int w = rw % nk;
+    const int r = rw / nk;
+
+    for (int i = tid; i <= nk; i += kHelpedThreads)
+        ml[i] = sh.mask[((size_t)(r * W + j) * nk + w) * (nk + 1) + i];
+    if (kE && tid < 64) Ublk[tid] = 0;
+    if (kE && !helper)
+        for (int i = 0; i < kDeep; ++i) DEEP[i * kHelpCols + tid] = 0;
+    __syncthreads();
+    const int bo0 = sh.boff[0], bo1 = sh.boff[1] - nb0, bo2 = sh.boff[2] - nb0 - nb1;
+    for (int a = tid; a < nbt; a += kHelpedThreads) {
+        const uint64_t e = sh.btab[a + (a < nb0 ? bo0 : (a < nb0 + nb1 ? bo1 : bo2))];
+        const uint32_t kb = (uint32_t)(e >> 32) & 0xFFFFu, mu = (uint32_t)(e >> 48);
+        TT[a] = (uint32_t)e;
+        MM[2 * a] = ml[kb];
+        MM[2 * a + 1] = ml[kb + mu];
+    }
+    Tables tb;
+    tb.T[0] = TT; tb.T[1] = TT + nb0; tb.T[2] = TT + nb0 + nb1;
+    tb.M[0] = MM; tb.M[1] = MM + 2 * nb0; tb.M[2] = MM + 2 * (nb0 + nb1);
+    tb.sh[0] = (uint32_t)sh.bsh[0]; tb.sh[1] = (uint32_t)sh.bsh[1]; tb.sh[2] = (uint32_t)sh.bsh[2];
+    tb.nb[0] = (uint32_t)sh.bnb[0]; tb.nb[1] = (uint32_t)sh.bnb[1]; tb.nb[2] = (uint32_t)sh.bnb[2];
+    __syncthreads();  // tables complete: the helpers look up segment 0's masks below
+
+    const uint32_t t = ctr->t;
+    const uint32_t c3 = ctr_word3(sh.word_offset + (uint32_t)j, sh.sid, kTagMetro);
+    const uint32_t c2_0 = (uint32_t)rw << 1, c2_1 = c2_0 | 1u;
+
+    // the column of this thread: its own, or (helper) that of the served lane
+    const int xy = helper ? 64 * (4 * h) + lane : tid;
+    const int x = xy % L, y = xy / L;
+    const int p = (x + y) & 1;
+    const int hx = xy;
+    const int hxp = ((x + 1) % L) + L * y;
+    const int hxm = ((x + L - 1) % L) + L * y;
+    const int hyp = x + L * ((y + 1) % L);
+    const int hym = x + L * ((y + L - 1) % L);
+    const uint64_t* Jb = sh.J + (size_t)j * 2 * L2;
+    const uint64_t jxp = Jb[xy], jxm = Jb[hxm], jyp = Jb[L2 + xy], jym = Jb[L2 + hym];
+
+    const uint64_t base = (uint64_t)(sh.S + (size_t)cfg * Lt * L2);
+    const uint32_t base_lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
+    const uint32_t base_hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
+    const __amdgpu_buffer_rsrc_t spins = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(((uint64_t)base_hi << 32) | base_lo), (short)0, Lt * L2 * 8, kBufferWord3);
+    const int voff = 8 * xy;
+    const int plane = 8 * L2;
+    const int half = Lt >> 1;
+    const int nq = Lt >> 3;
+    auto wrap = [Lt](int P) { return P >= Lt ? P - Lt : (P < 0 ? P + Lt : P); };
+    auto ld = [&](int P) -> uint64_t { return buf_load(spins, voff, wrap(min(P, Lt + 1)) * plane); };
+    auto ld_lane = [&](int P) -> uint64_t { return buf_load(spins, voff + wrap(P) * plane, 0); };
+    auto hm = [&](int buf, int k) -> uint64_t* { return HM + ((buf * 3 + h) * 64 + lane) * 6 + k; };
+
+    uint64_t w0 = 0, w1 = 0, w2 = 0, w3 = 0, w4 = 0, w5 = 0, pf0 = 0, pf1 = 0, nx0 = 0, nx1 = 0, pu1 = 0;
+    if (!helper) {
+        w3 = ld_lane(p - 1);
+        w4 = ld_lane(p);
+        w5 = ld_lane(p + 1);
+        pf0 = ld_lane(min(p + 2, Lt + 1));
+        pf1 = ld_lane(min(p + 3, Lt + 1));
+        pu1 = ld(4);
+    }
+    U4 G0, G1;
+    uint32_t prevlast = 0;
+    uint64_t sm[5] = {0, 0, 0, 0, 0};
+    uint64_t* deep = DEEP + tid;
+    uint64_t f0 = 0, f1 = 0, f2 = 0;
+
+    if (!helper) {
+        X[hx] = p ? w3 : w5;  // X(0)
+    } else {
+        // masks of segment 0 (colour 0, group 0) for the served lane
+        G0 = philox_dev((uint32_t)xy, t, c2_0, c3, key0, key1);
+        *hm(0, 0) = lane_mask(tb, 0, G0.v[0]);
+        *hm(0, 1) = lane_mask(tb, 1, G0.v[0]);
+        *hm(0, 2) = lane_mask(tb, 2, G0.v[0]);
+    }
+    __syncthreads();
+
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I3 = std::integral_constant<int, 3>;
+
+    // kRole 0: column wave that looks up its own masks; 1: column wave fed by
+    // a helper; 2: helper.  All roles run the same segments and barriers.
+    auto segment = [&](const int sigma, const auto ISc, const auto roleC, const bool do_c0, const bool do_c1) {
+            constexpr int kRole = decltype(roleC)::value;
+            constexpr int IS = decltype(ISc)::value;
+            if constexpr (kRole == 2) {
+                // the next segment's masks for the served lane
+                constexpr int ISn = (IS + 1) & 3;
+                const int sn = sigma + 1;
+                if (sn < half) {
+                    if (ISn == 0)
+                        G0 = philox_dev((uint32_t)(xy + L2 * (sn >> 2)), t, c2_0, c3, key0, key1);
+                    const uint32_t R0 = G0.v[ISn];
+                    *hm(ISn & 1, 0) = lane_mask(tb, 0, R0);
+                    *hm(ISn & 1, 1) = lane_mask(tb, 1, R0);
+                    *hm(ISn & 1, 2) = lane_mask(tb, 2, R0);
+                }
+                if (ISn == 1 && sn <= half + 1) {
+                    prevlast = G1.v[3];
+                    int q = (sn - 1) >> 2;
+                    if (q >= nq) q -= nq;
+                    G1 = philox_dev((uint32_t)(xy + L2 * q), t, c2_1, c3, key0, key1);
+                }
+                if (sn >= 2 && sn <= half + 1) {
+                    constexpr int S3 = (ISn + 3) & 3;
+                    const uint32_t R1 = p ? G1.v[S3] : (S3 == 0 ? prevlast : G1.v[(S3 + 3) & 3]);
+                    *hm(ISn & 1, 3) = lane_mask(tb, 0, R1);
+                    *hm(ISn & 1, 4) = lane_mask(tb, 1, R1);
+                    *hm(ISn & 1, 5) = lane_mask(tb, 2, R1);
+                }
+                __syncthreads();
+                return;
+            } else {
+                const int A = 2 * sigma + p;
+                const uint64_t u0 = ld(2 * sigma + 5), u1 = ld(2 * sigma + 6);
+                nx0 = p ? u0 : pu1;
+                nx1 = p ? u1 : u0;
+                pu1 = u1;
+                if (do_c0) {
+                    const uint64_t* Xb = X + (IS & 1) * H;
+                    const Nb n{Xb[hxp], Xb[hxm], Xb[hyp], Xb[hym]};
+                    uint64_t d0, d1, d2;
+                    if constexpr (kRole == 0) {
+                        if (IS == 0)
+                            G0 = philox_dev((uint32_t)(xy + L2 * (sigma >> 2)), t, c2_0, c3, key0, key1);
+                        w4 = site<false>(w4, n, jxp, jxm, jyp, jym, w5, w3, G0.v[IS], tb, d0, d1, d2);
+                    } else {
+                        w4 = site_m<false>(w4, n, jxp, jxm, jyp, jym, w5, w3, *hm(IS & 1, 0), *hm(IS & 1, 1),
+                                           *hm(IS & 1, 2), d0, d1, d2);
+                    }
+                }
+                if constexpr (kRole == 0) {
+                    if (IS == 1) {  // colour-1 Philox group of step s = sigma - 1 (s % 4 == 0)
+                        prevlast = G1.v[3];
+                        int q = (sigma - 1) >> 2;
+                        if (q >= nq) q -= nq;
+                        G1 = philox_dev((uint32_t)(xy + L2 * q), t, c2_1, c3, key0, key1);
+                    }
+                }
+                if (do_c1) {
+                    const uint64_t* Yb = Y + ((IS + 1) & 1) * H;
+                    const Nb n{Yb[hxp], Yb[hxm], Yb[hyp], Yb[hym]};
+                    if constexpr (kRole == 0) {
+                        constexpr int S3 = (IS + 3) & 3;  // (sigma - 1) & 3
+                        const uint32_t R1 = p ? G1.v[S3] : (S3 == 0 ? prevlast : G1.v[(S3 + 3) & 3]);
+                        w1 = site<kE>(w1, n, jxp, jxm, jyp, jym, w2, w0, R1, tb, f0, f1, f2);
+                    } else {
+                        w1 = site_m<kE>(w1, n, jxp, jxm, jyp, jym, w2, w0, *hm(IS & 1, 3), *hm(IS & 1, 4),
+                                        *hm(IS & 1, 5), f0, f1, f2);
+                    }
+                    if (kE) add3v(sm, f0, f1, f2);
+                }
+                const int P1 = 2 * sigma - 3, P2 = 2 * sigma - 2;
+                if (P1 >= 0) buf_store(p ? w0 : w1, spins, voff, wrap(P1) * plane);
+                if (P2 >= 0) buf_store(p ? w1 : w2, spins, voff, wrap(P2) * plane);
+                Y[(IS & 1) * H + hx] = p ? w2 : w4;
+                X[((IS + 1) & 1) * H + hx] = p ? w5 : pf1;
+                __syncthreads();
+                w0 = w2; w1 = w3; w2 = w4; w3 = w5; w4 = pf0; w5 = pf1; pf0 = nx0; pf1 = nx1;
+            }
+        };
+    using R0 = std::integral_constant<int, 0>;
+    using R1 = std::integral_constant<int, 1>;
+    using R2 = std::integral_constant<int, 2>;
+    if (helper) {
+        for (int gq = 0; gq < nq; ++gq) {
+            const int s0 = 4 * gq;
+            segment(s0 + 0, I0{}, R2{}, true, gq > 0);
+            segment(s0 + 1, I1{}, R2{}, true, gq > 0);
+            segment(s0 + 2, I2{}, R2{}, true, true);
+            segment(s0 + 3, I3{}, R2{}, true, true);
+        }
+        segment(half, I0{}, R2{}, false, true);
+        segment(half + 1, I1{}, R2{}, false, true);
+    } else if ((wave & 3) == 0) {
+        for (int gq = 0; gq < nq; ++gq) {
+            const int s0 = 4 * gq;
+            segment(s0 + 0, I0{}, R1{}, true, gq > 0);
+            segment(s0 + 1, I1{}, R1{}, true, gq > 0);
+            segment(s0 + 2, I2{}, R1{}, true, true);
+            segment(s0 + 3, I3{}, R1{}, true, true);
+            if (kE) {
+                add_deep(deep, kHelpCols, sm);
+                if ((gq % kFlushMacros) == kFlushMacros - 1) flush_deep(deep, kHelpCols, Ublk, true);
+            }
+        }
+        segment(half, I0{}, R1{}, false, true);
+        segment(half + 1, I1{}, R1{}, false, true);
+        if (kE) {
+            add_deep(deep, kHelpCols, sm);
+            flush_deep(deep, kHelpCols, Ublk, true);
+        }
+    } else {
+        for (int gq = 0; gq < nq; ++gq) {
+            const int s0 = 4 * gq;
+            segment(s0 + 0, I0{}, R0{}, true, gq > 0);
+            segment(s0 + 1, I1{}, R0{}, true, gq > 0);
+            segment(s0 + 2, I2{}, R0{}, true, true);
+            segment(s0 + 3, I3{}, R0{}, true, true);
+            if (kE) {
+                add_deep(deep, kHelpCols, sm);
+                if ((gq % kFlushMacros) == kFlushMacros - 1) flush_deep(deep, kHelpCols, Ublk, true);
+            }
+        }
+        segment(half, I0{}, R0{}, false, true);
+        segment(half + 1, I1{}, R0{}, false, true);
+        if (kE) {
+            add_deep(deep, kHelpCols, sm);
+            flush_deep(deep, kHelpCols, Ublk, true);
+        }
+    }
+    if (kE) {
+        __syncthreads();
+        if (tid < 64) sh.U[((size_t)r * W * 64 + (size_t)j * 64 + tid) * nk + w] = Ublk[tid];
+    }
+}
+
 // One configuration per workgroup (r, w, j) = blockIdx.x.
 // kOcc: minimum waves per SIMD the register allocation must allow (1 = no
 // constraint); a tuning knob, the results do not depend on it.
@@ -510,6 +781,31 @@ static hipError_t launch_one(const ShapeDev& sh, uint64_t seed, const Counters* 
     hipLaunchKernelGGL((k_sweep_stream<kE, kOcc>), dim3(nblk), dim3(threads), lds, st, sh,
                        (uint32_t)seed, (uint32_t)(seed >> 32), ctr);
     return hipGetLastError();
+}
+
+bool sweep_helped_ok(const ShapeDev& sh) { return sweep_stream_ok(sh) && sh.L2 == kHelpCols; }
+
+template <bool kE>
+static hipError_t launch_helped_one(const ShapeDev& sh, uint64_t seed, const Counters* ctr, hipStream_t st,
+                                    bool launch) {
+    static size_t lds_set = 0;
+    const size_t lds = (size_t)helped_words(sh) * 8;
+    hipError_t e = allow_lds((const void*)k_sweep_helped<kE>, lds, lds_set);
+    if (e != hipSuccess || !launch) return e;
+    hipLaunchKernelGGL((k_sweep_helped<kE>), dim3(sh.R * sh.nk * sh.W), dim3(kHelpedThreads), lds, st, sh,
+                       (uint32_t)seed, (uint32_t)(seed >> 32), ctr);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_helped(const ShapeDev& sh, uint64_t seed, const Counters* ctr, bool energy,
+                               hipStream_t st) {
+    return energy ? launch_helped_one<true>(sh, seed, ctr, st, true)
+                  : launch_helped_one<false>(sh, seed, ctr, st, true);
+}
+
+hipError_t prepare_sweep_helped(const ShapeDev& sh, bool energy) {
+    return energy ? launch_helped_one<true>(sh, 0, nullptr, nullptr, false)
+                  : launch_helped_one<false>(sh, 0, nullptr, nullptr, false);
 }
 
 hipError_t launch_sweep_stream(const ShapeDev& sh, uint64_t seed, const Counters* ctr,

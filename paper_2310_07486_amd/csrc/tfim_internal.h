@@ -138,7 +138,8 @@ hipError_t launch_labels_identity(const ShapeDev& sh, hipStream_t st);
 hipError_t launch_energy(const ShapeDev& sh, hipStream_t st);
 hipError_t launch_mask_rebuild(const ShapeDev& sh, hipStream_t st);
 // variant 0: streaming kernel (needs bucket tables), 1: chunked kernel,
-// 2: streaming kernel compiled for >= 5 waves per SIMD.
+// 2: streaming kernel compiled for >= 5 waves per SIMD, 3: streaming kernel
+// with helper waves where L^2 = 576 (else as 0).
 // energy: also recount U (the chunked kernel always does).
 hipError_t launch_sweep(const ShapeDev& sh, uint64_t seed, const Counters* ctr, int variant,
                         bool energy, hipStream_t st);
@@ -148,6 +149,11 @@ hipError_t launch_sweep_stream(const ShapeDev& sh, uint64_t seed, const Counters
 // LDS above 64 KiB), set outside any stream capture.
 hipError_t prepare_sweep(const ShapeDev& sh, int variant, bool energy);
 hipError_t prepare_sweep_stream(const ShapeDev& sh, bool energy, int occ);
+// Helper-wave form of the streaming sweep (L^2 = 576 only).
+bool sweep_helped_ok(const ShapeDev& sh);
+hipError_t launch_sweep_helped(const ShapeDev& sh, uint64_t seed, const Counters* ctr, bool energy,
+                               hipStream_t st);
+hipError_t prepare_sweep_helped(const ShapeDev& sh, bool energy);
 bool sweep_stream_ok(const ShapeDev& sh);
 // LDS of a streaming-sweep block of `teams` configurations and `threads`
 // threads; threads per configuration (L^2 rounded up to whole waves).

@@ -181,10 +181,10 @@ def test_multi_shape_plan_equals_single_shape_plans():
         assert all(np.array_equal(x, y) for x, y in zip(both.get_state(i), one.get_state(0)))
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 @pytest.mark.parametrize("L,Lt,W,R,nk,pt", [
     (8, 32, 1, 2, 6, 1), (12, 24, 1, 2, 5, 2), (24, 16, 1, 1, 4, 1), (2, 8, 1, 2, 2, 1),
-    (6, 8, 1, 2, 3, 1), (20, 40, 1, 1, 3, 0),
+    (6, 8, 1, 2, 3, 1), (20, 40, 1, 1, 3, 0), (24, 72, 2, 2, 5, 1),
 ])
 def test_sweep_kernel_variants(variant, L, Lt, W, R, nk, pt):
     """Every sweep-kernel variant reproduces the oracle bit for bit."""
@@ -197,7 +197,7 @@ def test_sweep_kernel_variants(variant, L, Lt, W, R, nk, pt):
     plan.sweep(5)
     plan.sweep(7)
     plan.sync()
-    lanes = list(range(64)) if L <= 8 else [0, 13, 63]
+    lanes = list(range(64)) if L <= 8 else ([0, 13, 63, 64, 127] if W > 1 else [0, 13, 63])
     _compare(plan, 0, sh, seed, lanes, 12)
 
 

@@ -187,21 +187,22 @@ constexpr int kDeep = 12;          // per-thread counter bits (kept in LDS)
 constexpr int kFlushMacros = 128;  // 128 * 24 < 2^12
 
 // deep += small (5 bits), ripple carry; deep lives in LDS, plane k of
-// thread t at d[k * stride + t].
+// thread t at d[k * stride + t].  Above the five planes of the addend the
+// carry rarely survives: the ripple stops once no lane of the wave carries.
 __device__ __forceinline__ void add_deep(uint64_t* d, int stride, uint64_t (&a)[5]) {
     uint64_t k = 0;
 #pragma unroll
-    for (int i = 0; i < kDeep; ++i) {
+    for (int i = 0; i < 5; ++i) {
         const uint64_t v = d[i * stride];
-        if (i < 5) {
-            const uint64_t nk = b3<kMaj>(v, a[i], k);
-            d[i * stride] = b3<kXor3>(v, a[i], k);
-            k = nk;
-            a[i] = 0;
-        } else {
-            d[i * stride] = v ^ k;
-            k = v & k;
-        }
+        const uint64_t nk = b3<kMaj>(v, a[i], k);
+        d[i * stride] = b3<kXor3>(v, a[i], k);
+        k = nk;
+        a[i] = 0;
+    }
+    for (int i = 5; i < kDeep && __any(k != 0); ++i) {
+        const uint64_t v = d[i * stride];
+        d[i * stride] = v ^ k;
+        k = v & k;
     }
 }
 
@@ -464,7 +465,7 @@ k_sweep_helped(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __rest
     uint64_t* ml = X + 4 * L2;
     uint64_t* MM = ml + nk + 1;
     uint32_t* Ublk = (uint32_t*)(MM + 2 * nbt);
-    uint64_t* HM = MM + 2 * nbt + 32;  // [2][3][64][6] masks of the served waves
+    uint64_t* HM = MM + 2 * nbt + 32;  // [2][3][6][64] masks of the served waves
     const int H = L2;
 
     const int cfg = blockIdx.x;  // ((r*nk + w)*W + j)
@@ -522,7 +523,8 @@ k_sweep_helped(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __rest
     auto wrap = [Lt](int P) { return P >= Lt ? P - Lt : (P < 0 ? P + Lt : P); };
     auto ld = [&](int P) -> uint64_t { return buf_load(spins, voff, wrap(min(P, Lt + 1)) * plane); };
     auto ld_lane = [&](int P) -> uint64_t { return buf_load(spins, voff + wrap(P) * plane, 0); };
-    auto hm = [&](int buf, int k) -> uint64_t* { return HM + ((buf * 3 + h) * 64 + lane) * 6 + k; };
+    // [buffer][helper][mask][lane]: lane-contiguous, so every access is conflict-free
+    auto hm = [&](int buf, int k) -> uint64_t* { return HM + ((buf * 3 + h) * 6 + k) * 64 + lane; };
 
     uint64_t w0 = 0, w1 = 0, w2 = 0, w3 = 0, w4 = 0, w5 = 0, pf0 = 0, pf1 = 0, nx0 = 0, nx1 = 0, pu1 = 0;
     if (!helper) {

@@ -665,10 +665,10 @@ static tfim_status batch_setup(tfim_plan* pl, uint32_t threads, uint32_t bpc) {
         devs[i] = d;
         const int cols = tfim::sweep_stream_cols(d);
         int g = std::min<int>((int)threads / cols, 255);
-        while (g > 1 && tfim::sweep_stream_lds_bytes(d, g, (int)threads) > kLdsLimit) --g;
-        if (tfim::sweep_stream_lds_bytes(d, g, (int)threads) > kLdsLimit)
+        while (g > 1 && tfim::sweep_stream_lds_bytes(d, g, (int)threads, false) > kLdsLimit) --g;
+        if (tfim::sweep_stream_lds_bytes(d, g, (int)threads, false) > kLdsLimit)
             return fail(TFIM_EUNSUPPORTED, "batched workgroup does not fit in LDS");
-        lds = std::max(lds, tfim::sweep_stream_lds_bytes(d, g, (int)threads));
+        lds = std::max(lds, tfim::sweep_stream_lds_bytes(d, g, (int)threads, false));
         const int ncfg = d.R * d.nk * d.W;
         for (int c0 = 0; c0 < ncfg; c0 += g) {
             const uint64_t live = (uint64_t)std::min(g, ncfg - c0);

@@ -113,11 +113,18 @@ struct Tables {
     uint32_t sh[3], nb[3];
 };
 
+// The threshold is read first, then only the mask it selects (12 bytes of
+// LDS per lane instead of 20): entry 2a + (R < T) of M.  The index is the
+// borrow of R - T carried into a + a, two ALU instructions.
 __device__ __forceinline__ uint64_t lane_mask(const Tables& tb, int u, uint32_t R) {
     const uint32_t a = min(R >> tb.sh[u], tb.nb[u]);
     const uint32_t T = tb.T[u][a];
-    const uint64_t lo = tb.M[u][2 * a], hi = tb.M[u][2 * a + 1];
-    return R < T ? hi : lo;
+    uint32_t diff, idx;
+    asm("v_sub_co_u32 %0, vcc, %2, %3\n\tv_addc_co_u32 %1, vcc, %4, %4, vcc"
+        : "=&v"(diff), "=v"(idx)
+        : "v"(R), "v"(T), "v"(a)
+        : "vcc");
+    return tb.M[u][idx];
 }
 
 // One site of 64 lanes given the three lane masks m_u = {lanes : R <
@@ -183,25 +190,49 @@ __device__ __forceinline__ void add3v(uint64_t (&a)[5], uint64_t f0, uint64_t f1
     a[4] ^= k3;
 }
 
-constexpr int kDeep = 12;          // per-thread counter bits (kept in LDS)
+constexpr int kDeep = 12;          // per-thread counter bits
 constexpr int kFlushMacros = 128;  // 128 * 24 < 2^12
 
-// deep += small (5 bits), ripple carry; deep lives in LDS, plane k of
-// thread t at d[k * stride + t].  Above the five planes of the addend the
-// carry rarely survives: the ripple stops once no lane of the wave carries.
-__device__ __forceinline__ void add_deep(uint64_t* d, int stride, uint64_t (&a)[5]) {
+// The kDeep counter planes of one thread: in registers (kInLds = false), or
+// in LDS at d[k * stride] for kernels with a tight register budget.
+template <bool kInLds>
+struct Deep;
+template <>
+struct Deep<false> {
+    uint64_t v[kDeep];
+    __device__ __forceinline__ Deep(uint64_t*, int) {
+#pragma unroll
+        for (int k = 0; k < kDeep; ++k) v[k] = 0;
+    }
+    __device__ __forceinline__ uint64_t& at(int k) { return v[k]; }
+};
+template <>
+struct Deep<true> {
+    uint64_t* d;
+    int stride;
+    __device__ __forceinline__ Deep(uint64_t* base, int s) : d(base), stride(s) {}
+    __device__ __forceinline__ uint64_t& at(int k) { return d[k * stride]; }
+};
+
+// deep += small (5 bits), ripple carry.  Above the five planes of the addend
+// the carry rarely survives: the ripple stops once no lane of the wave
+// carries.
+template <bool kInLds>
+__device__ __forceinline__ void add_deep(Deep<kInLds>& d, uint64_t (&a)[5]) {
     uint64_t k = 0;
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
-        const uint64_t v = d[i * stride];
+        const uint64_t v = d.at(i);
         const uint64_t nk = b3<kMaj>(v, a[i], k);
-        d[i * stride] = b3<kXor3>(v, a[i], k);
+        d.at(i) = b3<kXor3>(v, a[i], k);
         k = nk;
         a[i] = 0;
     }
-    for (int i = 5; i < kDeep && __any(k != 0); ++i) {
-        const uint64_t v = d[i * stride];
-        d[i * stride] = v ^ k;
+#pragma unroll
+    for (int i = 5; i < kDeep; ++i) {
+        if (!__any(k != 0)) break;
+        const uint64_t v = d.at(i);
+        d.at(i) = v ^ k;
         k = v & k;
     }
 }
@@ -210,20 +241,21 @@ __device__ __forceinline__ void add_deep(uint64_t* d, int stride, uint64_t (&a)[
 // counters are cleared).  Plane k is transposed across the wave, so lane b
 // holds bit b of every thread's plane and popcounts it.  Every lane of the
 // wave takes part; only waves of a team (add) contribute.
-__device__ void flush_deep(uint64_t* d, int stride, uint32_t* Ublk, bool add) {
+template <bool kInLds>
+__device__ __forceinline__ void flush_deep(Deep<kInLds>& d, uint32_t* Ublk, bool add) {
     const int lane = threadIdx.x & 63;
     uint32_t acc = 0;
 #pragma unroll
     for (int k = 0; k < kDeep; ++k) {
-        acc += (uint32_t)__popcll(wave_transpose64(d[k * stride])) << k;
-        d[k * stride] = 0;
+        acc += (uint32_t)__popcll(wave_transpose64(d.at(k))) << k;
+        d.at(k) = 0;
     }
     if (add) atomicAdd(&Ublk[lane], acc);
 }
 
 // LDS of a block (64-bit words): TT, the bucket thresholds of the shape
-// (uint32, shared by the block); DEEP[kDeep][threads], the energy counters;
-// then one region per team: X[2 L2], Y[2 L2], ml[nk+1], MM[2 nbt] (the two
+// (uint32, shared by the block); DEEP[kDeep][threads], the energy counters,
+// only where they are kept in LDS; then one region per team: X[2 L2], Y[2 L2], ml[nk+1], MM[2 nbt] (the two
 // candidate lane masks of every bucket), Ublk[64] (uint32).
 __host__ __device__ inline int stream_nbt(const ShapeDev& sh) {
     return sh.bnb[0] + sh.bnb[1] + sh.bnb[2] + 3;
@@ -240,8 +272,9 @@ __host__ __device__ inline int stream_cols(const ShapeDev& sh) { return ((sh.L2 
 // memory.  Segment sigma updates the colour-0 site at plane A = 2 sigma + p
 // and the colour-1 site of the previous step at A - 3.
 // kPacked = false: one team filling the workgroup (g = nlive = 1,
-// cols = blockDim.x), so every wave is a live member.
-template <bool kE, bool kPacked>
+// cols = blockDim.x), so every wave is a live member.  kDeepLds: the energy
+// counters live in LDS rather than registers.
+template <bool kE, bool kPacked, bool kDeepLds>
 __device__ __forceinline__ void sweep_teams(const ShapeDev& sh, const int cfg0, const int g,
                                             const int nlive, const int cols, uint64_t* lds,
                                             const uint32_t key0, const uint32_t key1,
@@ -259,7 +292,7 @@ __device__ __forceinline__ void sweep_teams(const ShapeDev& sh, const int cfg0, 
 
     uint32_t* TT = (uint32_t*)lds;
     uint64_t* DEEP = lds + ((nbt + 1) >> 1);
-    uint64_t* X = DEEP + kDeep * nthr + (size_t)lteam * stream_team_words(sh);
+    uint64_t* X = DEEP + (kDeepLds ? kDeep * nthr : 0) + (size_t)lteam * stream_team_words(sh);
     uint64_t* Y = X + 2 * L2;
     uint64_t* ml = X + 4 * L2;
     uint64_t* MM = ml + nk + 1;
@@ -276,7 +309,7 @@ __device__ __forceinline__ void sweep_teams(const ShapeDev& sh, const int cfg0, 
         for (int i = ttid; i <= nk; i += cols)
             ml[i] = live ? sh.mask[((size_t)(r * W + j) * nk + w) * (nk + 1) + i] : 0ull;
     if (kE && member && ttid < 64) Ublk[ttid] = 0;
-    if (kE)
+    if (kE && kDeepLds)
         for (int i = 0; i < kDeep; ++i) DEEP[i * nthr + tid] = 0;
     __syncthreads();
     // entry a of the concatenated tables (u = 0, 1, 2) sits at btab[a + shift(u)]
@@ -345,8 +378,7 @@ __device__ __forceinline__ void sweep_teams(const ShapeDev& sh, const int cfg0, 
     U4 G0, G1;
     uint32_t prevlast = 0;
     uint64_t sm[5] = {0, 0, 0, 0, 0};
-    uint64_t* deep = DEEP + tid;
-    const int dstride = nthr;
+    Deep<kDeepLds> deep(DEEP + tid, nthr);
     uint64_t f0 = 0, f1 = 0, f2 = 0;
 
     if (active) X[hx] = p ? w3 : w5;  // X(0)
@@ -414,16 +446,16 @@ __device__ __forceinline__ void sweep_teams(const ShapeDev& sh, const int cfg0, 
         segment(s0 + 2, I2{}, true, true);
         segment(s0 + 3, I3{}, true, true);
         if (kE && member) {
-            add_deep(deep, dstride, sm);
-            if ((gq % kFlushMacros) == kFlushMacros - 1) flush_deep(deep, dstride, Ublk, true);
+            add_deep(deep, sm);
+            if ((gq % kFlushMacros) == kFlushMacros - 1) flush_deep(deep, Ublk, true);
         }
     }
     segment(half, I0{}, false, true);      // colour 1, step half-1
     segment(half + 1, I1{}, false, true);  // colour 1, step half == step 0 (tau wrap)
     if (kE) {
         if (member) {
-            add_deep(deep, dstride, sm);
-            flush_deep(deep, dstride, Ublk, true);
+            add_deep(deep, sm);
+            flush_deep(deep, Ublk, true);
         }
         __syncthreads();
         if (live && ttid < 64) sh.U[((size_t)r * W * 64 + (size_t)j * 64 + ttid) * nk + w] = Ublk[ttid];
@@ -443,7 +475,7 @@ constexpr int kColWaves = 9;
 constexpr int kHelpCols = kColWaves * 64;  // 576
 
 __host__ __device__ inline int helped_words(const ShapeDev& sh) {
-    return (stream_nbt(sh) + 1) / 2 + kDeep * kHelpCols + stream_team_words(sh) + 2 * 3 * 64 * 6;
+    return (stream_nbt(sh) + 1) / 2 + stream_team_words(sh) + 2 * 3 * 64 * 6;
 }
 
 template <bool kE>
@@ -459,8 +491,7 @@ k_sweep_helped(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __rest
     const int h = helper ? wave - kColWaves : (wave >> 2);  // helper slot of a served wave
 
     uint32_t* TT = (uint32_t*)lds;
-    uint64_t* DEEP = lds + ((nbt + 1) >> 1);
-    uint64_t* X = DEEP + kDeep * kHelpCols;
+    uint64_t* X = lds + ((nbt + 1) >> 1);
     uint64_t* Y = X + 2 * L2;
     uint64_t* ml = X + 4 * L2;
     uint64_t* MM = ml + nk + 1;
@@ -477,8 +508,6 @@ k_sweep_helped(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __rest
     for (int i = tid; i <= nk; i += kHelpedThreads)
         ml[i] = sh.mask[((size_t)(r * W + j) * nk + w) * (nk + 1) + i];
     if (kE && tid < 64) Ublk[tid] = 0;
-    if (kE && !helper)
-        for (int i = 0; i < kDeep; ++i) DEEP[i * kHelpCols + tid] = 0;
     __syncthreads();
     const int bo0 = sh.boff[0], bo1 = sh.boff[1] - nb0, bo2 = sh.boff[2] - nb0 - nb1;
     for (int a = tid; a < nbt; a += kHelpedThreads) {
@@ -538,7 +567,7 @@ k_sweep_helped(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __rest
     U4 G0, G1;
     uint32_t prevlast = 0;
     uint64_t sm[5] = {0, 0, 0, 0, 0};
-    uint64_t* deep = DEEP + tid;
+    Deep<false> deep(nullptr, 0);  // energy counters in registers
     uint64_t f0 = 0, f1 = 0, f2 = 0;
 
     if (!helper) {
@@ -659,15 +688,15 @@ k_sweep_helped(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __rest
             segment(s0 + 2, I2{}, R1{}, true, true);
             segment(s0 + 3, I3{}, R1{}, true, true);
             if (kE) {
-                add_deep(deep, kHelpCols, sm);
-                if ((gq % kFlushMacros) == kFlushMacros - 1) flush_deep(deep, kHelpCols, Ublk, true);
+                add_deep(deep, sm);
+                if ((gq % kFlushMacros) == kFlushMacros - 1) flush_deep(deep, Ublk, true);
             }
         }
         segment(half, I0{}, R1{}, false, true);
         segment(half + 1, I1{}, R1{}, false, true);
         if (kE) {
-            add_deep(deep, kHelpCols, sm);
-            flush_deep(deep, kHelpCols, Ublk, true);
+            add_deep(deep, sm);
+            flush_deep(deep, Ublk, true);
         }
     } else {
         for (int gq = 0; gq < nq; ++gq) {
@@ -677,15 +706,15 @@ k_sweep_helped(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __rest
             segment(s0 + 2, I2{}, R0{}, true, true);
             segment(s0 + 3, I3{}, R0{}, true, true);
             if (kE) {
-                add_deep(deep, kHelpCols, sm);
-                if ((gq % kFlushMacros) == kFlushMacros - 1) flush_deep(deep, kHelpCols, Ublk, true);
+                add_deep(deep, sm);
+                if ((gq % kFlushMacros) == kFlushMacros - 1) flush_deep(deep, Ublk, true);
             }
         }
         segment(half, I0{}, R0{}, false, true);
         segment(half + 1, I1{}, R0{}, false, true);
         if (kE) {
-            add_deep(deep, kHelpCols, sm);
-            flush_deep(deep, kHelpCols, Ublk, true);
+            add_deep(deep, sm);
+            flush_deep(deep, Ublk, true);
         }
     }
     if (kE) {
@@ -696,12 +725,13 @@ k_sweep_helped(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __rest
 
 // One configuration per workgroup (r, w, j) = blockIdx.x.
 // kOcc: minimum waves per SIMD the register allocation must allow (1 = no
-// constraint); a tuning knob, the results do not depend on it.
+// constraint); a tuning knob, the results do not depend on it.  Above 1 the
+// energy counters move to LDS to fit the smaller register budget.
 template <bool kE, int kOcc>
 __global__ void __launch_bounds__(kMaxCols) __attribute__((amdgpu_waves_per_eu(kOcc)))
 k_sweep_stream(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __restrict__ ctr) {
     extern __shared__ uint64_t lds[];
-    sweep_teams<kE, false>(sh, (int)blockIdx.x, 1, 1, (int)blockDim.x, lds, key0, key1, ctr->t);
+    sweep_teams<kE, false, (kOcc > 1)>(sh, (int)blockIdx.x, 1, 1, (int)blockDim.x, lds, key0, key1, ctr->t);
 }
 
 // Persistent sweep of every shape of a plan in one launch.  Work items
@@ -728,7 +758,7 @@ k_sweep_batch(BatchArgs a) {
         const int s = (int)(lo & 0xFFu), g = (int)((lo >> 8) & 0xFFu), nlive = (int)((lo >> 16) & 0xFFu);
         const ShapeDev& sh = a.shapes[s];
         const uint32_t t = __builtin_amdgcn_readfirstlane(a.ctr[s].t);
-        sweep_teams<true, true>(sh, cfg0, g, nlive, stream_cols(sh), lds, a.key0, a.key1, t);
+        sweep_teams<true, true, false>(sh, cfg0, g, nlive, stream_cols(sh), lds, a.key0, a.key1, t);
     }
     if (threadIdx.x == 0) {
         __threadfence();
@@ -741,9 +771,10 @@ k_sweep_batch(BatchArgs a) {
 
 }  // namespace
 
-size_t sweep_stream_lds_bytes(const ShapeDev& sh, int teams, int threads) {
+size_t sweep_stream_lds_bytes(const ShapeDev& sh, int teams, int threads, bool deep_in_lds) {
     const size_t nbt = (size_t)stream_nbt(sh);
-    return ((nbt + 1) / 2 + (size_t)kDeep * threads + (size_t)teams * stream_team_words(sh)) * 8;
+    return ((nbt + 1) / 2 + (deep_in_lds ? (size_t)kDeep * threads : 0) +
+            (size_t)teams * stream_team_words(sh)) * 8;
 }
 
 int sweep_stream_cols(const ShapeDev& sh) { return stream_cols(sh); }
@@ -764,7 +795,7 @@ static hipError_t allow_lds(const void* fn, size_t bytes, size_t& done) {
 template <bool kE, int kOcc>
 static hipError_t prepare_one(const ShapeDev& sh) {
     static size_t lds_set = 0;
-    return allow_lds((const void*)k_sweep_stream<kE, kOcc>, sweep_stream_lds_bytes(sh, 1, stream_cols(sh)),
+    return allow_lds((const void*)k_sweep_stream<kE, kOcc>, sweep_stream_lds_bytes(sh, 1, stream_cols(sh), kOcc > 1),
                      lds_set);
 }
 
@@ -777,7 +808,7 @@ template <bool kE, int kOcc>
 static hipError_t launch_one(const ShapeDev& sh, uint64_t seed, const Counters* ctr, hipStream_t st) {
     const int nblk = sh.R * sh.nk * sh.W;
     const int threads = stream_cols(sh);
-    const size_t lds = sweep_stream_lds_bytes(sh, 1, threads);
+    const size_t lds = sweep_stream_lds_bytes(sh, 1, threads, kOcc > 1);
     hipError_t e = prepare_one<kE, kOcc>(sh);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_sweep_stream<kE, kOcc>), dim3(nblk), dim3(threads), lds, st, sh,

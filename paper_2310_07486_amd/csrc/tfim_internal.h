@@ -156,8 +156,9 @@ hipError_t launch_sweep_helped(const ShapeDev& sh, uint64_t seed, const Counters
 hipError_t prepare_sweep_helped(const ShapeDev& sh, bool energy);
 bool sweep_stream_ok(const ShapeDev& sh);
 // LDS of a streaming-sweep block of `teams` configurations and `threads`
-// threads; threads per configuration (L^2 rounded up to whole waves).
-size_t sweep_stream_lds_bytes(const ShapeDev& sh, int teams, int threads);
+// threads (deep_in_lds: the energy counters are kept in LDS, not registers);
+// threads per configuration (L^2 rounded up to whole waves).
+size_t sweep_stream_lds_bytes(const ShapeDev& sh, int teams, int threads, bool deep_in_lds);
 int sweep_stream_cols(const ShapeDev& sh);
 // Batched persistent sweep: allow its LDS and report resident blocks per CU
 // (occ: 1 or 2 = minimum waves per SIMD the kernel was compiled for).

@@ -68,7 +68,8 @@ constexpr uint32_t kOr3 = (kA | kB | kC) & 0xFF;
 constexpr uint32_t kAorBandC = (kA | (kB & kC)) & 0xFF;       // a | (b & c)
 constexpr uint32_t kAandBorC = ((kA & kB) | kC) & 0xFF;       // (a & b) | c
 constexpr uint32_t kAxorBorC = (kA ^ (kB | kC)) & 0xFF;       // a ^ (b | c)
-constexpr uint32_t kBothIfC = ((~kA & ~kB & kC) | (kA & kB & ~kC)) & 0xFF;  // c ? ~a&~b : a&b
+constexpr uint32_t kAxorBandNotC = (kA ^ (kB & ~kC)) & 0xFF;      // a ^ (b & ~c)
+constexpr uint32_t kAandNotBandNotC = (kA & ~kB & ~kC) & 0xFF;    // a & ~b & ~c
 
 template <uint32_t IMM>
 __device__ __forceinline__ uint64_t b3(uint64_t a, uint64_t b, uint64_t c) {
@@ -116,7 +117,7 @@ struct Tables {
 // The threshold is read first, then only the mask it selects (12 bytes of
 // LDS per lane instead of 20): entry 2a + (R < T) of M.  The index is the
 // borrow of R - T carried into a + a, two ALU instructions.
-__device__ __forceinline__ uint64_t lane_mask(const Tables& tb, int u, uint32_t R) {
+__device__ __forceinline__ uint32_t mask_index(const Tables& tb, int u, uint32_t R) {
     const uint32_t a = min(R >> tb.sh[u], tb.nb[u]);
     const uint32_t T = tb.T[u][a];
     uint32_t diff, idx;
@@ -124,7 +125,11 @@ __device__ __forceinline__ uint64_t lane_mask(const Tables& tb, int u, uint32_t 
         : "=&v"(diff), "=v"(idx)
         : "v"(R), "v"(T), "v"(a)
         : "vcc");
-    return tb.M[u][idx];
+    return idx;
+}
+
+__device__ __forceinline__ uint64_t lane_mask(const Tables& tb, int u, uint32_t R) {
+    return tb.M[u][mask_index(tb, u, R)];
 }
 
 // One site of 64 lanes given the three lane masks m_u = {lanes : R <
@@ -145,26 +150,25 @@ __device__ __forceinline__ uint64_t site_m(uint64_t s, const Nb& n, uint64_t jxp
     const uint64_t c1 = b3<kMaj>(p1, p2, p3);
     const uint64_t s2 = b3<kXor3>(p4, p5, p6);
     const uint64_t c2 = b3<kMaj>(p4, p5, p6);
-    const uint64_t so = s1 | s2;
-    const uint64_t co = c1 | c2;
-    const uint64_t ge1 = so | co;                     // u >= 1
-    const uint64_t ge2 = b3<kAorBandC>(co, s1, s2);   // u >= 2
-    const uint64_t ge3 = b3<kMaj>(c1, c2, so);        // u >= 3
-    // masks are nested (m0 in m1 in m2): flip = ge3 | ge2&m2 | ge1&m1 | m0
-    const uint64_t t1 = b3<kAandBorC>(ge2, m2, m0);
-    const uint64_t t2 = b3<kAandBorC>(ge1, m1, t1);
+    // u = s1 + s2 + 2 (c1 + c2) = u0 + 2 u1 + 4 u2
+    const uint64_t u0 = s1 ^ s2;
+    const uint64_t h = s1 & s2;
+    const uint64_t u1 = b3<kXor3>(c1, c2, h);
+    const uint64_t u2 = b3<kMaj>(c1, c2, h);
+    // masks are nested (m0 in m1 in m2): flip = u2 | u1 (u0 | m2) | u0 m1 | m0
+    const uint64_t w1 = b3<kAandBorC>(u0, m1, m0);
+    const uint64_t w2 = u0 | m2;
+    const uint64_t w3 = b3<kAandBorC>(u1, w2, w1);
     if constexpr (kE) {
-        const uint64_t f = ge3 | t2;
-        // after the move the six parities toggle where flipped: counts are
-        // (s1^f) + (s2^f) + 2 (c1^f) + 2 (c2^f)
-        const uint64_t y1 = b3<kBothIfC>(s1, s2, f);  // (s1^f) & (s2^f)
-        const uint64_t y2 = b3<kBothIfC>(c1, c2, f);  // (c1^f) & (c2^f)
-        const uint64_t x2 = c1 ^ c2;
-        f0 = s1 ^ s2;
-        f1 = x2 ^ y1;
-        f2 = b3<kAorBandC>(y2, x2, y1);
+        // the final count is u, or 6 - u where the site flipped: the same
+        // parity; bit 1 of 6 - u is XNOR(u0, u1), bit 2 is set iff u <= 2
+        const uint64_t f = u2 | w3;
+        f0 = u0;
+        f1 = b3<kAxorBandNotC>(u1, f, u0);          // u1 ^ (f & ~u0)
+        f2 = b3<kAandNotBandNotC>(f, u2, u1 & u0);  // f & ~u2 & ~(u1 & u0)
+        return s ^ f;
     }
-    return b3<kAxorBorC>(s, ge3, t2);  // s ^ flip
+    return b3<kAxorBorC>(s, u2, w3);  // s ^ flip
 }
 
 // The same with the masks looked up for the uniform R.
@@ -467,15 +471,17 @@ __device__ __forceinline__ void sweep_teams(const ShapeDev& sh, const int cfg0, 
 // half again the work of the others.  Three helper waves (9, 10, 11, one on
 // each other SIMD) take over the uniforms and the lane-mask lookups of those
 // three waves: one segment ahead, helper 9 + h runs the same Philox sequence
-// as column wave 4h would, lane for lane, and leaves the six masks of the
-// next segment's two sites in LDS.  Every role runs the same segments and
-// barriers; results are bit-identical to k_sweep_stream.
+// as column wave 4h would, lane for lane, compares each uniform with its
+// bucket threshold and leaves the six mask indices of the next segment's two
+// sites in LDS; the served wave reads the masks themselves.  Every role runs
+// the same segments and barriers; results are bit-identical to
+// k_sweep_stream.
 constexpr int kHelpedThreads = 768;
 constexpr int kColWaves = 9;
 constexpr int kHelpCols = kColWaves * 64;  // 576
 
 __host__ __device__ inline int helped_words(const ShapeDev& sh) {
-    return (stream_nbt(sh) + 1) / 2 + stream_team_words(sh) + 2 * 3 * 64 * 6;
+    return (stream_nbt(sh) + 1) / 2 + stream_team_words(sh) + (2 * 3 * 6 * 64) / 2;
 }
 
 template <bool kE>
@@ -496,7 +502,7 @@ k_sweep_helped(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __rest
     uint64_t* ml = X + 4 * L2;
     uint64_t* MM = ml + nk + 1;
     uint32_t* Ublk = (uint32_t*)(MM + 2 * nbt);
-    uint64_t* HM = MM + 2 * nbt + 32;  // [2][3][6][64] masks of the served waves
+    uint32_t* HM = (uint32_t*)(MM + 2 * nbt + 32);  // [2][3][6][64] mask indices for the served waves
     const int H = L2;
 
     const int cfg = blockIdx.x;  // ((r*nk + w)*W + j)
@@ -553,7 +559,7 @@ k_sweep_helped(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __rest
     auto ld = [&](int P) -> uint64_t { return buf_load(spins, voff, wrap(min(P, Lt + 1)) * plane); };
     auto ld_lane = [&](int P) -> uint64_t { return buf_load(spins, voff + wrap(P) * plane, 0); };
     // [buffer][helper][mask][lane]: lane-contiguous, so every access is conflict-free
-    auto hm = [&](int buf, int k) -> uint64_t* { return HM + ((buf * 3 + h) * 6 + k) * 64 + lane; };
+    auto hm = [&](int buf, int k) -> uint32_t* { return HM + ((buf * 3 + h) * 6 + k) * 64 + lane; };
 
     uint64_t w0 = 0, w1 = 0, w2 = 0, w3 = 0, w4 = 0, w5 = 0, pf0 = 0, pf1 = 0, nx0 = 0, nx1 = 0, pu1 = 0;
     if (!helper) {
@@ -575,9 +581,9 @@ k_sweep_helped(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __rest
     } else {
         // masks of segment 0 (colour 0, group 0) for the served lane
         G0 = philox_dev((uint32_t)xy, t, c2_0, c3, key0, key1);
-        *hm(0, 0) = lane_mask(tb, 0, G0.v[0]);
-        *hm(0, 1) = lane_mask(tb, 1, G0.v[0]);
-        *hm(0, 2) = lane_mask(tb, 2, G0.v[0]);
+        *hm(0, 0) = mask_index(tb, 0, G0.v[0]);
+        *hm(0, 1) = mask_index(tb, 1, G0.v[0]);
+        *hm(0, 2) = mask_index(tb, 2, G0.v[0]);
     }
     __syncthreads();
 
@@ -599,9 +605,9 @@ k_sweep_helped(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __rest
                     if (ISn == 0)
                         G0 = philox_dev((uint32_t)(xy + L2 * (sn >> 2)), t, c2_0, c3, key0, key1);
                     const uint32_t R0 = G0.v[ISn];
-                    *hm(ISn & 1, 0) = lane_mask(tb, 0, R0);
-                    *hm(ISn & 1, 1) = lane_mask(tb, 1, R0);
-                    *hm(ISn & 1, 2) = lane_mask(tb, 2, R0);
+                    *hm(ISn & 1, 0) = mask_index(tb, 0, R0);
+                    *hm(ISn & 1, 1) = mask_index(tb, 1, R0);
+                    *hm(ISn & 1, 2) = mask_index(tb, 2, R0);
                 }
                 if (ISn == 1 && sn <= half + 1) {
                     prevlast = G1.v[3];
@@ -612,9 +618,9 @@ k_sweep_helped(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __rest
                 if (sn >= 2 && sn <= half + 1) {
                     constexpr int S3 = (ISn + 3) & 3;
                     const uint32_t R1 = p ? G1.v[S3] : (S3 == 0 ? prevlast : G1.v[(S3 + 3) & 3]);
-                    *hm(ISn & 1, 3) = lane_mask(tb, 0, R1);
-                    *hm(ISn & 1, 4) = lane_mask(tb, 1, R1);
-                    *hm(ISn & 1, 5) = lane_mask(tb, 2, R1);
+                    *hm(ISn & 1, 3) = mask_index(tb, 0, R1);
+                    *hm(ISn & 1, 4) = mask_index(tb, 1, R1);
+                    *hm(ISn & 1, 5) = mask_index(tb, 2, R1);
                 }
                 __syncthreads();
                 return;
@@ -633,8 +639,8 @@ k_sweep_helped(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __rest
                             G0 = philox_dev((uint32_t)(xy + L2 * (sigma >> 2)), t, c2_0, c3, key0, key1);
                         w4 = site<false>(w4, n, jxp, jxm, jyp, jym, w5, w3, G0.v[IS], tb, d0, d1, d2);
                     } else {
-                        w4 = site_m<false>(w4, n, jxp, jxm, jyp, jym, w5, w3, *hm(IS & 1, 0), *hm(IS & 1, 1),
-                                           *hm(IS & 1, 2), d0, d1, d2);
+                        w4 = site_m<false>(w4, n, jxp, jxm, jyp, jym, w5, w3, tb.M[0][*hm(IS & 1, 0)],
+                                           tb.M[1][*hm(IS & 1, 1)], tb.M[2][*hm(IS & 1, 2)], d0, d1, d2);
                     }
                 }
                 if constexpr (kRole == 0) {
@@ -653,8 +659,8 @@ k_sweep_helped(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __rest
                         const uint32_t R1 = p ? G1.v[S3] : (S3 == 0 ? prevlast : G1.v[(S3 + 3) & 3]);
                         w1 = site<kE>(w1, n, jxp, jxm, jyp, jym, w2, w0, R1, tb, f0, f1, f2);
                     } else {
-                        w1 = site_m<kE>(w1, n, jxp, jxm, jyp, jym, w2, w0, *hm(IS & 1, 3), *hm(IS & 1, 4),
-                                        *hm(IS & 1, 5), f0, f1, f2);
+                        w1 = site_m<kE>(w1, n, jxp, jxm, jyp, jym, w2, w0, tb.M[0][*hm(IS & 1, 3)],
+                                        tb.M[1][*hm(IS & 1, 4)], tb.M[2][*hm(IS & 1, 5)], f0, f1, f2);
                     }
                     if (kE) add3v(sm, f0, f1, f2);
                 }

@@ -83,8 +83,11 @@ __device__ __forceinline__ uint32_t xor3_32(uint32_t a, uint32_t b, uint32_t c) 
     return __builtin_amdgcn_bitop3_b32(a, b, c, kXor3);
 }
 
-// Philox4x32-10 with three-input XORs (same function as philox10).
-__device__ __forceinline__ U4 philox_dev(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+// Philox4x32-10 with three-input XORs (same function as philox10).  The
+// four outputs are one vector value, so a parity select between two of them
+// stays in registers.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ u32x4 philox_dev(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                          uint32_t key0, uint32_t key1) {
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
@@ -99,8 +102,11 @@ __device__ __forceinline__ U4 philox_dev(uint32_t c0, uint32_t c1, uint32_t c2, 
         key0 += 0x9E3779B9u;
         key1 += 0xBB67AE85u;
     }
-    U4 r;
-    r.v[0] = c0; r.v[1] = c1; r.v[2] = c2; r.v[3] = c3;
+    u32x4 r;
+    r.x = c0;
+    r.y = c1;
+    r.z = c2;
+    r.w = c3;
     return r;
 }
 
@@ -379,7 +385,7 @@ __device__ __forceinline__ void sweep_teams(const ShapeDev& sh, const int cfg0, 
     pf0 = ld_lane(min(p + 2, Lt + 1));
     pf1 = ld_lane(min(p + 3, Lt + 1));
     uint64_t pu1 = ld(4);  // plane 2 sigma + 4 of the next segment for parity 0
-    U4 G0, G1;
+    u32x4 G0 = 0, G1 = 0;
     uint32_t prevlast = 0;
     uint64_t sm[5] = {0, 0, 0, 0, 0};
     Deep<kDeepLds> deep(DEEP + tid, nthr);
@@ -409,17 +415,17 @@ __device__ __forceinline__ void sweep_teams(const ShapeDev& sh, const int cfg0, 
             const uint64_t* Xb = X + (IS & 1) * H;
             const Nb n{Xb[hxp], Xb[hxm], Xb[hyp], Xb[hym]};
             uint64_t d0, d1, d2;
-            w4 = site<false>(w4, n, jxp, jxm, jyp, jym, w5, w3, G0.v[IS], tb, d0, d1, d2);
+            w4 = site<false>(w4, n, jxp, jxm, jyp, jym, w5, w3, G0[IS], tb, d0, d1, d2);
         }
         if (IS == 1) {  // colour-1 Philox group of step s = sigma - 1 (s % 4 == 0)
-            prevlast = G1.v[3];
+            prevlast = G1[3];
             int q = (sigma - 1) >> 2;
             if (q >= nq) q -= nq;
             G1 = philox_dev((uint32_t)(xy + L2 * q), t, c2_1, c3, key0, key1);
         }
         if (do_c1) {
             constexpr int S3 = (IS + 3) & 3;  // (sigma - 1) & 3
-            const uint32_t R1 = p ? G1.v[S3] : (S3 == 0 ? prevlast : G1.v[(S3 + 3) & 3]);
+            const uint32_t R1 = p ? G1[S3] : (S3 == 0 ? prevlast : G1[(S3 + 3) & 3]);
             const uint64_t* Yb = Y + ((IS + 1) & 1) * H;
             const Nb n{Yb[hxp], Yb[hxm], Yb[hyp], Yb[hym]};
             w1 = site<kE>(w1, n, jxp, jxm, jyp, jym, w2, w0, R1, tb, f0, f1, f2);
@@ -476,6 +482,10 @@ __device__ __forceinline__ void sweep_teams(const ShapeDev& sh, const int cfg0, 
 // sites in LDS; the served wave reads the masks themselves.  Every role runs
 // the same segments and barriers; results are bit-identical to
 // k_sweep_stream.
+// Loads: until the last group no tau plane wraps, so each lane loads its own
+// parity's two planes directly (no select that would wait for them at once),
+// one segment earlier than the whole-plane form: a load is first used two
+// segments after it is issued, which hides HBM latency under full load.
 constexpr int kHelpedThreads = 768;
 constexpr int kColWaves = 9;
 constexpr int kHelpCols = kColWaves * 64;  // 576
@@ -553,6 +563,7 @@ k_sweep_helped(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __rest
         (void*)(((uint64_t)base_hi << 32) | base_lo), (short)0, Lt * L2 * 8, kBufferWord3);
     const int voff = 8 * xy;
     const int plane = 8 * L2;
+    const int voffp = voff + p * plane;  // the thread's parity plane in the vector offset
     const int half = Lt >> 1;
     const int nq = Lt >> 3;
     auto wrap = [Lt](int P) { return P >= Lt ? P - Lt : (P < 0 ? P + Lt : P); };
@@ -562,6 +573,7 @@ k_sweep_helped(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __rest
     auto hm = [&](int buf, int k) -> uint32_t* { return HM + ((buf * 3 + h) * 6 + k) * 64 + lane; };
 
     uint64_t w0 = 0, w1 = 0, w2 = 0, w3 = 0, w4 = 0, w5 = 0, pf0 = 0, pf1 = 0, nx0 = 0, nx1 = 0, pu1 = 0;
+    uint64_t nn0 = 0, nn1 = 0;  // planes A + 4, A + 5 of the next segment (steady state)
     if (!helper) {
         w3 = ld_lane(p - 1);
         w4 = ld_lane(p);
@@ -569,8 +581,10 @@ k_sweep_helped(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __rest
         pf0 = ld_lane(min(p + 2, Lt + 1));
         pf1 = ld_lane(min(p + 3, Lt + 1));
         pu1 = ld(4);
+        nn0 = ld_lane(p + 4);
+        nn1 = ld_lane(p + 5);
     }
-    U4 G0, G1;
+    u32x4 G0 = 0, G1 = 0;
     uint32_t prevlast = 0;
     uint64_t sm[5] = {0, 0, 0, 0, 0};
     Deep<false> deep(nullptr, 0);  // energy counters in registers
@@ -581,9 +595,9 @@ k_sweep_helped(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __rest
     } else {
         // masks of segment 0 (colour 0, group 0) for the served lane
         G0 = philox_dev((uint32_t)xy, t, c2_0, c3, key0, key1);
-        *hm(0, 0) = mask_index(tb, 0, G0.v[0]);
-        *hm(0, 1) = mask_index(tb, 1, G0.v[0]);
-        *hm(0, 2) = mask_index(tb, 2, G0.v[0]);
+        *hm(0, 0) = mask_index(tb, 0, G0[0]);
+        *hm(0, 1) = mask_index(tb, 1, G0[0]);
+        *hm(0, 2) = mask_index(tb, 2, G0[0]);
     }
     __syncthreads();
 
@@ -594,9 +608,11 @@ k_sweep_helped(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __rest
 
     // kRole 0: column wave that looks up its own masks; 1: column wave fed by
     // a helper; 2: helper.  All roles run the same segments and barriers.
-    auto segment = [&](const int sigma, const auto ISc, const auto roleC, const bool do_c0, const bool do_c1) {
+    auto segment = [&](const int sigma, const auto ISc, const auto roleC, const auto bulkC, const bool do_c0,
+                       const bool do_c1) {
             constexpr int kRole = decltype(roleC)::value;
             constexpr int IS = decltype(ISc)::value;
+            constexpr bool kBulk = decltype(bulkC)::value;
             if constexpr (kRole == 2) {
                 // the next segment's masks for the served lane
                 constexpr int ISn = (IS + 1) & 3;
@@ -604,20 +620,20 @@ k_sweep_helped(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __rest
                 if (sn < half) {
                     if (ISn == 0)
                         G0 = philox_dev((uint32_t)(xy + L2 * (sn >> 2)), t, c2_0, c3, key0, key1);
-                    const uint32_t R0 = G0.v[ISn];
+                    const uint32_t R0 = G0[ISn];
                     *hm(ISn & 1, 0) = mask_index(tb, 0, R0);
                     *hm(ISn & 1, 1) = mask_index(tb, 1, R0);
                     *hm(ISn & 1, 2) = mask_index(tb, 2, R0);
                 }
                 if (ISn == 1 && sn <= half + 1) {
-                    prevlast = G1.v[3];
+                    prevlast = G1[3];
                     int q = (sn - 1) >> 2;
                     if (q >= nq) q -= nq;
                     G1 = philox_dev((uint32_t)(xy + L2 * q), t, c2_1, c3, key0, key1);
                 }
                 if (sn >= 2 && sn <= half + 1) {
                     constexpr int S3 = (ISn + 3) & 3;
-                    const uint32_t R1 = p ? G1.v[S3] : (S3 == 0 ? prevlast : G1.v[(S3 + 3) & 3]);
+                    const uint32_t R1 = p ? G1[S3] : (S3 == 0 ? prevlast : G1[(S3 + 3) & 3]);
                     *hm(ISn & 1, 3) = mask_index(tb, 0, R1);
                     *hm(ISn & 1, 4) = mask_index(tb, 1, R1);
                     *hm(ISn & 1, 5) = mask_index(tb, 2, R1);
@@ -625,11 +641,20 @@ k_sweep_helped(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __rest
                 __syncthreads();
                 return;
             } else {
-                const int A = 2 * sigma + p;
-                const uint64_t u0 = ld(2 * sigma + 5), u1 = ld(2 * sigma + 6);
-                nx0 = p ? u0 : pu1;
-                nx1 = p ? u1 : u0;
-                pu1 = u1;
+                if constexpr (kBulk) {
+                    // no plane wraps before the last group: each lane loads its
+                    // own parity's planes, A + 6 and A + 7, a segment ahead
+                    nx0 = nn0;
+                    nx1 = nn1;
+                    nn0 = buf_load(spins, voffp, (2 * sigma + 6) * plane);
+                    nn1 = buf_load(spins, voffp, (2 * sigma + 7) * plane);
+                } else {
+                    // whole planes 2 sigma + 5 and 2 sigma + 6, parity selected
+                    const uint64_t u0 = ld(2 * sigma + 5), u1 = ld(2 * sigma + 6);
+                    nx0 = p ? u0 : pu1;
+                    nx1 = p ? u1 : u0;
+                    pu1 = u1;
+                }
                 if (do_c0) {
                     const uint64_t* Xb = X + (IS & 1) * H;
                     const Nb n{Xb[hxp], Xb[hxm], Xb[hyp], Xb[hym]};
@@ -637,7 +662,7 @@ k_sweep_helped(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __rest
                     if constexpr (kRole == 0) {
                         if (IS == 0)
                             G0 = philox_dev((uint32_t)(xy + L2 * (sigma >> 2)), t, c2_0, c3, key0, key1);
-                        w4 = site<false>(w4, n, jxp, jxm, jyp, jym, w5, w3, G0.v[IS], tb, d0, d1, d2);
+                        w4 = site<false>(w4, n, jxp, jxm, jyp, jym, w5, w3, G0[IS], tb, d0, d1, d2);
                     } else {
                         w4 = site_m<false>(w4, n, jxp, jxm, jyp, jym, w5, w3, tb.M[0][*hm(IS & 1, 0)],
                                            tb.M[1][*hm(IS & 1, 1)], tb.M[2][*hm(IS & 1, 2)], d0, d1, d2);
@@ -645,7 +670,7 @@ k_sweep_helped(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __rest
                 }
                 if constexpr (kRole == 0) {
                     if (IS == 1) {  // colour-1 Philox group of step s = sigma - 1 (s % 4 == 0)
-                        prevlast = G1.v[3];
+                        prevlast = G1[3];
                         int q = (sigma - 1) >> 2;
                         if (q >= nq) q -= nq;
                         G1 = philox_dev((uint32_t)(xy + L2 * q), t, c2_1, c3, key0, key1);
@@ -656,7 +681,7 @@ k_sweep_helped(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __rest
                     const Nb n{Yb[hxp], Yb[hxm], Yb[hyp], Yb[hym]};
                     if constexpr (kRole == 0) {
                         constexpr int S3 = (IS + 3) & 3;  // (sigma - 1) & 3
-                        const uint32_t R1 = p ? G1.v[S3] : (S3 == 0 ? prevlast : G1.v[(S3 + 3) & 3]);
+                        const uint32_t R1 = p ? G1[S3] : (S3 == 0 ? prevlast : G1[(S3 + 3) & 3]);
                         w1 = site<kE>(w1, n, jxp, jxm, jyp, jym, w2, w0, R1, tb, f0, f1, f2);
                     } else {
                         w1 = site_m<kE>(w1, n, jxp, jxm, jyp, jym, w2, w0, tb.M[0][*hm(IS & 1, 3)],
@@ -676,52 +701,48 @@ k_sweep_helped(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __rest
     using R0 = std::integral_constant<int, 0>;
     using R1 = std::integral_constant<int, 1>;
     using R2 = std::integral_constant<int, 2>;
+    using B0 = std::false_type;
+    using B1 = std::true_type;
     if (helper) {
         for (int gq = 0; gq < nq; ++gq) {
             const int s0 = 4 * gq;
-            segment(s0 + 0, I0{}, R2{}, true, gq > 0);
-            segment(s0 + 1, I1{}, R2{}, true, gq > 0);
-            segment(s0 + 2, I2{}, R2{}, true, true);
-            segment(s0 + 3, I3{}, R2{}, true, true);
+            segment(s0 + 0, I0{}, R2{}, B0{}, true, gq > 0);
+            segment(s0 + 1, I1{}, R2{}, B0{}, true, gq > 0);
+            segment(s0 + 2, I2{}, R2{}, B0{}, true, true);
+            segment(s0 + 3, I3{}, R2{}, B0{}, true, true);
         }
-        segment(half, I0{}, R2{}, false, true);
-        segment(half + 1, I1{}, R2{}, false, true);
-    } else if ((wave & 3) == 0) {
-        for (int gq = 0; gq < nq; ++gq) {
-            const int s0 = 4 * gq;
-            segment(s0 + 0, I0{}, R1{}, true, gq > 0);
-            segment(s0 + 1, I1{}, R1{}, true, gq > 0);
-            segment(s0 + 2, I2{}, R1{}, true, true);
-            segment(s0 + 3, I3{}, R1{}, true, true);
-            if (kE) {
-                add_deep(deep, sm);
-                if ((gq % kFlushMacros) == kFlushMacros - 1) flush_deep(deep, Ublk, true);
-            }
-        }
-        segment(half, I0{}, R1{}, false, true);
-        segment(half + 1, I1{}, R1{}, false, true);
-        if (kE) {
-            add_deep(deep, sm);
-            flush_deep(deep, Ublk, true);
-        }
+        segment(half, I0{}, R2{}, B0{}, false, true);
+        segment(half + 1, I1{}, R2{}, B0{}, false, true);
     } else {
-        for (int gq = 0; gq < nq; ++gq) {
-            const int s0 = 4 * gq;
-            segment(s0 + 0, I0{}, R0{}, true, gq > 0);
-            segment(s0 + 1, I1{}, R0{}, true, gq > 0);
-            segment(s0 + 2, I2{}, R0{}, true, true);
-            segment(s0 + 3, I3{}, R0{}, true, true);
+        // column waves, fed by a helper (wave 4h) or self-served.  The last
+        // group and the tail reach the tau wrap: they load whole planes.
+        auto columns = [&](const auto roleC) {
+            for (int gq = 0; gq < nq - 1; ++gq) {
+                const int s0 = 4 * gq;
+                segment(s0 + 0, I0{}, roleC, B1{}, true, gq > 0);
+                segment(s0 + 1, I1{}, roleC, B1{}, true, gq > 0);
+                segment(s0 + 2, I2{}, roleC, B1{}, true, true);
+                segment(s0 + 3, I3{}, roleC, B1{}, true, true);
+                if (kE) {
+                    add_deep(deep, sm);
+                    if ((gq % kFlushMacros) == kFlushMacros - 1) flush_deep(deep, Ublk, true);
+                }
+            }
+            const int s0 = 4 * (nq - 1);
+            pu1 = ld(2 * s0 + 4);
+            segment(s0 + 0, I0{}, roleC, B0{}, true, nq > 1);
+            segment(s0 + 1, I1{}, roleC, B0{}, true, nq > 1);
+            segment(s0 + 2, I2{}, roleC, B0{}, true, true);
+            segment(s0 + 3, I3{}, roleC, B0{}, true, true);
+            segment(half, I0{}, roleC, B0{}, false, true);
+            segment(half + 1, I1{}, roleC, B0{}, false, true);
             if (kE) {
                 add_deep(deep, sm);
-                if ((gq % kFlushMacros) == kFlushMacros - 1) flush_deep(deep, Ublk, true);
+                flush_deep(deep, Ublk, true);
             }
-        }
-        segment(half, I0{}, R0{}, false, true);
-        segment(half + 1, I1{}, R0{}, false, true);
-        if (kE) {
-            add_deep(deep, sm);
-            flush_deep(deep, Ublk, true);
-        }
+        };
+        if ((wave & 3) == 0) columns(R1{});
+        else columns(R0{});
     }
     if (kE) {
         __syncthreads();

@@ -385,6 +385,9 @@ __device__ __forceinline__ void sweep_teams(const ShapeDev& sh, const int cfg0, 
     pf0 = ld_lane(min(p + 2, Lt + 1));
     pf1 = ld_lane(min(p + 3, Lt + 1));
     uint64_t pu1 = ld(4);  // plane 2 sigma + 4 of the next segment for parity 0
+    // steady state: planes A + 4, A + 5 of the next segment, already in flight
+    const int voffp = voff + p * plane;
+    uint64_t nn0 = ld_lane(p + 4), nn1 = ld_lane(p + 5);
     u32x4 G0 = 0, G1 = 0;
     uint32_t prevlast = 0;
     uint64_t sm[5] = {0, 0, 0, 0, 0};
@@ -396,20 +399,30 @@ __device__ __forceinline__ void sweep_teams(const ShapeDev& sh, const int cfg0, 
 
     // one segment; IS = sigma & 3 is a compile-time constant.  Waves outside
     // every team (member is wave-uniform) only take part in the barrier.
-    auto segment = [&](const int sigma, const auto ISc, const bool do_c0, const bool do_c1) {
+    auto segment = [&](const int sigma, const auto ISc, const auto bulkC, const bool do_c0, const bool do_c1) {
         constexpr int IS = decltype(ISc)::value;
+        constexpr bool kBulk = decltype(bulkC)::value;
         if (!member) {
             __syncthreads();
             return;
         }
-        const int A = 2 * sigma + p;
-        // every load instruction reads whole planes 2 sigma + 5 and 2 sigma + 6
-        // (all columns, full cache lines); a thread keeps the two planes of
-        // its parity, A + 4 and A + 5
-        const uint64_t u0 = ld(2 * sigma + 5), u1 = ld(2 * sigma + 6);
-        nx0 = p ? u0 : pu1;
-        nx1 = p ? u1 : u0;
-        pu1 = u1;
+        if constexpr (kBulk) {
+            // no plane wraps before the last group: each lane loads its own
+            // parity's planes, A + 6 and A + 7, a segment ahead of their use
+            // as A + 4, A + 5 (no select that would wait for them at once)
+            nx0 = nn0;
+            nx1 = nn1;
+            nn0 = buf_load(spins, voffp, (2 * sigma + 6) * plane);
+            nn1 = buf_load(spins, voffp, (2 * sigma + 7) * plane);
+        } else {
+            // every load instruction reads whole planes 2 sigma + 5 and
+            // 2 sigma + 6 (all columns, full cache lines); a thread keeps the
+            // two planes of its parity, A + 4 and A + 5
+            const uint64_t u0 = ld(2 * sigma + 5), u1 = ld(2 * sigma + 6);
+            nx0 = p ? u0 : pu1;
+            nx1 = p ? u1 : u0;
+            pu1 = u1;
+        }
         if (do_c0) {
             if (IS == 0) G0 = philox_dev((uint32_t)(xy + L2 * (sigma >> 2)), t, c2_0, c3, key0, key1);
             const uint64_t* Xb = X + (IS & 1) * H;
@@ -449,19 +462,29 @@ __device__ __forceinline__ void sweep_teams(const ShapeDev& sh, const int cfg0, 
     using I2 = std::integral_constant<int, 2>;
     using I3 = std::integral_constant<int, 3>;
 
-    for (int gq = 0; gq < nq; ++gq) {
+    using B0 = std::false_type;
+    using B1 = std::true_type;
+    for (int gq = 0; gq < nq - 1; ++gq) {
         const int s0 = 4 * gq;
-        segment(s0 + 0, I0{}, true, gq > 0);
-        segment(s0 + 1, I1{}, true, gq > 0);
-        segment(s0 + 2, I2{}, true, true);
-        segment(s0 + 3, I3{}, true, true);
+        segment(s0 + 0, I0{}, B1{}, true, gq > 0);
+        segment(s0 + 1, I1{}, B1{}, true, gq > 0);
+        segment(s0 + 2, I2{}, B1{}, true, true);
+        segment(s0 + 3, I3{}, B1{}, true, true);
         if (kE && member) {
             add_deep(deep, sm);
             if ((gq % kFlushMacros) == kFlushMacros - 1) flush_deep(deep, Ublk, true);
         }
     }
-    segment(half, I0{}, false, true);      // colour 1, step half-1
-    segment(half + 1, I1{}, false, true);  // colour 1, step half == step 0 (tau wrap)
+    // the last group and the tail reach the tau wrap: whole-plane loads
+    const int sl = 4 * (nq - 1);
+    pu1 = ld(2 * sl + 4);
+    segment(sl + 0, I0{}, B0{}, true, nq > 1);
+    segment(sl + 1, I1{}, B0{}, true, nq > 1);
+    segment(sl + 2, I2{}, B0{}, true, true);
+    segment(sl + 3, I3{}, B0{}, true, true);
+    if (kE && member) add_deep(deep, sm);  // the 5-bit counters hold at most four sites
+    segment(half, I0{}, B0{}, false, true);      // colour 1, step half-1
+    segment(half + 1, I1{}, B0{}, false, true);  // colour 1, step half == step 0 (tau wrap)
     if (kE) {
         if (member) {
             add_deep(deep, sm);
@@ -734,6 +757,7 @@ k_sweep_helped(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __rest
             segment(s0 + 1, I1{}, roleC, B0{}, true, nq > 1);
             segment(s0 + 2, I2{}, roleC, B0{}, true, true);
             segment(s0 + 3, I3{}, roleC, B0{}, true, true);
+            if (kE) add_deep(deep, sm);  // the 5-bit counters hold at most four sites
             segment(half, I0{}, roleC, B0{}, false, true);
             segment(half + 1, I1{}, roleC, B0{}, false, true);
             if (kE) {

@@ -230,8 +230,10 @@ tfim_status tfim_set_schedule(tfim_plan *plan, uint32_t schedule);
  * most 768.  blocks_per_cu: resident workgroups per compute unit (0 = as
  * many as fit).  A configuration needs the shape's L^2 (rounded up to 64)
  * threads, and a workgroup sweeps as many configurations of one shape at
- * once as fit in its threads and LDS.  Bound plan only; TFIM_EINVAL for a
- * geometry that does not fit. */
+ * once as fit in its threads and LDS.  At 768 threads a shape with L^2 =
+ * 576 runs one configuration per workgroup with helper waves, as sweep
+ * variant 3 does.  Bound plan only; TFIM_EINVAL for a geometry that does not
+ * fit. */
 tfim_status tfim_set_batch(tfim_plan *plan, uint32_t threads, uint32_t blocks_per_cu);
 
 typedef struct {

@@ -669,6 +669,10 @@ static tfim_status batch_setup(tfim_plan* pl, uint32_t threads, uint32_t bpc) {
         if (tfim::sweep_stream_lds_bytes(d, g, (int)threads, false) > kLdsLimit)
             return fail(TFIM_EUNSUPPORTED, "batched workgroup does not fit in LDS");
         lds = std::max(lds, tfim::sweep_stream_lds_bytes(d, g, (int)threads, false));
+        if (threads == kMaxBatchThreads && tfim::sweep_helped_ok(d)) {
+            g = 1;  // the batched kernel runs these configurations with helper waves
+            lds = std::max(lds, tfim::sweep_helped_lds_bytes(d));
+        }
         const int ncfg = d.R * d.nk * d.W;
         for (int c0 = 0; c0 < ncfg; c0 += g) {
             const uint64_t live = (uint64_t)std::min(g, ncfg - c0);

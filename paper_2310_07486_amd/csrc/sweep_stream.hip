@@ -517,10 +517,11 @@ __host__ __device__ inline int helped_words(const ShapeDev& sh) {
     return (stream_nbt(sh) + 1) / 2 + stream_team_words(sh) + (2 * 3 * 6 * 64) / 2;
 }
 
+// The body for configuration cfg = ((r*nk + w)*W + j), by a workgroup of
+// kHelpedThreads threads; lds at least helped_words(sh) words.
 template <bool kE>
-__global__ void __launch_bounds__(kHelpedThreads)
-k_sweep_helped(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __restrict__ ctr) {
-    extern __shared__ uint64_t lds[];
+__device__ __forceinline__ void helped_body(const ShapeDev& sh, const int cfg, uint64_t* lds, const uint32_t key0,
+                                            const uint32_t key1, const uint32_t t) {
     const int L = sh.L, L2 = sh.L2, Lt = sh.Lt, nk = sh.nk, W = sh.W;
     const int nb0 = sh.bnb[0] + 1, nb1 = sh.bnb[1] + 1, nb2 = sh.bnb[2] + 1;
     const int nbt = nb0 + nb1 + nb2;
@@ -538,7 +539,6 @@ k_sweep_helped(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __rest
     uint32_t* HM = (uint32_t*)(MM + 2 * nbt + 32);  // [2][3][6][64] mask indices for the served waves
     const int H = L2;
 
-    const int cfg = blockIdx.x;  // ((r*nk + w)*W + j)
     const int j = cfg % W;
     const int rw = cfg / W;
     const int w = rw % nk;
@@ -563,7 +563,6 @@ k_sweep_helped(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __rest
     tb.nb[0] = (uint32_t)sh.bnb[0]; tb.nb[1] = (uint32_t)sh.bnb[1]; tb.nb[2] = (uint32_t)sh.bnb[2];
     __syncthreads();  // tables complete: the helpers look up segment 0's masks below
 
-    const uint32_t t = ctr->t;
     const uint32_t c3 = ctr_word3(sh.word_offset + (uint32_t)j, sh.sid, kTagMetro);
     const uint32_t c2_0 = (uint32_t)rw << 1, c2_1 = c2_0 | 1u;
 
@@ -774,6 +773,13 @@ k_sweep_helped(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __rest
     }
 }
 
+template <bool kE>
+__global__ void __launch_bounds__(kHelpedThreads)
+k_sweep_helped(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __restrict__ ctr) {
+    extern __shared__ uint64_t lds[];
+    helped_body<kE>(sh, (int)blockIdx.x, lds, key0, key1, ctr->t);
+}
+
 // One configuration per workgroup (r, w, j) = blockIdx.x.
 // kOcc: minimum waves per SIMD the register allocation must allow (1 = no
 // constraint); a tuning knob, the results do not depend on it.  Above 1 the
@@ -809,7 +815,10 @@ k_sweep_batch(BatchArgs a) {
         const int s = (int)(lo & 0xFFu), g = (int)((lo >> 8) & 0xFFu), nlive = (int)((lo >> 16) & 0xFFu);
         const ShapeDev& sh = a.shapes[s];
         const uint32_t t = __builtin_amdgcn_readfirstlane(a.ctr[s].t);
-        sweep_teams<true, true, false>(sh, cfg0, g, nlive, stream_cols(sh), lds, a.key0, a.key1, t);
+        if (sh.L2 == kHelpCols && blockDim.x == kHelpedThreads)
+            helped_body<true>(sh, cfg0, lds, a.key0, a.key1, t);  // one configuration, helper waves
+        else
+            sweep_teams<true, true, false>(sh, cfg0, g, nlive, stream_cols(sh), lds, a.key0, a.key1, t);
     }
     if (threadIdx.x == 0) {
         __threadfence();
@@ -829,6 +838,8 @@ size_t sweep_stream_lds_bytes(const ShapeDev& sh, int teams, int threads, bool d
 }
 
 int sweep_stream_cols(const ShapeDev& sh) { return stream_cols(sh); }
+
+size_t sweep_helped_lds_bytes(const ShapeDev& sh) { return (size_t)helped_words(sh) * 8; }
 
 bool sweep_stream_ok(const ShapeDev& sh) {
     return sh.bnb[0] >= 0 && sh.bnb[1] >= 0 && sh.bnb[2] >= 0 && sh.L2 <= kMaxCols &&

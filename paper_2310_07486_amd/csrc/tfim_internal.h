@@ -160,6 +160,9 @@ bool sweep_stream_ok(const ShapeDev& sh);
 // threads per configuration (L^2 rounded up to whole waves).
 size_t sweep_stream_lds_bytes(const ShapeDev& sh, int teams, int threads, bool deep_in_lds);
 int sweep_stream_cols(const ShapeDev& sh);
+// LDS of the helper-wave workgroup (L^2 = 576, 768 threads), which the batched
+// kernel also runs for such shapes when launched with 768 threads.
+size_t sweep_helped_lds_bytes(const ShapeDev& sh);
 // Batched persistent sweep: allow its LDS and report resident blocks per CU
 // (occ: 1 or 2 = minimum waves per SIMD the kernel was compiled for).
 hipError_t sweep_batch_prepare(int occ, size_t lds_bytes, int threads, int* blocks_per_cu);

@@ -98,6 +98,39 @@ def test_batch_geometry_does_not_change_results(threads, bpc):
     _same(_state(ref, len(SHAPES)), _state(bat, len(SHAPES)))
 
 
+# an L = 24 shape (576 columns): at 768 threads the batched kernel runs its
+# configurations with the helper-wave body, at fewer with the packed teams
+SHAPES24 = [
+    Shape(24, 32, 1, 2, ladder(0.22, 0.36, 4), pt_every=1, stream_id=0),
+    Shape(8, 64, 1, 2, ladder(0.25, 0.30, 3), pt_every=2, stream_id=1),
+]
+
+
+@pytest.mark.parametrize("threads", [576, 768])
+def test_batched_with_helper_wave_items(threads):
+    seed = 404
+    _say(f"batched L=24 + L=8, threads={threads}, 19 sweeps")
+    ref = tfim.Plan(SHAPES24, seed)
+    ref.init()
+    ref.sweep(19)
+    bat = tfim.Plan(SHAPES24, seed)
+    bat.init()
+    bat.set_batch(threads, 0)
+    bat.set_schedule(tfim.TFIM_SCHED_BATCHED)
+    bat.sweep(19)  # one graph of 16 sweeps and one of 3
+    bat.sync()
+    _same(_state(ref, 2), _state(bat, 2))
+    sh = SHAPES24[0]
+    lanes = [0, 40, 63]
+    ch = oracle.Chain(sh.L, sh.Ltau, sh.k, sh.n_replicas, seed, lanes, pt_every=sh.pt_every,
+                      stream_id=sh.stream_id)
+    ch.run(19)
+    S = bat.export_spins(0)
+    kidx, U = bat.get_state(0)
+    assert np.array_equal(tfim.lanes_of(S, lanes, word_axis=2), ch.S)
+    assert np.array_equal(kidx[:, lanes], ch.kidx) and np.array_equal(U[:, lanes], ch.U)
+
+
 @pytest.mark.parametrize("schedule", [tfim.TFIM_SCHED_BATCHED, tfim.TFIM_SCHED_CONCURRENT])
 def test_graph_replays_and_timing(schedule):
     seed = 5

@@ -210,3 +210,35 @@ def test_kernel_timing_counts_launches():
     plan.sweep(6)
     ms, n = plan.get_timing()
     assert n == 6 and ms > 0.0
+
+
+@pytest.mark.parametrize("L,Lt,nk,variant", [
+    (8, 16, 1, 0), (24, 16, 1, 3), (4, 16, 255, 0), (4, 16, 255, 1), (24, 32, 255, 3),
+])
+def test_ladder_ends(L, Lt, nk, variant):
+    """One k (tempering has no pair to try) and the longest ladder (255 k, the
+    lane masks and bucket tables at full size)."""
+    sh = Shape(L, Lt, 1, 1, ladder(0.05, 0.95, nk) if nk > 1 else [0.29], pt_every=1)
+    seed = 7100 + nk + L
+    _say(f"ladder ends L={L} Lt={Lt} nk={nk} variant={variant}")
+    plan = tfim.Plan([sh], seed)
+    plan.set_variant(variant)
+    plan.init()
+    plan.sweep(6)
+    plan.sync()
+    lanes = list(range(64)) if L <= 8 else [0, 31, 63]
+    ch = _compare(plan, 0, sh, seed, lanes, 6)
+    assert plan.counters() == (ch.t.value, ch.m.value) and ch.t.value == 6
+
+
+def test_zero_sweeps_is_a_no_op():
+    sh = Shape(8, 16, 1, 2, ladder(0.2, 0.4, 3), pt_every=1)
+    plan = tfim.Plan([sh], 11)
+    plan.init()
+    plan.sweep(3)
+    plan.sync()
+    before = (plan.export_spins(0), *plan.get_state(0), plan.counters())
+    plan.sweep(0)
+    plan.sync()
+    after = (plan.export_spins(0), *plan.get_state(0), plan.counters())
+    assert all(np.array_equal(a, b) for a, b in zip(before[:3], after[:3])) and before[3] == after[3]

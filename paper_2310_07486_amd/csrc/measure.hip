@@ -238,9 +238,13 @@ k_overlap_mfma(ShapeDev sh, int cfg0, int ncfg) {
     constexpr int kPer = (kRows + 255) / 256;  // rows per thread
     for (int e = tid; e < PP * 2; e += 256) red[e] = 0;
     for (int cfg = cfg0 + blockIdx.x; cfg < cfg0 + ncfg; cfg += gridDim.x) {
-        long long s4[PP], tr[PP];
+        unsigned long long s4u[PP];
+        long long tr[PP];
 #pragma unroll
-        for (int p = 0; p < PP; ++p) s4[p] = tr[p] = 0;
+        for (int p = 0; p < PP; ++p) {
+            s4u[p] = 0;
+            tr[p] = 0;
+        }
         for (int tt = 0; tt < ntt * ntt; ++tt) {
             const int T = tt / ntt, T2 = tt % ntt;
             const bool diag = T == T2;
@@ -303,31 +307,52 @@ k_overlap_mfma(ShapeDev sh, int cfg0, int ncfg) {
                 }
             }
             __syncthreads();
-            // epilogue: Q = L^2 - 2 (m_tau + m_tau') + 4 B^aT B^b; |Q| <= L^2 fits
-            // 24-bit multiplies, Q^2 < 2^19, Q^4 < 2^38
+            // epilogue: Q = L^2 - 2 (m_tau + m_tau') + 4 B^aT B^b; |Q| <= L^2,
+            // Q^2 < 2^19, Q^4 < 2^38
             const int col = 32 * wy + (lane & 31);
             const int tau2 = 64 * T2 + col;
             int cc[RR];
 #pragma unroll
             for (int rb = 0; rb < RR; ++rb) cc[rb] = -2 * mBsrc[rb * 64 + col];
+            if (!diag && 64 * (T + 1) <= Lt && 64 * (T2 + 1) <= Lt) {
+                // interior off-diagonal tile: no bounds, no trace; Q^4 summed
+                // unsigned, one 32x32->64 multiply-add per element and pair
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int row = 32 * wx + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
-                const int tau = 64 * T + row;
-                if (tau >= Lt || tau2 >= Lt) continue;
-                int cr[RR];
+                for (int q = 0; q < 16; ++q) {
+                    const int row = 32 * wx + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+                    int cr[RR];
 #pragma unroll
-                for (int ra = 0; ra < RR; ++ra) cr[ra] = L2 - 2 * mA[ra * 64 + row];
-                int p = 0;
+                    for (int ra = 0; ra < RR; ++ra) cr[ra] = L2 - 2 * mA[ra * 64 + row];
+                    int p = 0;
 #pragma unroll
-                for (int ra = 0; ra < RR; ++ra)
+                    for (int ra = 0; ra < RR; ++ra)
 #pragma unroll
-                    for (int rb = ra + 1; rb < RR; ++rb, ++p) {
-                        const int qv = cr[ra] + cc[rb] + 4 * acc[p][q];
-                        const unsigned q2 = (unsigned)__mul24(qv, qv);
-                        s4[p] += (long long)((unsigned long long)q2 * q2);
-                        if (diag && tau == tau2) tr[p] += qv;
-                    }
+                        for (int rb = ra + 1; rb < RR; ++rb, ++p) {
+                            const int qv = cr[ra] + cc[rb] + 4 * acc[p][q];
+                            const uint32_t q2 = (uint32_t)(qv * qv);
+                            s4u[p] += (unsigned long long)q2 * q2;
+                        }
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int row = 32 * wx + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+                    const int tau = 64 * T + row;
+                    if (tau >= Lt || tau2 >= Lt) continue;
+                    int cr[RR];
+#pragma unroll
+                    for (int ra = 0; ra < RR; ++ra) cr[ra] = L2 - 2 * mA[ra * 64 + row];
+                    int p = 0;
+#pragma unroll
+                    for (int ra = 0; ra < RR; ++ra)
+#pragma unroll
+                        for (int rb = ra + 1; rb < RR; ++rb, ++p) {
+                            const int qv = cr[ra] + cc[rb] + 4 * acc[p][q];
+                            const uint32_t q2 = (uint32_t)__mul24(qv, qv);
+                            s4u[p] += (unsigned long long)q2 * q2;
+                            if (diag && tau == tau2) tr[p] += qv;
+                        }
+                }
             }
         }
         // per-configuration flush: wave reduction, then one atomic per value
@@ -335,7 +360,7 @@ k_overlap_mfma(ShapeDev sh, int cfg0, int ncfg) {
         for (int p = 0; p < PP; ++p) {
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) {
-                s4[p] += __shfl_xor(s4[p], off, 64);
+                s4u[p] += (unsigned long long)__shfl_xor((long long)s4u[p], off, 64);
                 tr[p] += __shfl_xor(tr[p], off, 64);
             }
         }
@@ -343,7 +368,7 @@ k_overlap_mfma(ShapeDev sh, int cfg0, int ncfg) {
 #pragma unroll
             for (int p = 0; p < PP; ++p) {
                 atomicAdd(&red[p * 2 + 0], (unsigned long long)tr[p]);
-                atomicAdd(&red[p * 2 + 1], (unsigned long long)s4[p]);
+                atomicAdd(&red[p * 2 + 1], s4u[p]);
             }
         }
         __syncthreads();

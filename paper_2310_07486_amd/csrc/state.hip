@@ -48,13 +48,14 @@ __global__ void k_labels_identity(ShapeDev sh) {
     }
 }
 
-// Lane masks of one (r, j) group from the k labels of its 64 lanes (one
-// thread per lane): mask[w][K] = lanes whose walker w has k-index < K.
+// Lane masks of one (r, j) group from the k labels of its 64 lanes:
+// mask[w][K] = lanes whose walker w has k-index < K.  Lane = sample; wave v
+// of the workgroup builds walkers v, v + (waves), ...
 __device__ void rebuild_masks(const ShapeDev& sh, int r, int j, const uint8_t* kl /*[64][nk]*/) {
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
     const int nk = sh.nk;
     uint64_t* out = sh.mask + (size_t)(r * sh.W + j) * nk * (nk + 1);
-    for (int w = 0; w < nk; ++w) {
+    for (int w = wave; w < nk; w += nwaves) {
         const int mine = kl[lane * nk + w];
         for (int K0 = 0; K0 <= nk; K0 += 64) {
             uint64_t keep = 0;
@@ -82,23 +83,33 @@ __global__ void __launch_bounds__(64) k_mask_rebuild(ShapeDev sh) {
 // with d = U_a - U_b the swap of labels is accepted iff d <= 0 or
 // R < floor(2^32 exp(-(k_{i+1} - k_i) 2d)) (the exchange ratio of the two
 // Boltzmann weights, E = 2U - 3N).  One uniform per lane.
+constexpr int kTemperThreads = 1024;  // 64 lanes x 16 pair slots
+
 __device__ void temper_group(const ShapeDev& sh, int r, int j, uint32_t key0, uint32_t key1,
                              uint32_t m, uint8_t* kl /*[2][64][nk]*/) {
-    const int lane = threadIdx.x, nk = sh.nk;
-    uint8_t* ki = kl + lane * nk;
-    uint8_t* wi = kl + 64 * nk + lane * nk;
-    const size_t base = ((size_t)r * sh.W * 64 + (size_t)j * 64 + lane) * nk;
-    for (int w = 0; w < nk; ++w) {
-        ki[w] = sh.kidx[base + w];
-        wi[w] = sh.winv[base + w];
+    const int nk = sh.nk, tid = threadIdx.x, nthr = blockDim.x;
+    const int lane = tid & 63, slot = tid >> 6, nslots = nthr >> 6;
+    uint8_t* K = kl;             // [64][nk]: k-index of each walker
+    uint8_t* Wv = kl + 64 * nk;  // [64][nk]: walker of each k-index
+    // the group's labels are 64 nk contiguous bytes
+    const size_t gbase = ((size_t)r * sh.W * 64 + (size_t)j * 64) * nk;
+    for (int e = tid; e < 64 * nk; e += nthr) {
+        K[e] = sh.kidx[gbase + e];
+        Wv[e] = sh.winv[gbase + e];
     }
+    __syncthreads();
+    // the pairs of one step are disjoint (they touch different k-indices and
+    // walkers), so the slots of a lane decide theirs in parallel
+    uint8_t* ki = K + lane * nk;
+    uint8_t* wi = Wv + lane * nk;
+    const size_t base = gbase + (size_t)lane * nk;
     const uint32_t c3 = ctr_word3(sh.word_offset + (uint32_t)j, sh.sid, kTagTemper);
-    for (int i = (int)(m & 1u); i + 1 < nk; i += 2) {
+    for (int i = (int)(m & 1u) + 2 * slot; i + 1 < nk; i += 2 * nslots) {
         const int wa = wi[i], wb = wi[i + 1];
         const int64_t d = (int64_t)sh.U[base + wa] - (int64_t)sh.U[base + wb];
         const U4 o = philox10(((uint32_t)lane >> 2) | ((uint32_t)i << 4), m, (uint32_t)r, c3, key0,
                               key1);
-        const uint32_t R = o.v[lane & 3];
+        const uint32_t R = (lane & 2) ? ((lane & 1) ? o.v[3] : o.v[2]) : ((lane & 1) ? o.v[1] : o.v[0]);
         bool acc = d <= 0;
         if (!acc && d <= (int64_t)sh.dmax[i]) acc = R < sh.Tpt[sh.tpt_off[i] + (uint32_t)(d - 1)];
         if (acc) {
@@ -108,15 +119,15 @@ __device__ void temper_group(const ShapeDev& sh, int r, int j, uint32_t key0, ui
             wi[i + 1] = (uint8_t)wa;
         }
     }
-    for (int w = 0; w < nk; ++w) {
-        sh.kidx[base + w] = ki[w];
-        sh.winv[base + w] = wi[w];
-    }
     __syncthreads();
-    rebuild_masks(sh, r, j, kl);
+    for (int e = tid; e < 64 * nk; e += nthr) {
+        sh.kidx[gbase + e] = K[e];
+        sh.winv[gbase + e] = Wv[e];
+    }
+    rebuild_masks(sh, r, j, K);
 }
 
-__global__ void __launch_bounds__(64) k_temper(ShapeDev sh, uint32_t key0, uint32_t key1,
+__global__ void __launch_bounds__(kTemperThreads) k_temper(ShapeDev sh, uint32_t key0, uint32_t key1,
                                                const Counters* __restrict__ ctr) {
     extern __shared__ uint8_t kl[];  // [64][nk] labels, then [64][nk] inverse
     temper_group(sh, (int)blockIdx.x / sh.W, (int)blockIdx.x % sh.W, key0, key1, ctr->m, kl);
@@ -128,7 +139,7 @@ __device__ __forceinline__ bool pt_due(const ShapeDev& sh, uint32_t t) {
 
 // Every shape's (r, j) groups in one launch; a shape whose tempering is not
 // due after this sweep is skipped.
-__global__ void __launch_bounds__(64) k_temper_batch(TemperBatchArgs a) {
+__global__ void __launch_bounds__(kTemperThreads) k_temper_batch(TemperBatchArgs a) {
     extern __shared__ uint8_t kl[];
     const uint32_t b = blockIdx.x;
     uint32_t s = 0;
@@ -191,13 +202,13 @@ hipError_t launch_mask_rebuild(const ShapeDev& sh, hipStream_t st) {
 }
 
 hipError_t launch_temper(const ShapeDev& sh, uint64_t seed, const Counters* ctr, hipStream_t st) {
-    hipLaunchKernelGGL(k_temper, dim3(sh.R * sh.W), dim3(64), (size_t)128 * sh.nk, st, sh,
+    hipLaunchKernelGGL(k_temper, dim3(sh.R * sh.W), dim3(kTemperThreads), (size_t)128 * sh.nk, st, sh,
                        (uint32_t)seed, (uint32_t)(seed >> 32), ctr);
     return hipGetLastError();
 }
 
 hipError_t launch_temper_batch(const TemperBatchArgs& a, int blocks, int max_nk, hipStream_t st) {
-    hipLaunchKernelGGL(k_temper_batch, dim3(blocks), dim3(64), (size_t)128 * max_nk, st, a);
+    hipLaunchKernelGGL(k_temper_batch, dim3(blocks), dim3(kTemperThreads), (size_t)128 * max_nk, st, a);
     return hipGetLastError();
 }
 

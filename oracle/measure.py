@@ -114,3 +114,119 @@ def xi2(A, L: int) -> float:
     if ratio < 1.0:
         return math.nan
     return math.sqrt(ratio - 1.0) / (2.0 * math.sin(math.pi / L))
+
+
+# ---------------------------------------------------------------------------
+# Three-replica estimator for r = 3 and the Binder ratio.
+#
+# Methods, "One-time observables": chi^(3) = avg Tr[M^3] / L^D and
+# F^(3) = avg Tr[M-hat M^2] / L^D.  Three distinct replicas a, b, c give an
+# unbiased estimate of a product of three thermal averages, so per
+# configuration Tr[M^3] ~ Tr[G^a G^b G^c] / Ltau^3.  In Tr[M-hat M^2] the
+# phase sits on one factor; averaging over which replica carries it, the
+# record of a triple {a, b, c} (a < b < c) sums the three choices:
+#   T_x[d] = sum_{carrier e in {a,b,c}, f < g the other two}
+#            sum_{x,y: (x1 - y1) mod L = d} G^e_xy (G^f G^g)_yx
+# (T_y likewise with x2 - y2).  Since e^{i p.(x-y)} has real part
+# cos(2 pi d / L), sum_d T_x[d] cos(2 pi d/L) = Re sum_e Tr[(G^e o P) G^f G^g]
+# and sum_d T_x[d] = 3 Tr[G^a G^b G^c]; normalisations cancel in chi/F.
+# Taking g before f conjugates that carrier's trace (d -> -d), so only
+# T[d] + T[-d] is independent of the order, and that is all chi and F use.
+#
+# Binder ratio (Methods, "One-time observables"): B = Q_4 / Q_2^2 with
+# Q_2 = Tr[M^2] and Q_4 the sum of squared equal-time four-point functions.
+# With two replicas and the tau average of each, both come from the overlap
+# matrix Q^{ab} = S^aT S^b:  Q_2 ~ sum Q^2 / Ltau^2,  Q_4 ~ sum Q^4 / Ltau^2,
+# so B = Ltau^2 <sum Q^4> / <sum Q^2>^2 (means over samples and pairs).
+# ---------------------------------------------------------------------------
+def triples(n_replicas: int):
+    """Replica triples a < b < c in lexicographic order."""
+    return list(combinations(range(n_replicas), 3))
+
+
+def triple_record_bound(L: int, Ltau: int) -> int:
+    """Largest |T| a triple record can reach (3 carriers, every |G| <= Ltau)."""
+    n = L * L
+    return 3 * n * n * Ltau * (n * Ltau * Ltau)
+
+
+def _bucket_sums(H: np.ndarray, L: int):
+    """Sums of H[x][y] over (x1 - y1) mod L = d and (x2 - y2) mod L = d."""
+    H4 = H.reshape(L, L, L, L)  # [x2][x1][y2][y1]
+    Mx = H4.sum(axis=(0, 2))    # [x1][y1]
+    My = H4.sum(axis=(1, 3))    # [x2][y2]
+    Tx = np.zeros(L, dtype=np.int64)
+    Ty = np.zeros(L, dtype=np.int64)
+    for a in range(L):
+        for c in range(L):
+            Tx[(a - c) % L] += Mx[a, c]
+            Ty[(a - c) % L] += My[a, c]
+    return Tx, Ty
+
+
+def triple_record(Gs, triple, L: int) -> np.ndarray:
+    """[T_x[0..L-1], T_y[0..L-1]] (int64) of one replica triple.
+
+    G^f G^g is formed in float64: its entries are integers of magnitude at
+    most L^2 Ltau^2 < 2^53, so every partial sum is exact."""
+    a, b, c = triple
+    Tx = np.zeros(L, dtype=np.int64)
+    Ty = np.zeros(L, dtype=np.int64)
+    for e, (f, g) in ((a, (b, c)), (b, (a, c)), (c, (a, b))):
+        P = (Gs[f].astype(np.float64) @ Gs[g].astype(np.float64)).astype(np.int64)
+        tx, ty = _bucket_sums(Gs[e] * P.T, L)
+        Tx += tx
+        Ty += ty
+    return np.concatenate([Tx, Ty])
+
+
+def measure_triples_chain(chain, k_indices=None, sample_indices=None) -> np.ndarray:
+    """Triple records for every (k-index i, sample si, triple) of an oracle
+    Chain: int64 [n_i][n_si][n_triples][2L]."""
+    L, R, Lt = chain.L, chain.R, chain.Ltau
+    assert triple_record_bound(L, Lt) < 2 ** 63, "triple records would overflow int64"
+    winv = chain.winv()
+    ks = range(chain.n_k) if k_indices is None else k_indices
+    ss = range(chain.ns) if sample_indices is None else sample_indices
+    trs = triples(R)
+    out = np.zeros((len(ks), len(ss), len(trs), 2 * L), dtype=np.int64)
+    for ii, i in enumerate(ks):
+        for jj, si in enumerate(ss):
+            Gs = [gram(spin_matrix(chain.S[r, winv[r, si, i], si])) for r in range(R)]
+            for t, tr in enumerate(trs):
+                out[ii, jj, t] = triple_record(Gs, tr, L)
+    return out
+
+
+def _xi_from_sums(chi: float, F: float, L: int) -> float:
+    if F <= 0.0:
+        return math.inf
+    ratio = chi / F
+    if ratio < 1.0:
+        return math.nan
+    return math.sqrt(ratio - 1.0) / (2.0 * math.sin(math.pi / L))
+
+
+def xi3(records, L: int, direction: int = 0) -> float:
+    """xi^(3) of one k-index from triple records [..][2L] (any leading shape:
+    samples, triples, measurements).  direction 0: x half, 1: y half, 2: both.
+    Sums are exact (Python integers) before the cosine weights."""
+    R = np.asarray(records, dtype=np.int64).reshape(-1, 2 * L)
+    halves = [R[:, :L], R[:, L:]] if direction == 2 else [R[:, direction * L:(direction + 1) * L]]
+    A = [sum(int(v) for h in halves for v in h[:, d]) for d in range(L)]
+    chi = float(sum(A))
+    F = math.fsum(a * math.cos(2.0 * math.pi * d / L) for d, a in enumerate(A))
+    return _xi_from_sums(chi, F, L)
+
+
+def binder(records, L: int, Ltau: int) -> float:
+    """B = Ltau^2 <sum Q^4> / <sum Q^2>^2 from pair records [..][2L+3]
+    (any leading shape: samples, pairs, measurements).  NaN if sum Q^2 = 0."""
+    R = np.asarray(records, dtype=np.int64).reshape(-1, 2 * L + 3)
+    n = R.shape[0]
+    q2 = sum(int(v) for v in R[:, 2 * L + 1])
+    q4 = sum(int(v) for v in R[:, 2 * L + 2])
+    if q2 == 0:
+        return math.nan
+    from fractions import Fraction
+    return float(Fraction(Ltau * Ltau * n * q4, q2 * q2))

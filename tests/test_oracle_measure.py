@@ -84,3 +84,169 @@ def test_xi2_special_cases():
     assert math.isinf(flat) or flat > 1e10  # F = 0 up to rounding
     assert math.isinf(om.xi2([1] + [0] * 5 + [9] + [0] * 5, L))  # F < 0
     assert math.isnan(om.xi2([1] + [0] * 5 + [-1] + [0] * 5, L))  # chi/F < 1
+
+
+# ---------------------------------------------------------------------------
+# Three-replica records (chi^(3), F^(3)) and the Binder ratio.
+# ---------------------------------------------------------------------------
+def _gram_loops(S, L2, Lt):
+    return [[sum(int(S[t][x]) * int(S[t][y]) for t in range(Lt)) for y in range(L2)]
+            for x in range(L2)]
+
+
+@pytest.mark.parametrize("L,Lt,R", [(2, 4, 3), (3, 4, 3), (2, 6, 4), (3, 2, 4)])
+def test_triple_record_matches_brute_force_loops(L, Lt, R):
+    """T_x[d] = sum over carriers e of sum_{x,y,z} G^e_xy G^f_yz G^g_zx,
+    bucketed by (x1 - y1) mod L, written as plain loops from the trace."""
+    rng = np.random.default_rng(10 + L + R)
+    L2 = L * L
+    Ss = [_rand_S(rng, L, Lt) for _ in range(R)]
+    Gl = [_gram_loops(S, L2, Lt) for S in Ss]
+    Gs = [om.gram(om.spin_matrix(S)) for S in Ss]
+    for tr in om.triples(R):
+        a, b, c = tr
+        Tx, Ty = [0] * L, [0] * L
+        for e, f, g in ((a, b, c), (b, a, c), (c, a, b)):
+            for x in range(L2):
+                for y in range(L2):
+                    s = sum(Gl[e][x][y] * Gl[f][y][z] * Gl[g][z][x] for z in range(L2))
+                    Tx[(x % L - y % L) % L] += s
+                    Ty[(x // L - y // L) % L] += s
+        assert om.triple_record(Gs, tr, L).tolist() == Tx + Ty
+
+
+def test_triple_trace_identity_in_time_space():
+    """sum_d T_x = sum_d T_y = 3 Tr[G^a G^b G^c] = 3 Tr[Q^ab Q^bc Q^ca]
+    (the trace moved to the Ltau x Ltau overlaps)."""
+    rng = np.random.default_rng(3)
+    L, Lt = 4, 20
+    Ss = [om.spin_matrix(_rand_S(rng, L, Lt)) for _ in range(3)]
+    Gs = [om.gram(S) for S in Ss]
+    rec = om.triple_record(Gs, (0, 1, 2), L)
+    Qab, Qbc, Qca = om.overlap(Ss[0], Ss[1]), om.overlap(Ss[1], Ss[2]), om.overlap(Ss[2], Ss[0])
+    tr_q = int(np.trace(Qab @ Qbc @ Qca))
+    assert rec[:L].sum() == rec[L:].sum() == 3 * tr_q
+
+
+@pytest.mark.parametrize("L,Lt", [(3, 8), (4, 12), (5, 6)])
+def test_triple_cosine_weights_equal_the_complex_phase_trace(L, Lt):
+    """sum_d T_x[d] cos(2 pi d/L) = Re sum_e Tr[(G^e o P) G^f G^g] with
+    P_xy = exp(i p.(x - y)), p = (2 pi/L, 0); T_y with p = (0, 2 pi/L)."""
+    rng = np.random.default_rng(4 + L)
+    Ss = [om.spin_matrix(_rand_S(rng, L, Lt)) for _ in range(3)]
+    Gs = [om.gram(S) for S in Ss]
+    rec = om.triple_record(Gs, (0, 1, 2), L)
+    idx = np.arange(L * L)
+    x1, x2 = idx % L, idx // L
+    cosw = np.cos(2 * np.pi * np.arange(L) / L)
+    for half, coord in ((0, x1), (1, x2)):
+        P = np.exp(1j * 2 * np.pi * (coord[:, None] - coord[None, :]) / L)
+        want = 0.0
+        for e, f, g in ((0, 1, 2), (1, 0, 2), (2, 0, 1)):
+            want += np.trace((Gs[e] * P) @ (Gs[f] @ Gs[g]).astype(np.complex128)).real
+        got = float((rec[half * L:(half + 1) * L] * cosw).sum())
+        assert got == pytest.approx(want, rel=1e-12)
+
+
+def _sym(rec, L):
+    """T[d] + T[-d] of both halves: the part that enters chi and F."""
+    neg = (-np.arange(L)) % L
+    return np.concatenate([rec[:L] + rec[:L][neg], rec[L:] + rec[L:][neg]])
+
+
+def test_triple_record_symmetries():
+    """Relabelling the replicas reverses some products G^f G^g, which maps
+    that carrier's d to -d (the trace becomes its complex conjugate): the
+    d-symmetric part is invariant.  A global flip of one replica and a flip
+    of one site in every replica (G -> e G e) leave the record unchanged."""
+    rng = np.random.default_rng(5)
+    L, Lt = 3, 10
+    Ss = [_rand_S(rng, L, Lt) for _ in range(3)]
+    Gs = [om.gram(om.spin_matrix(S)) for S in Ss]
+    ref = om.triple_record(Gs, (0, 1, 2), L)
+    perm = [Gs[2], Gs[0], Gs[1]]
+    got = om.triple_record(perm, (0, 1, 2), L)
+    assert np.array_equal(_sym(got, L), _sym(ref, L))
+    assert not np.array_equal(got, ref)  # the raw buckets are not symmetric
+    flip_one = [Gs[0], om.gram(om.spin_matrix(-Ss[1])), Gs[2]]
+    assert np.array_equal(om.triple_record(flip_one, (0, 1, 2), L), ref)
+    gauged = []
+    for S in Ss:
+        T = S.copy()
+        T[:, 4] *= -1
+        gauged.append(om.gram(om.spin_matrix(T)))
+    assert np.array_equal(om.triple_record(gauged, (0, 1, 2), L), ref)
+    # the product's orientation matters: (G^f G^g)_xy in place of _yx gives T[-d]
+    a, b, c = Gs
+    wrong = (om._bucket_sums(a * (b @ c), L)[0] + om._bucket_sums(b * (a @ c), L)[0]
+             + om._bucket_sums(c * (a @ b), L)[0])
+    assert np.array_equal(wrong, ref[:L][(-np.arange(L)) % L])
+    assert not np.array_equal(wrong, ref[:L])
+
+
+def _hadamard(n):
+    H = np.array([[1]], dtype=np.int64)
+    while H.shape[0] < n:
+        H = np.block([[H, H], [H, -H]])
+    return H
+
+
+@pytest.mark.parametrize("L,Lt", [(2, 4), (4, 16), (4, 32)])
+def test_xi3_zero_for_orthogonal_sites(L, Lt):
+    """Sites whose spin rows are orthogonal over tau (distinct Walsh
+    functions, random signs per replica) have G = Ltau I: every T is on
+    d = 0, T_x[0] = 3 L^2 Ltau^3, chi = F and xi^(3) = 0 exactly."""
+    rng = np.random.default_rng(6)
+    H = _hadamard(Lt)[: L * L]  # rows = sites
+    Gs = []
+    for _ in range(3):
+        S = H * rng.choice([-1, 1], size=(L * L, 1))
+        Gs.append(om.gram(S.astype(np.float64)))
+        assert np.array_equal(Gs[-1], Lt * np.eye(L * L, dtype=np.int64))
+    rec = om.triple_record(Gs, (0, 1, 2), L)
+    want = np.zeros(2 * L, dtype=np.int64)
+    want[0] = want[L] = 3 * L * L * Lt ** 3
+    assert np.array_equal(rec, want)
+    assert om.xi3(rec, L, 0) == 0.0 and om.xi3(rec, L, 2) == 0.0
+
+
+@pytest.mark.parametrize("L,Lt", [(2, 4), (3, 6), (6, 8)])
+def test_triple_record_ordered_state(L, Lt):
+    """All spins equal: G = Ltau everywhere, G^f G^g = L^2 Ltau^2, so
+    T_x[d] = 3 L^2 Ltau^3 * L^3 (pairs with a given x1 - y1) for every d:
+    F vanishes and xi^(3) diverges."""
+    S = np.ones((Lt, L * L), dtype=np.int8)
+    Gs = [om.gram(om.spin_matrix(S))] * 3
+    rec = om.triple_record(Gs, (0, 1, 2), L)
+    assert np.all(rec == 3 * L ** 5 * Lt ** 3)
+    xi = om.xi3(rec, L, 0)
+    assert xi == math.inf or xi > 1e6
+
+
+def test_triple_bound_covers_the_largest_configurations():
+    assert om.triple_record_bound(24, 2048) < 2 ** 63
+    S = np.ones((8, 9), dtype=np.int8)
+    rec = om.triple_record([om.gram(om.spin_matrix(S))] * 3, (0, 1, 2), 3)
+    assert rec[:3].sum() == om.triple_record_bound(3, 8)
+
+
+def test_binder_closed_forms():
+    """Ordered replicas (Q = L^2 everywhere): B = 1.  Independent random
+    spins: each Q entry is a sum of n = L^2 independent signs, so
+    E sum Q^4 = Ltau^2 (3 n^2 - 2 n), E sum Q^2 = Ltau^2 n and B -> 3 - 2/n."""
+    L, Lt = 3, 6
+    S = np.ones((Lt, L * L), dtype=np.int8)
+    rec = om.pair_record(om.spin_matrix(S), om.spin_matrix(-S), L)
+    assert om.binder(rec, L, Lt) == 1.0
+    rng = np.random.default_rng(7)
+    L, Lt, n_rec = 2, 4, 4000
+    recs = [om.pair_record(om.spin_matrix(_rand_S(rng, L, Lt)), om.spin_matrix(_rand_S(rng, L, Lt)), L)
+            for _ in range(n_rec)]
+    n = L * L
+    B = om.binder(np.array(recs), L, Lt)
+    assert abs(B - (3 - 2 / n)) < 0.05
+    # the estimator is the ratio of the means, not the mean of the ratios
+    two = np.array(recs[:2])
+    q2 = int(two[:, 2 * L + 1].sum())
+    q4 = int(two[:, 2 * L + 2].sum())
+    assert om.binder(two, L, Lt) == pytest.approx(Lt ** 2 * 2 * q4 / q2 ** 2, rel=1e-15)

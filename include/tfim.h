@@ -176,6 +176,50 @@ tfim_status tfim_dump_gram(tfim_plan *plan, uint32_t shape, uint32_t i, uint32_t
  * A is [n_k][L] int64 (e.g. the D_x half of the buckets).  Host-only. */
 tfim_status tfim_xi2(const int64_t *A, uint32_t L, uint32_t n_k, double *xi_out);
 
+/* Three-replica records (Methods, "One-time observables": chi^(r) and F^(r)
+ * with r = 3; replica estimators of "Simulation details").  For
+ * configuration cfg = i*samples + s and each replica triple a < b < c
+ * (lexicographic; n_triples = R(R-1)(R-2)/6), with G^r = S^r S^rT:
+ *   T_x[d] = sum over the carrier e in {a,b,c}, f < g the other two, of
+ *            sum_{(x1-y1) mod L = d} G^e_xy (G^f G^g)_yx
+ * and T_y[d] likewise with x2 - y2.  sum_d T_x[d] = 3 Tr[G^a G^b G^c] ~ Tr[M^3]
+ * and sum_d T_x[d] cos(2 pi d/L) ~ Tr[M-hat M^2] (phase on the carrier,
+ * averaged over the three choices).  Records are int64
+ * [ncfg][n_triples][2L] = [T_x[0..L-1], T_y[0..L-1]], exact.
+ * Needs 3 or 4 replicas, L <= 32, L^2 (Ltau/2)^2 < 2^31 and
+ * 3 L^6 Ltau^3 < 2^63 (else TFIM_EUNSUPPORTED).
+ * tfim_triples_workspace: bytes of device workspace for ncfg configurations
+ *   (records, then int8 planes of G/2 for every replica; about
+ *   2 R (64 ceil(L/8)^2)^2 bytes per configuration).  Host-only.
+ * tfim_measure_triples: configurations cfg0 .. cfg0+ncfg-1; ws is caller-owned
+ *   device memory (256-byte aligned, at least the workspace size), used as
+ *   scratch and holding the records at its start afterwards.  flags as for
+ *   tfim_measure_range.  out == NULL: enqueue only (asynchronous); otherwise
+ *   the call synchronises and copies the records to out. */
+tfim_status tfim_triples_workspace(const tfim_plan *plan, uint32_t shape, uint32_t ncfg,
+                                   size_t *bytes_out);
+tfim_status tfim_measure_triples(tfim_plan *plan, uint32_t shape, uint32_t cfg0, uint32_t ncfg,
+                                 uint32_t flags, void *workspace, size_t workspace_bytes,
+                                 int64_t *out, size_t out_bytes);
+
+/* xi^(3) per k-index (Methods, "One-time observables") from three-replica
+ * records rec[n_k][n_per_k][2L] (n_per_k = samples x triples x measurements):
+ * A[d] = sum of T_x[d] (direction 0), T_y[d] (1) or both (2), summed exactly;
+ * chi = sum_d A[d], F = sum_d A[d] cos(2 pi d/L), xi = sqrt(chi/F - 1) /
+ * (2 sin(pi/L)); +inf if F <= 0, NaN if chi/F < 1.  Host-only. */
+tfim_status tfim_xi3(const int64_t *rec, uint32_t L, uint32_t n_k, uint32_t n_per_k,
+                     uint32_t direction, double *xi_out);
+
+/* Binder ratio B = Q_4 / Q_2^2 per k-index (Methods, "One-time
+ * observables") from pair records rec[n_k][n_per_k][2L+3] (the layout of
+ * TFIM_MEASURE_RECORDS; n_per_k = samples x pairs x measurements).  With the
+ * tau average of each replica, Q_2 ~ sum Q^2 / Ltau^2 and Q_4 ~ sum Q^4 /
+ * Ltau^2 for the overlap Q = S^aT S^b, so
+ * B = Ltau^2 n_per_k (sum Q^4) / (sum Q^2)^2 over the k-index's records
+ * (exact integer sums; NaN if sum Q^2 = 0).  Host-only. */
+tfim_status tfim_binder(const int64_t *rec, uint32_t L, uint32_t Ltau, uint32_t n_k,
+                        uint32_t n_per_k, double *B_out);
+
 /* Threshold tables of a shape (host-only): Tm[n_k][3] with
  * Tm[i][u] = floor(2^32 exp(-k_i (12 - 4u))) for u = 0,1,2 unsatisfied
  * bonds of six; dmax[n_k-1]; Tpt[sum dmax] with, for pair i, entries

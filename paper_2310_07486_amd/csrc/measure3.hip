@@ -1,0 +1,399 @@
+// Three-replica records for chi^(3) and F^(3) on int8 MFMA.
+//
+// Paper: arXiv:2310.07486, Methods, "One-time observables" (chi^(r), F^(r)
+// and the second-moment length xi^(r), here r = 3) with the independent
+// replicas of "Simulation details".
+//
+// For configuration (k-index i, sample s) and replicas r = 0..R-1 with
+// G^r = S^r S^rT (L^2 x L^2), the record of a replica triple a < b < c is
+//   T_x[d] = sum_{carrier e in {a,b,c}, f < g the other two}
+//            sum_{(x1 - y1) mod L = d} G^e_xy (G^f G^g)_yx     (T_y: x2 - y2)
+// so that Tr[M^3] ~ sum_d T_x[d] and Tr[M-hat M^2] ~ sum_d T_x[d] cos(2 pi d/L)
+// (the phase on the carrier's factor, averaged over the three choices).
+//
+// 1. k_gram_store computes G of every replica from the bit rows along tau
+//    (the {0,1} algebra of the pair measurement) and writes G' = G/2 (exact:
+//    every entry has the parity of Ltau, which is even), |G'| <= Ltau/2,
+//    as two int8 digits G' = 64 h + l, h in [-16, 16], l in [-32, 31], to
+//    the caller's workspace.  Sites are stored in 8 x 8 blocks, one 64-row
+//    tile per block (zero rows and columns where L is not a multiple of 8),
+//    in a slot order chosen so that the 16 outputs a lane holds in the
+//    32x32 MFMA layout cover four values of y1 and four of y2.
+// 2. k_triple_mfma forms P = G'^f G'^g = 4096 h^f h^g + 64 (h^f l^g + l^f h^g)
+//    + l^f l^g with three exact int8 GEMMs on v_mfma_i32_32x32x32_i8 (the
+//    middle one with K doubled), |P| <= L^2 (Ltau/2)^2 < 2^31.  Its epilogue
+//    multiplies P_yx by G'^e_xy of each carrier e outside {f, g}, sums each
+//    lane's 16 products into four x-buckets and four y-buckets in registers
+//    and adds those to LDS buckets of the triple {e, f, g}.  Records are
+//    scaled by 8 at the flush (G = 2 G').  Work items (configuration, pair,
+//    output tile) are handed out so that the workgroups with the same
+//    blockIdx.x mod 8 (one XCD under round-robin dispatch) share one
+//    configuration at a time, whose 2 R Np^2 bytes then stay in that XCD's
+//    L2.
+#include <algorithm>
+
+#include "tfim_internal.h"
+
+namespace tfim {
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+constexpr int kPitch = 80;  // bytes per 64-byte staged row in LDS (16-byte aligned)
+constexpr int kMaxL = 32;
+
+// Slot rho in [0, 64) of a tile <-> offsets (d1, d2) in [0, 8)^2 within the
+// 8 x 8 site block: rho = 32 (d2 >> 2) + 8 (d2 & 3) + 4 (d1 >> 2) + (d1 & 3).
+// Output row 32 wx + 8 g + 4 h + j of the MFMA layout is then d1 = 4 h + j,
+// d2 = 4 wx + g.
+__device__ __forceinline__ int slot_d1(int rho) { return 4 * ((rho >> 2) & 1) + (rho & 3); }
+__device__ __forceinline__ int slot_d2(int rho) { return 4 * (rho >> 5) + ((rho >> 3) & 3); }
+
+__device__ __forceinline__ uint64_t low_bits(int n) {
+    return n >= 64 ? ~0ull : (n <= 0 ? 0ull : ((1ull << n) - 1ull));
+}
+
+// 64 bits -> 64 bytes in {0,1} (byte t = bit t), four 16-byte stores.
+__device__ __forceinline__ void unpack64(uint64_t v, uint8_t* dst) {
+    uint32_t out[16];
+#pragma unroll
+    for (int d = 0; d < 16; ++d) {
+        const uint32_t nib = (uint32_t)(v >> (4 * d)) & 0xFu;
+        out[d] = __umul24(nib, 0x00204081u) & 0x01010101u;
+    }
+    v4i* p = (v4i*)dst;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        v4i x;
+        x[0] = (int)out[4 * q]; x[1] = (int)out[4 * q + 1];
+        x[2] = (int)out[4 * q + 2]; x[3] = (int)out[4 * q + 3];
+        p[q] = x;
+    }
+}
+
+__device__ __forceinline__ v4i lds_v4(const uint8_t* base) { return *(const v4i*)base; }
+
+__device__ __forceinline__ int mod_l(int v, int L) {
+    v %= L;
+    return v < 0 ? v + L : v;
+}
+
+// Index of the sorted triple a < b < c among the lexicographic triples of R.
+__device__ __forceinline__ int triple_index(int a, int b, int c, int R) {
+    int t = 0;
+    for (int i = 0; i < R; ++i)
+        for (int j = i + 1; j < R; ++j)
+            for (int k = j + 1; k < R; ++k) {
+                if (i == a && j == b && k == c) return t;
+                ++t;
+            }
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
+// G' of every replica into the workspace, digit planes [cl][r][plane][Np][Np].
+// ---------------------------------------------------------------------------
+template <int RR>
+__global__ void __launch_bounds__(256) k_gram_store(ShapeDev sh, int cfg0, int ncfg, int nb,
+                                                    int8_t* __restrict__ ws) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    uint8_t* Al = smem;                           // [RR][64][kPitch]
+    uint8_t* Bl = smem + RR * 64 * kPitch;        // [RR][64][kPitch]
+    int* nA = (int*)(Bl + RR * 64 * kPitch);      // [RR][64] popcounts
+    int* nB = nA + RR * 64;                       // [RR][64]
+    int* xyA = nB + RR * 64;                      // [64] site of each row slot, -1 = padding
+    int* xyB = xyA + 64;                          // [64]
+    const int L = sh.L, Lt = sh.Lt;
+    const int nt = nb * nb, Np = 64 * nt;
+    const size_t plane = (size_t)Np * Np;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int wx = wv & 1, wy = wv >> 1;
+    const int ntp = nt * (nt + 1) / 2;
+    const long long items = (long long)ncfg * ntp;
+    for (long long item = blockIdx.x; item < items; item += gridDim.x) {
+        const int cl = (int)(item / ntp);
+        int X = 0, rem = (int)(item % ntp);
+        while (rem >= nt - X) { rem -= nt - X; ++X; }
+        const int Y = X + rem;
+        const bool diag = X == Y;
+        __syncthreads();  // the previous item's epilogue has read nA, nB, xyA, xyB
+        if (tid < 128) {
+            const int side = tid >> 6, rho = tid & 63, T = side ? Y : X;
+            const int x1 = 8 * (T % nb) + slot_d1(rho), x2 = 8 * (T / nb) + slot_d2(rho);
+            (side ? xyB : xyA)[rho] = (x1 < L && x2 < L) ? x1 + L * x2 : -1;
+        }
+        for (int e = tid; e < 2 * RR * 64; e += 256) nA[e] = 0;  // nA and nB
+        const uint8_t* Bsrc = diag ? Al : Bl;
+        const int* nBs = diag ? nA : nB;
+        v16i acc[RR];
+#pragma unroll
+        for (int r = 0; r < RR; ++r)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc[r][q] = 0;
+        for (int c = 0; c < sh.nc; ++c) {
+            __syncthreads();
+            const uint64_t vm = low_bits(Lt - 64 * c);
+            for (int e = tid; e < (diag ? 1 : 2) * RR * 64; e += 256) {
+                const int side = e / (RR * 64), rr = (e / 64) % RR, row = e & 63;
+                const int xy = (side ? xyB : xyA)[row];
+                const size_t m = (size_t)(cfg0 + cl) * RR + rr;
+                const uint64_t v = xy >= 0 ? (sh.Pt[(m * sh.nc + c) * sh.nxp + xy] & vm) : 0ull;
+                (side ? nB : nA)[rr * 64 + row] += __popcll(v);
+                unpack64(v, (side ? Bl : Al) + (rr * 64 + row) * kPitch);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {
+                const int ko = 32 * ks + 16 * (lane >> 5);
+#pragma unroll
+                for (int r = 0; r < RR; ++r) {
+                    const v4i a = lds_v4(Al + (r * 64 + 32 * wx + (lane & 31)) * kPitch + ko);
+                    const v4i b = lds_v4(Bsrc + (r * 64 + 32 * wy + (lane & 31)) * kPitch + ko);
+                    acc[r] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, acc[r], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();  // popcounts complete
+        // element (row slot rho of tile X, column slot col of tile Y):
+        // G = Ltau - 2 (n_rho + n_col) + 4 (B B^T), zero on padding
+        const int col = 32 * wy + (lane & 31);
+        const bool col_ok = (diag ? xyA : xyB)[col] >= 0;
+#pragma unroll
+        for (int r = 0; r < RR; ++r) {
+            const size_t m = (size_t)cl * RR + r;
+            int8_t* ph = ws + (2 * m) * plane;
+            int8_t* pl = ph + plane;
+            uint32_t hw[4] = {0u, 0u, 0u, 0u}, lw[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int row = 32 * wx + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+                const int G = Lt - 2 * (nA[r * 64 + row] + nBs[r * 64 + col]) + 4 * acc[r][q];
+                const int gp = (col_ok && xyA[row] >= 0) ? (G >> 1) : 0;
+                const int h = (gp + 32) >> 6;
+                const int l = gp - 64 * h;
+                hw[q >> 2] |= ((uint32_t)h & 0xFFu) << (8 * (q & 3));
+                lw[q >> 2] |= ((uint32_t)l & 0xFFu) << (8 * (q & 3));
+                if (!diag) {  // the block (X, Y) itself, one byte per element
+                    const size_t o = (size_t)(64 * X + row) * Np + 64 * Y + col;
+                    ph[o] = (int8_t)h;
+                    pl[o] = (int8_t)l;
+                }
+            }
+            // the mirror block (Y, X): row 64 Y + col, four consecutive row slots
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const size_t o = (size_t)(64 * Y + col) * Np + 64 * X + 32 * wx + 8 * g + 4 * (lane >> 5);
+                *(uint32_t*)(ph + o) = hw[g];
+                *(uint32_t*)(pl + o) = lw[g];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pair products and the carrier epilogue; records [cl][NT][2][L].
+// ---------------------------------------------------------------------------
+template <int RR>
+__global__ void __launch_bounds__(256) k_triple_mfma(int L, int ncfg, int nb,
+                                                     const int8_t* __restrict__ ws,
+                                                     int64_t* __restrict__ rec) {
+    constexpr int PP = RR * (RR - 1) / 2;
+    constexpr int NT = RR * (RR - 1) * (RR - 2) / 6;
+    constexpr int NC = RR - 2;  // carriers of a pair
+    __shared__ __align__(16) uint8_t stg[4 * 64 * kPitch];  // f high, f low, g high, g low
+    __shared__ unsigned long long Tb[NT * 2 * kMaxL];
+    const int nt = nb * nb, Np = 64 * nt;
+    const size_t plane = (size_t)Np * Np;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int wx = wv & 1, wy = wv >> 1, h5 = lane >> 5;
+    const int ipc = PP * nt * nt;  // items per configuration
+    const int grp = blockIdx.x & 7, ngrp_blocks = (int)(gridDim.x >> 3), kk = (int)(blockIdx.x >> 3);
+    const int ncg = grp < ncfg ? (ncfg - grp + 7) / 8 : 0;  // configurations grp, grp + 8, ...
+    const int rl = NT * 2 * L;
+    for (int e = tid; e < rl; e += 256) Tb[e] = 0;
+    int cur = -1;
+    for (long long s = kk; s < (long long)ncg * ipc; s += ngrp_blocks) {
+        const int cfg = grp + 8 * (int)(s / ipc);
+        const int it = (int)(s % ipc);
+        if (cfg != cur) {  // uniform over the workgroup
+            __syncthreads();
+            if (cur >= 0)
+                for (int e = tid; e < rl; e += 256) {
+                    atomicAdd((unsigned long long*)&rec[(size_t)cur * rl + e], Tb[e] * 8ull);
+                    Tb[e] = 0;
+                }
+            __syncthreads();
+            cur = cfg;
+        }
+        const int p = it / (nt * nt), Y = (it / nt) % nt, X = it % nt;
+        int f = 0, g = 1;
+        {
+            int q = p;
+            for (f = 0; f < RR - 1; ++f) {
+                if (q < RR - 1 - f) { g = f + 1 + q; break; }
+                q -= RR - 1 - f;
+            }
+        }
+        int car[NC], tri[NC];
+        {
+            int n = 0;
+            for (int e = 0; e < RR; ++e)
+                if (e != f && e != g && n < NC) {
+                    car[n] = e;
+                    const int a = min(e, f), c = max(e, g), b = e + f + g - a - c;
+                    tri[n] = triple_index(a, b, c, RR);
+                    ++n;
+                }
+        }
+        const int8_t* base = ws + (size_t)cfg * RR * 2 * plane;
+        const int8_t* pf = base + (size_t)(2 * f) * plane;  // rows of tile Y
+        const int8_t* pg = base + (size_t)(2 * g) * plane;  // rows of tile X
+        // carriers: G'^e_xy for x = column slot of tile X, y = the lane's row slots of tile Y
+        const int col = 32 * wy + (lane & 31);
+        uint32_t cw[NC][2][4];
+#pragma unroll
+        for (int ci = 0; ci < NC; ++ci)
+#pragma unroll
+            for (int pl = 0; pl < 2; ++pl)
+#pragma unroll
+                for (int g4 = 0; g4 < 4; ++g4)
+                    cw[ci][pl][g4] = *(const uint32_t*)(base + (size_t)(2 * car[ci] + pl) * plane +
+                                                        (size_t)(64 * X + col) * Np + 64 * Y + 32 * wx +
+                                                        8 * g4 + 4 * h5);
+        const int srow = tid >> 2, spart = 16 * (tid & 3);
+        const int8_t* src[4] = {pf + (size_t)(64 * Y + srow) * Np + spart,
+                                pf + plane + (size_t)(64 * Y + srow) * Np + spart,
+                                pg + (size_t)(64 * X + srow) * Np + spart,
+                                pg + plane + (size_t)(64 * X + srow) * Np + spart};
+        v4i vn[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) vn[k] = *(const v4i*)src[k];
+        v16i hh, xx, ll;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) hh[q] = xx[q] = ll[q] = 0;
+        for (int kc = 0; kc < nt; ++kc) {
+            __syncthreads();  // the previous chunk's MFMAs have read stg
+#pragma unroll
+            for (int k = 0; k < 4; ++k) *(v4i*)(stg + (k * 64 + srow) * kPitch + spart) = vn[k];
+            __syncthreads();
+            if (kc + 1 < nt) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) vn[k] = *(const v4i*)(src[k] + 64 * (kc + 1));
+            }
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {
+                const int ko = 32 * ks + 16 * h5;
+                const v4i ah = lds_v4(stg + (0 * 64 + 32 * wx + (lane & 31)) * kPitch + ko);
+                const v4i al = lds_v4(stg + (1 * 64 + 32 * wx + (lane & 31)) * kPitch + ko);
+                const v4i bh = lds_v4(stg + (2 * 64 + 32 * wy + (lane & 31)) * kPitch + ko);
+                const v4i bl = lds_v4(stg + (3 * 64 + 32 * wy + (lane & 31)) * kPitch + ko);
+                hh = __builtin_amdgcn_mfma_i32_32x32x32_i8(ah, bh, hh, 0, 0, 0);
+                ll = __builtin_amdgcn_mfma_i32_32x32x32_i8(al, bl, ll, 0, 0, 0);
+                xx = __builtin_amdgcn_mfma_i32_32x32x32_i8(ah, bl, xx, 0, 0, 0);
+                xx = __builtin_amdgcn_mfma_i32_32x32x32_i8(al, bh, xx, 0, 0, 0);
+            }
+        }
+        // epilogue: x = column slot col of tile X, y = row slot 32 wx + 8 g4 + 4 h5 + j of tile Y
+        const int x1 = 8 * (X % nb) + slot_d1(col), x2 = 8 * (X / nb) + slot_d2(col);
+        const int y1b = 8 * (Y % nb) + 4 * h5, y2b = 8 * (Y / nb) + 4 * wx;
+        long long ax[NC][4], ay[NC][4];
+#pragma unroll
+        for (int ci = 0; ci < NC; ++ci)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) ax[ci][j] = ay[ci][j] = 0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int j = q & 3, g4 = q >> 2;
+            const int P = 4096 * hh[q] + 64 * xx[q] + ll[q];
+#pragma unroll
+            for (int ci = 0; ci < NC; ++ci) {
+                const int hb = (int)(int8_t)(cw[ci][0][g4] >> (8 * j));
+                const int lb = (int)(int8_t)(cw[ci][1][g4] >> (8 * j));
+                const long long v = (long long)(64 * hb + lb) * (long long)P;
+                ax[ci][j] += v;
+                ay[ci][g4] += v;
+            }
+        }
+#pragma unroll
+        for (int ci = 0; ci < NC; ++ci) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                atomicAdd(&Tb[(tri[ci] * 2 + 0) * L + mod_l(x1 - y1b - j, L)],
+                          (unsigned long long)ax[ci][j]);
+#pragma unroll
+            for (int g4 = 0; g4 < 4; ++g4)
+                atomicAdd(&Tb[(tri[ci] * 2 + 1) * L + mod_l(x2 - y2b - g4, L)],
+                          (unsigned long long)ay[ci][g4]);
+        }
+    }
+    __syncthreads();
+    if (cur >= 0)
+        for (int e = tid; e < rl; e += 256)
+            atomicAdd((unsigned long long*)&rec[(size_t)cur * rl + e], Tb[e] * 8ull);
+}
+
+size_t store_lds(int RR) { return (size_t)2 * RR * 64 * kPitch + (size_t)2 * RR * 64 * 4 + 2 * 64 * 4; }
+
+template <int RR>
+hipError_t launch_triples_rr(const ShapeDev& sh, int cfg0, int ncfg, const TripleLayout& lay,
+                             void* ws, hipStream_t st) {
+    int dev = 0, ncu = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    char* w = (char*)ws;
+    int64_t* rec = (int64_t*)w;
+    int8_t* gw = (int8_t*)(w + lay.rec_bytes);
+    hipError_t e = hipMemsetAsync(rec, 0, lay.rec_bytes, st);
+    if (e != hipSuccess) return e;
+    const int ntp = lay.nt * (lay.nt + 1) / 2;
+    const long long items = (long long)ncfg * ntp;
+    const int g1 = (int)std::min<long long>(items, 16LL * ncu);
+    hipLaunchKernelGGL(k_gram_store<RR>, dim3(g1), dim3(256), store_lds(RR), st, sh, cfg0, ncfg, lay.nb, gw);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const long long ipc = (long long)(RR * (RR - 1) / 2) * lay.nt * lay.nt;
+    const long long per_grp = std::max<long long>(1, (long long)((ncfg + 7) / 8) * ipc);
+    const int g2 = 8 * (int)std::min<long long>(per_grp, (long long)(4 * ncu) / 8);
+    hipLaunchKernelGGL(k_triple_mfma<RR>, dim3(g2), dim3(256), 0, st, sh.L, ncfg, lay.nb,
+                       (const int8_t*)gw, rec);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+TripleLayout triple_layout(const ShapeDev& sh, int ncfg) {
+    TripleLayout t;
+    t.nb = (sh.L + 7) / 8;
+    t.nt = t.nb * t.nb;
+    t.Np = 64 * t.nt;
+    const int NT = sh.R * (sh.R - 1) * (sh.R - 2) / 6;
+    t.rec_bytes = ((size_t)ncfg * NT * 2 * sh.L * 8 + 255) & ~(size_t)255;
+    t.g_bytes = (size_t)ncfg * sh.R * 2 * (size_t)t.Np * t.Np;
+    return t;
+}
+
+const char* triples_unsupported(const ShapeDev& sh) {
+    if (sh.R < 3 || sh.R > 4) return "three-replica records need 3 or 4 replicas";
+    if (sh.L > kMaxL) return "three-replica records need L <= 32";
+    // |G'^f G'^g| <= L^2 (Ltau/2)^2 must fit the int32 accumulators
+    const unsigned long long half = (unsigned long long)sh.Lt / 2;
+    if ((unsigned long long)sh.L2 * half * half >= (1ull << 31))
+        return "L^2 (Ltau/2)^2 exceeds the int32 range of the pair products";
+    // a record of three carriers, 3 L^6 Ltau^3, must fit int64
+    const unsigned __int128 n = (unsigned)sh.L2, t = (unsigned)sh.Lt;
+    if (3 * n * n * n * t * t * t >= ((unsigned __int128)1 << 63))
+        return "3 L^6 Ltau^3 exceeds the int64 range of a record";
+    return nullptr;
+}
+
+hipError_t launch_triples(const ShapeDev& sh, int cfg0, int ncfg, void* ws, hipStream_t st) {
+    if (ncfg <= 0) return hipSuccess;
+    const TripleLayout lay = triple_layout(sh, ncfg);
+    switch (sh.R) {
+        case 3: return launch_triples_rr<3>(sh, cfg0, ncfg, lay, ws, st);
+        case 4: return launch_triples_rr<4>(sh, cfg0, ncfg, lay, ws, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace tfim

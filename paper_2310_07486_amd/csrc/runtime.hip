@@ -923,6 +923,64 @@ tfim_status tfim_get_thresholds(const tfim_plan* pl, uint32_t shape, uint32_t* T
     return TFIM_OK;
 }
 
+tfim_status tfim_xi3(const int64_t* rec, uint32_t L, uint32_t n_k, uint32_t n_per_k,
+                     uint32_t direction, double* xi) {
+    if (!rec || !xi || L < 2 || direction > 2) return fail(TFIM_EINVAL, "bad xi3 arguments");
+    const double pi = 3.14159265358979323846;
+    const double s = 2.0 * std::sin(pi / (double)L);
+    std::vector<__int128> A(L);
+    for (uint32_t i = 0; i < n_k; ++i) {
+        // exact bucket sums over records, then chi and a compensated F
+        std::fill(A.begin(), A.end(), (__int128)0);
+        for (uint32_t n = 0; n < n_per_k; ++n) {
+            const int64_t* r = rec + ((size_t)i * n_per_k + n) * 2 * L;
+            for (uint32_t d = 0; d < L; ++d) {
+                if (direction != 1) A[d] += r[d];
+                if (direction != 0) A[d] += r[L + d];
+            }
+        }
+        __int128 chi_i = 0;
+        double F = 0.0, comp = 0.0;
+        for (uint32_t d = 0; d < L; ++d) {
+            chi_i += A[d];
+            const double term = (double)A[d] * std::cos(2.0 * pi * (double)d / (double)L);
+            const double y = term - comp;
+            const double tsum = F + y;
+            comp = (tsum - F) - y;
+            F = tsum;
+        }
+        const double chi = (double)chi_i;
+        if (F <= 0.0) {
+            xi[i] = INFINITY;
+            continue;
+        }
+        const double ratio = chi / F;
+        xi[i] = ratio < 1.0 ? NAN : std::sqrt(ratio - 1.0) / s;
+    }
+    return TFIM_OK;
+}
+
+tfim_status tfim_binder(const int64_t* rec, uint32_t L, uint32_t Ltau, uint32_t n_k,
+                        uint32_t n_per_k, double* B) {
+    if (!rec || !B || L < 2 || Ltau < 2) return fail(TFIM_EINVAL, "bad binder arguments");
+    const size_t rl = 2 * (size_t)L + 3;
+    for (uint32_t i = 0; i < n_k; ++i) {
+        __int128 q2 = 0, q4 = 0;
+        for (uint32_t n = 0; n < n_per_k; ++n) {
+            const int64_t* r = rec + ((size_t)i * n_per_k + n) * rl;
+            q2 += r[2 * L + 1];
+            q4 += r[2 * L + 2];
+        }
+        if (q2 == 0) {
+            B[i] = NAN;
+            continue;
+        }
+        const long double lq2 = (long double)q2;
+        B[i] = (double)((long double)Ltau * Ltau * n_per_k * (long double)q4 / (lq2 * lq2));
+    }
+    return TFIM_OK;
+}
+
 tfim_status tfim_xi2(const int64_t* A, uint32_t L, uint32_t n_k, double* xi) {
     if (!A || !xi || L < 2) return fail(TFIM_EINVAL, "bad xi2 arguments");
     const double pi = 3.14159265358979323846;
@@ -1266,6 +1324,43 @@ tfim_status tfim_measure_range(tfim_plan* pl, uint32_t shape, uint32_t mode, uin
     if ((st = measure_core(pl, shape, mode, cfg0, ncfg, flags)) != TFIM_OK) return st;
     if (!out) return TFIM_OK;
     return copy_back(pl, out, pl->arena + h.oRec + (size_t)cfg0 * rl, (size_t)ncfg * rl, "copy records");
+}
+
+tfim_status tfim_triples_workspace(const tfim_plan* pl, uint32_t shape, uint32_t ncfg,
+                                   size_t* bytes) {
+    if (!pl || !bytes) return fail(TFIM_EINVAL, "null argument");
+    if (shape >= pl->shapes.size()) return fail(TFIM_EINVAL, "shape index out of range");
+    const tfim::ShapeDev d = dev_of(pl, shape);
+    if (const char* why = tfim::triples_unsupported(d)) return fail(TFIM_EUNSUPPORTED, why);
+    const tfim::TripleLayout lay = tfim::triple_layout(d, (int)ncfg);
+    *bytes = lay.rec_bytes + lay.g_bytes;
+    return TFIM_OK;
+}
+
+tfim_status tfim_measure_triples(tfim_plan* pl, uint32_t shape, uint32_t cfg0, uint32_t ncfg,
+                                 uint32_t flags, void* ws, size_t ws_bytes, int64_t* out,
+                                 size_t out_bytes) {
+    tfim_status st = shape_ok(pl, shape);
+    if (st != TFIM_OK) return st;
+    ShapeHost& h = pl->shapes[shape];
+    if (!h.S_ready) return fail(TFIM_ESTATE, "spins of this shape are not initialised");
+    const tfim::ShapeDev d = dev_of(pl, shape);
+    if (const char* why = tfim::triples_unsupported(d)) return fail(TFIM_EUNSUPPORTED, why);
+    const uint64_t ncfg_all = (uint64_t)h.s.n_k * 64 * h.s.n_words;
+    if ((uint64_t)cfg0 + ncfg > ncfg_all) return fail(TFIM_EINVAL, "configuration range out of bounds");
+    const tfim::TripleLayout lay = tfim::triple_layout(d, (int)ncfg);
+    if (!ws || ((uintptr_t)ws & 255)) return fail(TFIM_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < lay.rec_bytes + lay.g_bytes) return fail(TFIM_EINVAL, "workspace too small");
+    const uint32_t R = h.s.n_replicas;
+    const size_t rec_used = (size_t)ncfg * (R * (R - 1) * (R - 2) / 6) * 2 * h.s.L * 8;
+    if (out && out_bytes < rec_used) return fail(TFIM_EINVAL, "output buffer too small");
+    if (ncfg == 0) return TFIM_OK;
+    hipError_t e = hipSuccess;
+    if (!(flags & TFIM_MEASURE_REUSE_LAYOUT)) e = tfim::launch_transpose(d, pl->stream);
+    if (e == hipSuccess) e = tfim::launch_triples(d, (int)cfg0, (int)ncfg, ws, pl->stream);
+    if ((st = check_hip(pl, e, "triples")) != TFIM_OK) return st;
+    if (!out) return TFIM_OK;
+    return copy_back(pl, out, (const char*)ws, rec_used, "copy triple records");
 }
 
 tfim_status tfim_set_measure_mode(tfim_plan* pl, uint32_t mode) {

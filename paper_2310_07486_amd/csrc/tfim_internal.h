@@ -182,6 +182,16 @@ hipError_t launch_measure(const ShapeDev& sh, int mode, int cfg0, int ncfg, hipS
 hipError_t launch_buckets(const ShapeDev& sh, hipStream_t st);
 hipError_t launch_dump(const ShapeDev& sh, int cfg, int a, int b, hipStream_t st);
 bool measure_ok(const ShapeDev& sh);
+// Three-replica records (chi^(3), F^(3)) of configurations cfg0 .. cfg0+ncfg-1
+// into a caller workspace: int64 records [ncfg][triples][2][L] (rec_bytes,
+// 256-aligned), then the G' digit planes [ncfg][R][2][Np][Np] (g_bytes).
+struct TripleLayout {
+    int nb, nt, Np;  // 8x8 site blocks per edge, tiles, padded sites
+    size_t rec_bytes, g_bytes;
+};
+TripleLayout triple_layout(const ShapeDev& sh, int ncfg);
+const char* triples_unsupported(const ShapeDev& sh);  // nullptr if supported
+hipError_t launch_triples(const ShapeDev& sh, int cfg0, int ncfg, void* ws, hipStream_t st);
 int sweep_variants();
 const char* sweep_variant_name(int v);
 }  // namespace tfim

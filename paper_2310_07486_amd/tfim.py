@@ -40,6 +40,7 @@ SYMBOLS = [
     "tfim_set_schedule", "tfim_autotune", "tfim_get_tuning", "tfim_sync", "tfim_strerror",
     "tfim_last_error_detail", "tfim_set_variant", "tfim_set_timing", "tfim_get_timing",
     "tfim_measure_range", "tfim_set_measure_mode", "tfim_set_batch",
+    "tfim_triples_workspace", "tfim_measure_triples", "tfim_xi3", "tfim_binder",
 ]
 TFIM_MEASURE_REUSE_LAYOUT = 1
 
@@ -118,6 +119,10 @@ def lib():
             "tfim_get_timing": [P, P, P],
             "tfim_measure_range": [P, U32, U32, U32, U32, U32, P, SZ],
             "tfim_set_measure_mode": [P, U32],
+            "tfim_triples_workspace": [P, U32, U32, P],
+            "tfim_measure_triples": [P, U32, U32, U32, U32, P, SZ, P, SZ],
+            "tfim_xi3": [P, U32, U32, U32, U32, P],
+            "tfim_binder": [P, U32, U32, U32, U32, P],
             "tfim_strerror": [ctypes.c_int32],
             "tfim_last_error_detail": [],
         }
@@ -151,6 +156,26 @@ def tfim_xi2(A: np.ndarray, L: int) -> np.ndarray:
     return out
 
 
+def tfim_xi3(rec: np.ndarray, L: int, direction: int = 0) -> np.ndarray:
+    """xi^(3) per k-index from triple records [n_k][...][2L] (host-only call)."""
+    rec = np.ascontiguousarray(rec, dtype=np.int64)
+    n_k = rec.shape[0]
+    n_per_k = rec.size // (n_k * 2 * L)
+    out = np.zeros(n_k, dtype=np.float64)
+    _check(lib().tfim_xi3(_ptr(rec), L, n_k, n_per_k, direction, _ptr(out)), "tfim_xi3")
+    return out
+
+
+def tfim_binder(rec: np.ndarray, L: int, Ltau: int) -> np.ndarray:
+    """Binder ratio per k-index from pair records [n_k][...][2L+3] (host-only call)."""
+    rec = np.ascontiguousarray(rec, dtype=np.int64)
+    n_k = rec.shape[0]
+    n_per_k = rec.size // (n_k * (2 * L + 3))
+    out = np.zeros(n_k, dtype=np.float64)
+    _check(lib().tfim_binder(_ptr(rec), L, Ltau, n_k, n_per_k, _ptr(out)), "tfim_binder")
+    return out
+
+
 class Plan:
     """A plan over one or more shapes; owns a torch device arena.
 
@@ -178,6 +203,7 @@ class Plan:
         _check(lib().tfim_plan_sizes(self._h, ctypes.byref(sz)), "tfim_plan_sizes")
         self.sizes = {n: getattr(sz, n) for n, _ in tfim_sizes._fields_}
         self.arena = None
+        self._tws = None
         self.stream = None
         if bind:
             self.bind(device=device, stream=stream)
@@ -198,6 +224,7 @@ class Plan:
             lib().tfim_plan_destroy(self._h)
             self._h = None
         self.arena = None
+        self._tws = None
 
     def __del__(self):
         try:
@@ -336,6 +363,36 @@ class Plan:
         out = np.zeros((ncfg, P, 2 * L + 3), dtype=np.int64)
         _check(lib().tfim_measure_range(self._h, shape, mode, cfg0, ncfg, flags, _ptr(out),
                                         out.nbytes), "tfim_measure_range")
+        return out
+
+    def triples_workspace_bytes(self, shape: int, ncfg: int) -> int:
+        n = ctypes.c_size_t(0)
+        _check(lib().tfim_triples_workspace(self._h, shape, ncfg, ctypes.byref(n)),
+               "tfim_triples_workspace")
+        return n.value
+
+    def measure_triples(self, shape: int, cfg0: int, ncfg: int, flags: int = 0,
+                        copy: bool = True):
+        """Three-replica records [ncfg][triples][2L] of configurations
+        cfg = i*S + s; the device workspace is a torch tensor kept on the plan
+        and grown on demand.  copy=False only enqueues."""
+        import torch
+        L, Lt, W, R, nk = self._dims(shape)
+        need = self.triples_workspace_bytes(shape, ncfg)
+        if getattr(self, "_tws", None) is None or self._tws.numel() < need:
+            self._tws = None
+            self._tws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.arena.device)
+        ws = self._tws
+        if not copy:
+            _check(lib().tfim_measure_triples(self._h, shape, cfg0, ncfg, flags,
+                                              ctypes.c_void_p(ws.data_ptr()), ws.numel(), None, 0),
+                   "tfim_measure_triples")
+            return None
+        NT = R * (R - 1) * (R - 2) // 6
+        out = np.zeros((ncfg, NT, 2 * L), dtype=np.int64)
+        _check(lib().tfim_measure_triples(self._h, shape, cfg0, ncfg, flags,
+                                          ctypes.c_void_p(ws.data_ptr()), ws.numel(), _ptr(out),
+                                          out.nbytes), "tfim_measure_triples")
         return out
 
     def set_measure_mode(self, mode: int):

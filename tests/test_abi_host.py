@@ -119,3 +119,51 @@ def test_xi2_matches_oracle(oracle_lib):
             want = om.xi2(A[i], L)
             assert abs(got[i] - want) <= 1e-12 * abs(want), (L, i, got[i], want)
     assert math.isinf(tfim.tfim_xi2(np.array([[1] + [0] * 5 + [9] + [0] * 5]), 12)[0])
+
+
+def test_xi3_and_binder_match_oracle(oracle_lib):
+    """Host-side xi^(3) and Binder ratio against the oracle's exact sums."""
+    from oracle import measure as om
+    rng = np.random.default_rng(8)
+    for L in (6, 12, 24):
+        # a dominant d = 0 bucket and non-negative others keep 1 < chi/F
+        rec = rng.integers(0, 10**14, size=(3, 40, 4, 2 * L)).astype(np.int64)
+        rec[..., 0] = rec[..., 0] * 60 + 10**17
+        rec[..., L] = rec[..., L] * 60 + 10**17
+        for direction in (0, 1, 2):
+            got = tfim.tfim_xi3(rec, L, direction)
+            for i in range(3):
+                want = om.xi3(rec[i], L, direction)
+                assert got[i] == pytest.approx(want, rel=1e-12), (L, direction, i)
+        # per-k sums beyond int64 are exact (2^63 / 10^17 ~ 92 records)
+        big = np.full((1, 200, 1, 2 * L), 10**17, dtype=np.int64)
+        big[..., 1:L] = 0
+        big[..., L + 1:] = 0
+        assert tfim.tfim_xi3(big, L, 2)[0] == 0.0
+        pr = rng.integers(1, 10**12, size=(2, 30, 6, 2 * L + 3)).astype(np.int64)
+        pr[..., 2 * L + 2] = rng.integers(10**15, 10**17, size=(2, 30, 6))
+        B = tfim.tfim_binder(pr, L, 64)
+        for i in range(2):
+            assert B[i] == pytest.approx(om.binder(pr[i], L, 64), rel=1e-15)
+    ordered = np.zeros((1, 1, 2 * 3 + 3), dtype=np.int64)
+    ordered[0, 0, 7], ordered[0, 0, 8] = 6 * 6 * 81, 6 * 6 * 9 ** 4  # Q = 9 everywhere, Ltau = 6
+    assert tfim.tfim_binder(ordered, 3, 6)[0] == 1.0
+    assert math.isnan(tfim.tfim_binder(np.zeros((1, 1, 9), dtype=np.int64), 3, 6)[0])
+
+
+def test_triples_workspace_and_limits():
+    p = _plan([Shape(24, 2048, 16, 4, ladder(0.22, 0.36, 32))])
+    # records (4 triples x 48 int64, 256-aligned) + 4 replicas x 2 planes x 576^2
+    assert p.triples_workspace_bytes(0, 1) == 1536 + 4 * 2 * 576 * 576
+    assert p.triples_workspace_bytes(0, 100) == 100 * 1536 + 100 * 4 * 2 * 576 * 576
+    p.close()
+    p = _plan([Shape(10, 64, 1, 3, ladder(0.2, 0.3, 2))])
+    assert p.triples_workspace_bytes(0, 3) == 256 * ((3 * 1 * 20 * 8 + 255) // 256) + 3 * 3 * 2 * 256 * 256
+    p.close()
+    for sh in (Shape(8, 64, 1, 2, ladder(0.2, 0.3, 2)),      # two replicas
+               Shape(24, 4096, 1, 4, ladder(0.2, 0.3, 2))):  # L^2 (Ltau/2)^2 >= 2^31
+        p = _plan([sh])
+        with pytest.raises(tfim.TfimError) as ei:
+            p.triples_workspace_bytes(0, 1)
+        assert ei.value.status == tfim.TFIM_EUNSUPPORTED
+        p.close()

@@ -144,6 +144,64 @@ def measure_leg(plan, sh, torch, args):
     }
 
 
+def triples_ops(sh):
+    """Integer ops of the three-replica records of one configuration.
+    Algorithmic: the Gram of every replica, L^2 (L^2 + 1) Ltau, and the
+    product G^f G^g of every replica pair, 2 L^6 (multiply and add counted
+    as two).  Executed on the matrix cores: the stored Gram over padded 8x8
+    site blocks (tile pairs of the upper triangle, 64 x 64 x Ltau each) and
+    four int8 products per pair over the padded Np = 64 ceil(L/8)^2 sites
+    (two digits per factor)."""
+    L2, Lt, R = sh.L * sh.L, sh.Ltau, sh.n_replicas
+    P = R * (R - 1) // 2
+    nt = ((sh.L + 7) // 8) ** 2
+    Np = 64 * nt
+    alg = L2 * (L2 + 1) * Lt * R + 2 * L2 ** 3 * P
+    exe = (nt * (nt + 1) // 2) * 2 * 64 * 64 * (64 * ((Lt + 63) // 64)) * R + 4 * 2 * Np ** 3 * P
+    return alg, exe
+
+
+def triples_leg(plan, sh, torch, args):
+    """Three-replica records of every configuration (xi^(3)), in chunks, and
+    the Binder ratio from the pair records."""
+    from paper_2310_07486_amd import tfim
+    ncfg = len(sh.k) * sh.n_samples
+    alg, exe = triples_ops(sh)
+    chunk = min(args.triples_chunk, ncfg)
+    stream = torch.cuda.current_stream()
+    plan.measure_triples(0, 0, chunk, copy=False)  # layouts and workspace
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for c0 in range(0, ncfg, chunk):
+        plan.measure_triples(0, c0, min(chunk, ncfg - c0), flags=tfim.TFIM_MEASURE_REUSE_LAYOUT,
+                             copy=False)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    tops_alg = alg * ncfg / (ms * 1e-3) / 1e12
+    tops_exe = exe * ncfg / (ms * 1e-3) / 1e12
+    log("bench: xi3: %d configurations in chunks of %d: %.1f ms, %.1f TOP/s algorithmic, "
+        "%.1f TOP/s int8 executed" % (ncfg, chunk, ms, tops_alg, tops_exe))
+    rec = np.concatenate([plan.measure_triples(0, c0, min(chunk, ncfg - c0),
+                                               flags=tfim.TFIM_MEASURE_REUSE_LAYOUT)
+                          for c0 in range(0, ncfg, chunk)])
+    L = sh.L
+    xi3 = tfim.tfim_xi3(rec.reshape(len(sh.k), -1, 2 * L), L, 2)
+    pairs = plan.measure(0, tfim.TFIM_MEASURE_RECORDS)  # [k][s][pair][2L+3]
+    B = tfim.tfim_binder(pairs, L, sh.Ltau)
+    plan._tws = None
+    return {
+        "configurations": ncfg, "chunk": chunk, "ms": round(ms, 3),
+        "algorithmic_ops_per_configuration": alg, "int8_ops_per_configuration": exe,
+        "algorithmic_tops": round(tops_alg, 2), "int8_executed_tops": round(tops_exe, 2),
+        "frac_of_int8_peak": round(tops_exe / 5000.0, 4),
+        "xi3_over_L": [round(float(v) / L, 6) for v in xi3],
+        "binder": [round(float(v), 6) for v in B],
+    }
+
+
 def batched_leg(torch, args):
     """Five uneven sizes (L, Ltau) = (8,256) .. (24,2048), 512 samples each:
     the per-shape schedule (five sweep launches per sweep, one per size)
@@ -213,6 +271,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-measure", action="store_true")
+    ap.add_argument("--no-triples", action="store_true")
+    ap.add_argument("--triples-chunk", type=int, default=4096)
     ap.add_argument("--unbatched-cfgs", type=int, default=64)
     ap.add_argument("--plain-cfgs", type=int, default=1)
     ap.add_argument("--no-batched", action="store_true", help="skip the five-size batched leg")
@@ -316,6 +376,8 @@ def main():
         result["roofline"]["traffic_over_algorithmic"] = tr["traffic_over_algorithmic"]
     if not args.no_measure:
         result["measure"] = measure_leg(plan, sh, torch, args)
+    if not args.no_triples:
+        result["xi3"] = triples_leg(plan, sh, torch, args)
     plan.close()
     del plan
     torch.cuda.empty_cache()

@@ -22,14 +22,14 @@
 // 2. k_triple_mfma forms P = G'^f G'^g = 4096 h^f h^g + 64 (h^f l^g + l^f h^g)
 //    + l^f l^g with three exact int8 GEMMs on v_mfma_i32_32x32x32_i8 (the
 //    middle one with K doubled), |P| <= L^2 (Ltau/2)^2 < 2^31.  Its epilogue
-//    multiplies P_yx by G'^e_xy of each carrier e outside {f, g}, sums each
-//    lane's 16 products into four x-buckets and four y-buckets in registers
-//    and adds those to LDS buckets of the triple {e, f, g}.  Records are
-//    scaled by 8 at the flush (G = 2 G').  Work items (configuration, pair,
-//    output tile) are handed out so that the workgroups with the same
-//    blockIdx.x mod 8 (one XCD under round-robin dispatch) share one
-//    configuration at a time, whose 2 R Np^2 bytes then stay in that XCD's
-//    L2.
+//    multiplies P_yx by G'^e_xy of each carrier e outside {f, g} and sums
+//    each lane's 16 products into four x-buckets and four y-buckets of the
+//    triple {e, f, g}.  A work item is one output tile of one configuration
+//    with every replica pair unrolled, so these sums stay in registers
+//    across the pairs and reach the LDS buckets once per tile.  Records are
+//    scaled by 8 at the flush (G = 2 G').  Work items are handed out so that
+//    the workgroups with the same blockIdx.x mod 8 (one XCD under round-robin
+//    dispatch) share one configuration at a time.
 #include <algorithm>
 
 #include "tfim_internal.h"
@@ -79,18 +79,6 @@ __device__ __forceinline__ int mod_l(int v, int L) {
     return v < 0 ? v + L : v;
 }
 
-// Index of the sorted triple a < b < c among the lexicographic triples of R.
-__device__ __forceinline__ int triple_index(int a, int b, int c, int R) {
-    int t = 0;
-    for (int i = 0; i < R; ++i)
-        for (int j = i + 1; j < R; ++j)
-            for (int k = j + 1; k < R; ++k) {
-                if (i == a && j == b && k == c) return t;
-                ++t;
-            }
-    return 0;
-}
-
 // ---------------------------------------------------------------------------
 // G' of every replica into the workspace, digit planes [cl][r][plane][Np][Np].
 // ---------------------------------------------------------------------------
@@ -131,18 +119,38 @@ __global__ void __launch_bounds__(256) k_gram_store(ShapeDev sh, int cfg0, int n
         for (int r = 0; r < RR; ++r)
 #pragma unroll
             for (int q = 0; q < 16; ++q) acc[r][q] = 0;
+        constexpr int kPer = (2 * RR * 64 + 255) / 256;  // bit rows per thread
+        const int nrows = (diag ? 1 : 2) * RR * 64;
+        uint64_t vn[kPer];
+        __syncthreads();  // xyA, xyB written
+        auto fetch = [&](int c) {
+            const uint64_t vm = low_bits(Lt - 64 * c);
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) {
+                const int e = tid + 256 * k;
+                vn[k] = 0;
+                if (e < nrows) {
+                    const int side = e / (RR * 64), rr = (e / 64) % RR, row = e & 63;
+                    const int xy = (side ? xyB : xyA)[row];
+                    const size_t m = (size_t)(cfg0 + cl) * RR + rr;
+                    if (xy >= 0) vn[k] = sh.Pt[(m * sh.nc + c) * sh.nxp + xy] & vm;
+                }
+            }
+        };
+        fetch(0);
         for (int c = 0; c < sh.nc; ++c) {
             __syncthreads();
-            const uint64_t vm = low_bits(Lt - 64 * c);
-            for (int e = tid; e < (diag ? 1 : 2) * RR * 64; e += 256) {
-                const int side = e / (RR * 64), rr = (e / 64) % RR, row = e & 63;
-                const int xy = (side ? xyB : xyA)[row];
-                const size_t m = (size_t)(cfg0 + cl) * RR + rr;
-                const uint64_t v = xy >= 0 ? (sh.Pt[(m * sh.nc + c) * sh.nxp + xy] & vm) : 0ull;
-                (side ? nB : nA)[rr * 64 + row] += __popcll(v);
-                unpack64(v, (side ? Bl : Al) + (rr * 64 + row) * kPitch);
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) {
+                const int e = tid + 256 * k;
+                if (e < nrows) {
+                    const int side = e / (RR * 64), rr = (e / 64) % RR, row = e & 63;
+                    (side ? nB : nA)[rr * 64 + row] += __popcll(vn[k]);
+                    unpack64(vn[k], (side ? Bl : Al) + (rr * 64 + row) * kPitch);
+                }
             }
             __syncthreads();
+            if (c + 1 < sh.nc) fetch(c + 1);
 #pragma unroll
             for (int ks = 0; ks < 2; ++ks) {
                 const int ko = 32 * ks + 16 * (lane >> 5);
@@ -194,20 +202,136 @@ __global__ void __launch_bounds__(256) k_gram_store(ShapeDev sh, int cfg0, int n
 // ---------------------------------------------------------------------------
 // Pair products and the carrier epilogue; records [cl][NT][2][L].
 // ---------------------------------------------------------------------------
+constexpr int pair_f(int R, int p) {
+    int f = 0;
+    while (p >= R - 1 - f) { p -= R - 1 - f; ++f; }
+    return f;
+}
+constexpr int pair_g(int R, int p) {
+    int f = 0;
+    while (p >= R - 1 - f) { p -= R - 1 - f; ++f; }
+    return f + 1 + p;
+}
+constexpr int carrier_of(int R, int f, int g, int ci) {
+    int n = 0;
+    for (int e = 0; e < R; ++e)
+        if (e != f && e != g) {
+            if (n == ci) return e;
+            ++n;
+        }
+    return 0;
+}
+constexpr int triple_of(int R, int e, int f, int g) {  // index of the sorted triple {e, f, g}
+    const int a = e < f ? e : f, c = e > g ? e : g, b = e + f + g - a - c;
+    int t = 0;
+    for (int i = 0; i < R; ++i)
+        for (int j = i + 1; j < R; ++j)
+            for (int k = j + 1; k < R; ++k) {
+                if (i == a && j == b && k == c) return t;
+                ++t;
+            }
+    return 0;
+}
+
+template <int RR>
+struct TriAcc {
+    static constexpr int NT = RR * (RR - 1) * (RR - 2) / 6;
+    long long tx[NT][4], ty[NT][4];  // x-buckets by j, y-buckets by g4
+    uint32_t cw[RR][2][4];           // G'^e digits at (x = column slot, y = row slots)
+};
+
+struct TriGeom {
+    const int8_t* base;
+    size_t plane;
+    int Np, nt, X, Y, tid, lane, wx, wy, h5;
+    uint8_t* stg;
+};
+
+template <int RR, int C, int P>
+struct CarrierStep {
+    static __device__ __forceinline__ void run(TriAcc<RR>& a, int q, int Pv) {
+        constexpr int f = pair_f(RR, P), g = pair_g(RR, P);
+        constexpr int e = carrier_of(RR, f, g, C);
+        constexpr int t = triple_of(RR, e, f, g);
+        const int j = q & 3, g4 = q >> 2;
+        const int hb = (int)(int8_t)(a.cw[e][0][g4] >> (8 * j));
+        const int lb = (int)(int8_t)(a.cw[e][1][g4] >> (8 * j));
+        const long long v = (long long)(64 * hb + lb) * (long long)Pv;
+        a.tx[t][j] += v;
+        a.ty[t][g4] += v;
+        CarrierStep<RR, C + 1, P>::run(a, q, Pv);
+    }
+};
+template <int RR, int P>
+struct CarrierStep<RR, RR - 2, P> {
+    static __device__ __forceinline__ void run(TriAcc<RR>&, int, int) {}
+};
+
+template <int RR, int P>
+struct PairStep {
+    static __device__ __forceinline__ void run(TriAcc<RR>& a, const TriGeom& G) {
+        constexpr int f = pair_f(RR, P), g = pair_g(RR, P);
+        const int8_t* pf = G.base + (size_t)(2 * f) * G.plane;  // rows of tile Y
+        const int8_t* pg = G.base + (size_t)(2 * g) * G.plane;  // rows of tile X
+        const int srow = G.tid >> 2, spart = 16 * (G.tid & 3);
+        const int8_t* src[4] = {pf + (size_t)(64 * G.Y + srow) * G.Np + spart,
+                                pf + G.plane + (size_t)(64 * G.Y + srow) * G.Np + spart,
+                                pg + (size_t)(64 * G.X + srow) * G.Np + spart,
+                                pg + G.plane + (size_t)(64 * G.X + srow) * G.Np + spart};
+        v4i vn[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) vn[k] = *(const v4i*)src[k];
+        v16i hh, xx, ll;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) hh[q] = xx[q] = ll[q] = 0;
+        const int lane = G.lane;
+        for (int kc = 0; kc < G.nt; ++kc) {
+            __syncthreads();  // the previous chunk's MFMAs have read stg
+#pragma unroll
+            for (int k = 0; k < 4; ++k) *(v4i*)(G.stg + (k * 64 + srow) * kPitch + spart) = vn[k];
+            __syncthreads();
+            if (kc + 1 < G.nt) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) vn[k] = *(const v4i*)(src[k] + 64 * (kc + 1));
+            }
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {
+                const int ko = 32 * ks + 16 * G.h5;
+                const v4i ah = lds_v4(G.stg + (0 * 64 + 32 * G.wx + (lane & 31)) * kPitch + ko);
+                const v4i al = lds_v4(G.stg + (1 * 64 + 32 * G.wx + (lane & 31)) * kPitch + ko);
+                const v4i bh = lds_v4(G.stg + (2 * 64 + 32 * G.wy + (lane & 31)) * kPitch + ko);
+                const v4i bl = lds_v4(G.stg + (3 * 64 + 32 * G.wy + (lane & 31)) * kPitch + ko);
+                hh = __builtin_amdgcn_mfma_i32_32x32x32_i8(ah, bh, hh, 0, 0, 0);
+                ll = __builtin_amdgcn_mfma_i32_32x32x32_i8(al, bl, ll, 0, 0, 0);
+                xx = __builtin_amdgcn_mfma_i32_32x32x32_i8(ah, bl, xx, 0, 0, 0);
+                xx = __builtin_amdgcn_mfma_i32_32x32x32_i8(al, bh, xx, 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int Pv = 4096 * hh[q] + 64 * xx[q] + ll[q];
+            CarrierStep<RR, 0, P>::run(a, q, Pv);
+        }
+        PairStep<RR, P + 1>::run(a, G);
+    }
+};
+template <int RR>
+struct PairStep<RR, RR * (RR - 1) / 2> {
+    static __device__ __forceinline__ void run(TriAcc<RR>&, const TriGeom&) {}
+};
+
 template <int RR>
 __global__ void __launch_bounds__(256) k_triple_mfma(int L, int ncfg, int nb,
                                                      const int8_t* __restrict__ ws,
                                                      int64_t* __restrict__ rec) {
-    constexpr int PP = RR * (RR - 1) / 2;
-    constexpr int NT = RR * (RR - 1) * (RR - 2) / 6;
-    constexpr int NC = RR - 2;  // carriers of a pair
+    constexpr int NT = TriAcc<RR>::NT;
     __shared__ __align__(16) uint8_t stg[4 * 64 * kPitch];  // f high, f low, g high, g low
     __shared__ unsigned long long Tb[NT * 2 * kMaxL];
     const int nt = nb * nb, Np = 64 * nt;
     const size_t plane = (size_t)Np * Np;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int wx = wv & 1, wy = wv >> 1, h5 = lane >> 5;
-    const int ipc = PP * nt * nt;  // items per configuration
+    const int ipc = nt * nt;  // output tiles per configuration, all pairs each
     const int grp = blockIdx.x & 7, ngrp_blocks = (int)(gridDim.x >> 3), kk = (int)(blockIdx.x >> 3);
     const int ncg = grp < ncfg ? (ncfg - grp + 7) / 8 : 0;  // configurations grp, grp + 8, ...
     const int rl = NT * 2 * L;
@@ -226,105 +350,35 @@ __global__ void __launch_bounds__(256) k_triple_mfma(int L, int ncfg, int nb,
             __syncthreads();
             cur = cfg;
         }
-        const int p = it / (nt * nt), Y = (it / nt) % nt, X = it % nt;
-        int f = 0, g = 1;
-        {
-            int q = p;
-            for (f = 0; f < RR - 1; ++f) {
-                if (q < RR - 1 - f) { g = f + 1 + q; break; }
-                q -= RR - 1 - f;
-            }
-        }
-        int car[NC], tri[NC];
-        {
-            int n = 0;
-            for (int e = 0; e < RR; ++e)
-                if (e != f && e != g && n < NC) {
-                    car[n] = e;
-                    const int a = min(e, f), c = max(e, g), b = e + f + g - a - c;
-                    tri[n] = triple_index(a, b, c, RR);
-                    ++n;
-                }
-        }
+        const int Y = it / nt, X = it % nt;
         const int8_t* base = ws + (size_t)cfg * RR * 2 * plane;
-        const int8_t* pf = base + (size_t)(2 * f) * plane;  // rows of tile Y
-        const int8_t* pg = base + (size_t)(2 * g) * plane;  // rows of tile X
-        // carriers: G'^e_xy for x = column slot of tile X, y = the lane's row slots of tile Y
         const int col = 32 * wy + (lane & 31);
-        uint32_t cw[NC][2][4];
+        TriAcc<RR> a;
 #pragma unroll
-        for (int ci = 0; ci < NC; ++ci)
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) a.tx[t][j] = a.ty[t][j] = 0;
+#pragma unroll
+        for (int e = 0; e < RR; ++e)
 #pragma unroll
             for (int pl = 0; pl < 2; ++pl)
 #pragma unroll
                 for (int g4 = 0; g4 < 4; ++g4)
-                    cw[ci][pl][g4] = *(const uint32_t*)(base + (size_t)(2 * car[ci] + pl) * plane +
-                                                        (size_t)(64 * X + col) * Np + 64 * Y + 32 * wx +
-                                                        8 * g4 + 4 * h5);
-        const int srow = tid >> 2, spart = 16 * (tid & 3);
-        const int8_t* src[4] = {pf + (size_t)(64 * Y + srow) * Np + spart,
-                                pf + plane + (size_t)(64 * Y + srow) * Np + spart,
-                                pg + (size_t)(64 * X + srow) * Np + spart,
-                                pg + plane + (size_t)(64 * X + srow) * Np + spart};
-        v4i vn[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) vn[k] = *(const v4i*)src[k];
-        v16i hh, xx, ll;
-#pragma unroll
-        for (int q = 0; q < 16; ++q) hh[q] = xx[q] = ll[q] = 0;
-        for (int kc = 0; kc < nt; ++kc) {
-            __syncthreads();  // the previous chunk's MFMAs have read stg
-#pragma unroll
-            for (int k = 0; k < 4; ++k) *(v4i*)(stg + (k * 64 + srow) * kPitch + spart) = vn[k];
-            __syncthreads();
-            if (kc + 1 < nt) {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) vn[k] = *(const v4i*)(src[k] + 64 * (kc + 1));
-            }
-#pragma unroll
-            for (int ks = 0; ks < 2; ++ks) {
-                const int ko = 32 * ks + 16 * h5;
-                const v4i ah = lds_v4(stg + (0 * 64 + 32 * wx + (lane & 31)) * kPitch + ko);
-                const v4i al = lds_v4(stg + (1 * 64 + 32 * wx + (lane & 31)) * kPitch + ko);
-                const v4i bh = lds_v4(stg + (2 * 64 + 32 * wy + (lane & 31)) * kPitch + ko);
-                const v4i bl = lds_v4(stg + (3 * 64 + 32 * wy + (lane & 31)) * kPitch + ko);
-                hh = __builtin_amdgcn_mfma_i32_32x32x32_i8(ah, bh, hh, 0, 0, 0);
-                ll = __builtin_amdgcn_mfma_i32_32x32x32_i8(al, bl, ll, 0, 0, 0);
-                xx = __builtin_amdgcn_mfma_i32_32x32x32_i8(ah, bl, xx, 0, 0, 0);
-                xx = __builtin_amdgcn_mfma_i32_32x32x32_i8(al, bh, xx, 0, 0, 0);
-            }
-        }
-        // epilogue: x = column slot col of tile X, y = row slot 32 wx + 8 g4 + 4 h5 + j of tile Y
+                    a.cw[e][pl][g4] = *(const uint32_t*)(base + (size_t)(2 * e + pl) * plane +
+                                                         (size_t)(64 * X + col) * Np + 64 * Y + 32 * wx +
+                                                         8 * g4 + 4 * h5);
+        const TriGeom G{base, plane, Np, nt, X, Y, tid, lane, wx, wy, h5, stg};
+        PairStep<RR, 0>::run(a, G);
         const int x1 = 8 * (X % nb) + slot_d1(col), x2 = 8 * (X / nb) + slot_d2(col);
         const int y1b = 8 * (Y % nb) + 4 * h5, y2b = 8 * (Y / nb) + 4 * wx;
-        long long ax[NC][4], ay[NC][4];
 #pragma unroll
-        for (int ci = 0; ci < NC; ++ci)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) ax[ci][j] = ay[ci][j] = 0;
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int j = q & 3, g4 = q >> 2;
-            const int P = 4096 * hh[q] + 64 * xx[q] + ll[q];
-#pragma unroll
-            for (int ci = 0; ci < NC; ++ci) {
-                const int hb = (int)(int8_t)(cw[ci][0][g4] >> (8 * j));
-                const int lb = (int)(int8_t)(cw[ci][1][g4] >> (8 * j));
-                const long long v = (long long)(64 * hb + lb) * (long long)P;
-                ax[ci][j] += v;
-                ay[ci][g4] += v;
-            }
-        }
-#pragma unroll
-        for (int ci = 0; ci < NC; ++ci) {
+        for (int t = 0; t < NT; ++t) {
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                atomicAdd(&Tb[(tri[ci] * 2 + 0) * L + mod_l(x1 - y1b - j, L)],
-                          (unsigned long long)ax[ci][j]);
+                atomicAdd(&Tb[(t * 2 + 0) * L + mod_l(x1 - y1b - j, L)], (unsigned long long)a.tx[t][j]);
 #pragma unroll
             for (int g4 = 0; g4 < 4; ++g4)
-                atomicAdd(&Tb[(tri[ci] * 2 + 1) * L + mod_l(x2 - y2b - g4, L)],
-                          (unsigned long long)ay[ci][g4]);
+                atomicAdd(&Tb[(t * 2 + 1) * L + mod_l(x2 - y2b - g4, L)], (unsigned long long)a.ty[t][g4]);
         }
     }
     __syncthreads();
@@ -351,7 +405,7 @@ hipError_t launch_triples_rr(const ShapeDev& sh, int cfg0, int ncfg, const Tripl
     const int g1 = (int)std::min<long long>(items, 16LL * ncu);
     hipLaunchKernelGGL(k_gram_store<RR>, dim3(g1), dim3(256), store_lds(RR), st, sh, cfg0, ncfg, lay.nb, gw);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const long long ipc = (long long)(RR * (RR - 1) / 2) * lay.nt * lay.nt;
+    const long long ipc = (long long)lay.nt * lay.nt;
     const long long per_grp = std::max<long long>(1, (long long)((ncfg + 7) / 8) * ipc);
     const int g2 = 8 * (int)std::min<long long>(per_grp, (long long)(4 * ncu) / 8);
     hipLaunchKernelGGL(k_triple_mfma<RR>, dim3(g2), dim3(256), 0, st, sh.L, ncfg, lay.nb,

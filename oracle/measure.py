@@ -230,3 +230,60 @@ def binder(records, L: int, Ltau: int) -> float:
         return math.nan
     from fractions import Fraction
     return float(Fraction(Ltau * Ltau * n * q4, q2 * q2))
+
+
+# ---------------------------------------------------------------------------
+# Two-time correlations (Methods, "Two-times observables").
+#
+# C_A(tau) is the average over tau1 of A(S_tau1) A(S_tau1+tau) (periodic in
+# tau).  With A = sigma^Z_x summed over x, and A = sigma^Z_x sigma^Z_y summed
+# over pairs, both follow from the time Gram H = S^T S (Ltau x Ltau,
+# H_t1t2 = sum_x S_x,t1 S_x,t2):
+#   c[d]  = sum_t1 H_t1,(t1+d) mod Ltau          -> C(tau)  = c / (L^2 Ltau)
+#   q2[d] = sum_t1 H_t1,(t1+d) mod Ltau ^ 2      -> Q2(tau) = q2 / (L^4 Ltau)
+# (the garbled Ltau^D, Ltau^{2D} normalisations read as L^D, L^{2D}, which
+# give C(0) = Q2(0) = 1).  The record of one configuration sums c and q2 over
+# the replicas, each an independent sample of the same thermal average.
+# ---------------------------------------------------------------------------
+def time_gram(S: np.ndarray) -> np.ndarray:
+    """H = S^T S as int64 (Ltau x Ltau); float64 products are exact (|H| <= L^2)."""
+    return (S.T @ S).astype(np.int64)
+
+
+def time_bands(H: np.ndarray):
+    """c[d] and q2[d] for d = 0..Ltau-1: sums of H and H^2 along the periodic
+    diagonal t2 - t1 = d (mod Ltau)."""
+    Lt = H.shape[0]
+    c = np.zeros(Lt, dtype=np.int64)
+    q2 = np.zeros(Lt, dtype=np.int64)
+    t1 = np.arange(Lt)
+    for d in range(Lt):
+        band = H[t1, (t1 + d) % Lt]
+        c[d] = band.sum()
+        q2[d] = (band * band).sum()
+    return c, q2
+
+
+def time_record(Ss) -> np.ndarray:
+    """[c[0..Ltau-1], q2[0..Ltau-1]] (int64) summed over the replicas' S."""
+    Lt = Ss[0].shape[1]
+    out = np.zeros(2 * Lt, dtype=np.int64)
+    for S in Ss:
+        c, q2 = time_bands(time_gram(S))
+        out[:Lt] += c
+        out[Lt:] += q2
+    return out
+
+
+def measure_time_chain(chain, k_indices=None, sample_indices=None) -> np.ndarray:
+    """Two-time records for every (k-index i, sample si) of an oracle Chain:
+    int64 [n_i][n_si][2 Ltau]."""
+    R, Lt = chain.R, chain.Ltau
+    winv = chain.winv()
+    ks = range(chain.n_k) if k_indices is None else k_indices
+    ss = range(chain.ns) if sample_indices is None else sample_indices
+    out = np.zeros((len(ks), len(ss), 2 * Lt), dtype=np.int64)
+    for ii, i in enumerate(ks):
+        for jj, si in enumerate(ss):
+            out[ii, jj] = time_record([spin_matrix(chain.S[r, winv[r, si, i], si]) for r in range(R)])
+    return out

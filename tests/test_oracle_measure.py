@@ -250,3 +250,61 @@ def test_binder_closed_forms():
     q2 = int(two[:, 2 * L + 1].sum())
     q4 = int(two[:, 2 * L + 2].sum())
     assert om.binder(two, L, Lt) == pytest.approx(Lt ** 2 * 2 * q4 / q2 ** 2, rel=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# Two-time correlations.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("L,Lt", [(2, 4), (3, 6), (2, 10)])
+def test_time_bands_match_brute_force_loops(L, Lt):
+    rng = np.random.default_rng(20 + L + Lt)
+    S = _rand_S(rng, L, Lt).astype(int)  # [tau][xy]
+    L2 = L * L
+    c = [0] * Lt
+    q2 = [0] * Lt
+    for t1 in range(Lt):
+        for d in range(Lt):
+            h = sum(S[t1][x] * S[(t1 + d) % Lt][x] for x in range(L2))
+            c[d] += h
+            q2[d] += h * h
+    rec = om.time_record([om.spin_matrix(S.astype(np.int8))])
+    assert rec.tolist() == c + q2
+
+
+def test_time_bands_identities():
+    """c[0] = L^2 Ltau, q2[0] = L^4 Ltau; c, q2 even under d -> -d;
+    sum_d q2[d] = sum_xy G_xy^2 (the trace of H^2 equals that of G^2);
+    sum_d c[d] = sum_x (sum_tau S_x,tau)^2; unchanged by a shift along tau."""
+    rng = np.random.default_rng(21)
+    L, Lt = 4, 24
+    S = om.spin_matrix(_rand_S(rng, L, Lt))
+    rec = om.time_record([S])
+    c, q2 = rec[:Lt], rec[Lt:]
+    assert c[0] == L * L * Lt and q2[0] == L ** 4 * Lt
+    neg = (-np.arange(Lt)) % Lt
+    assert np.array_equal(c, c[neg]) and np.array_equal(q2, q2[neg])
+    G = om.gram(S)
+    assert q2.sum() == (G * G).sum()
+    assert c.sum() == int((S.sum(axis=1) ** 2).sum())
+    assert np.array_equal(om.time_record([np.roll(S, 5, axis=1)]), rec)
+
+
+def test_time_bands_closed_forms():
+    """A product state S_x,tau = a_x b_tau has H = L^2 b b^T: c = L^2 times the
+    periodic autocorrelation of b, q2 = L^4 Ltau at every d.  Independent
+    random spins: E q2[d != 0] = Ltau L^2."""
+    rng = np.random.default_rng(22)
+    L, Lt = 3, 16
+    a = rng.choice([-1, 1], size=L * L)
+    b = rng.choice([-1, 1], size=Lt)
+    S = np.outer(a, b).astype(np.float64)
+    rec = om.time_record([S])
+    auto = np.array([sum(b[t] * b[(t + d) % Lt] for t in range(Lt)) for d in range(Lt)])
+    assert np.array_equal(rec[:Lt], L * L * auto)
+    assert np.all(rec[Lt:] == L ** 4 * Lt)
+    L, Lt, n = 2, 8, 3000
+    q = np.zeros(Lt)
+    for _ in range(n):
+        q += om.time_record([om.spin_matrix(_rand_S(rng, L, Lt))])[Lt:]
+    mean = q[1:] / n
+    assert np.all(np.abs(mean - Lt * L * L) < 0.1 * Lt * L * L)

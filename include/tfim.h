@@ -202,6 +202,22 @@ tfim_status tfim_measure_triples(tfim_plan *plan, uint32_t shape, uint32_t cfg0,
                                  uint32_t flags, void *workspace, size_t workspace_bytes,
                                  int64_t *out, size_t out_bytes);
 
+/* Two-time records (Methods, "Two-times observables"): for configuration
+ * cfg = i*samples + s, with the time Gram H^r = S^rT S^r of each replica
+ * (Ltau x Ltau, H_t1t2 = sum_x S_x,t1 S_x,t2),
+ *   c[d]  = sum_r sum_t1 H^r_t1,(t1+d) mod Ltau
+ *   q2[d] = sum_r sum_t1 (H^r_t1,(t1+d) mod Ltau)^2,   d = 0..Ltau-1,
+ * as int64 [ncfg][2][Ltau] = [c[0..Ltau-1], q2[0..Ltau-1]], exact.
+ * C(tau) = c[tau] / (R L^2 Ltau) and Q2(tau) = q2[tau] / (R L^4 Ltau)
+ * (C(0) = Q2(0) = 1).  Needs 1..4 replicas, L <= 32, Ltau <= 4096 (else
+ * TFIM_EUNSUPPORTED).  ws: caller-owned device memory, 256-byte aligned, at
+ * least ncfg*2*Ltau*8 bytes, holding the records afterwards.  flags as for
+ * tfim_measure_range.  out == NULL: enqueue only (asynchronous); otherwise
+ * the call synchronises and copies the records to out. */
+tfim_status tfim_measure_time(tfim_plan *plan, uint32_t shape, uint32_t cfg0, uint32_t ncfg,
+                              uint32_t flags, void *workspace, size_t workspace_bytes,
+                              int64_t *out, size_t out_bytes);
+
 /* xi^(3) per k-index (Methods, "One-time observables") from three-replica
  * records rec[n_k][n_per_k][2L] (n_per_k = samples x triples x measurements):
  * A[d] = sum of T_x[d] (direction 0), T_y[d] (1) or both (2), summed exactly;

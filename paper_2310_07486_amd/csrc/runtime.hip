@@ -309,8 +309,9 @@ tfim_status tfim_plan_create(const tfim_shape* shapes, uint32_t n_shapes, uint64
         h.nBuck = nk * 2 * h.s.L * 8;
         h.nc = (int)((Lt + 63) / 64);
         h.nx = (int)((L2 + 63) / 64);
-        h.nPt = h.P ? nk * S * R * (size_t)h.nc * 64 * h.nx * 8 : 0;
-        h.nPx = h.P ? nk * S * R * (size_t)h.nx * Lt * 8 : 0;
+        // bit layouts for every measurement, the one-replica two-time records included
+        h.nPt = nk * S * R * (size_t)h.nc * 64 * h.nx * 8;
+        h.nPx = nk * S * R * (size_t)h.nx * Lt * 8;
         h.nDump = h.P ? (2 * L2 * L2 + Lt * Lt) * 4 : 0;
         h.oS = off; off = align256(off + h.nS); tot_S += h.nS;
         h.oJ = off; off = align256(off + h.nJ); tot_J += h.nJ;
@@ -1361,6 +1362,30 @@ tfim_status tfim_measure_triples(tfim_plan* pl, uint32_t shape, uint32_t cfg0, u
     if ((st = check_hip(pl, e, "triples")) != TFIM_OK) return st;
     if (!out) return TFIM_OK;
     return copy_back(pl, out, (const char*)ws, rec_used, "copy triple records");
+}
+
+tfim_status tfim_measure_time(tfim_plan* pl, uint32_t shape, uint32_t cfg0, uint32_t ncfg,
+                              uint32_t flags, void* ws, size_t ws_bytes, int64_t* out,
+                              size_t out_bytes) {
+    tfim_status st = shape_ok(pl, shape);
+    if (st != TFIM_OK) return st;
+    ShapeHost& h = pl->shapes[shape];
+    if (!h.S_ready) return fail(TFIM_ESTATE, "spins of this shape are not initialised");
+    const tfim::ShapeDev d = dev_of(pl, shape);
+    if (const char* why = tfim::timecorr_unsupported(d)) return fail(TFIM_EUNSUPPORTED, why);
+    const uint64_t ncfg_all = (uint64_t)h.s.n_k * 64 * h.s.n_words;
+    if ((uint64_t)cfg0 + ncfg > ncfg_all) return fail(TFIM_EINVAL, "configuration range out of bounds");
+    const size_t need = tfim::timecorr_record_bytes(d, (int)ncfg);
+    if (!ws || ((uintptr_t)ws & 255)) return fail(TFIM_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < need) return fail(TFIM_EINVAL, "workspace too small");
+    if (out && out_bytes < need) return fail(TFIM_EINVAL, "output buffer too small");
+    if (ncfg == 0) return TFIM_OK;
+    hipError_t e = hipSuccess;
+    if (!(flags & TFIM_MEASURE_REUSE_LAYOUT)) e = tfim::launch_transpose(d, pl->stream);
+    if (e == hipSuccess) e = tfim::launch_timecorr(d, (int)cfg0, (int)ncfg, (int64_t*)ws, pl->stream);
+    if ((st = check_hip(pl, e, "two-time records")) != TFIM_OK) return st;
+    if (!out) return TFIM_OK;
+    return copy_back(pl, out, (const char*)ws, need, "copy two-time records");
 }
 
 tfim_status tfim_set_measure_mode(tfim_plan* pl, uint32_t mode) {

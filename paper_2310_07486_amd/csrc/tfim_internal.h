@@ -192,6 +192,11 @@ struct TripleLayout {
 TripleLayout triple_layout(const ShapeDev& sh, int ncfg);
 const char* triples_unsupported(const ShapeDev& sh);  // nullptr if supported
 hipError_t launch_triples(const ShapeDev& sh, int cfg0, int ncfg, void* ws, hipStream_t st);
+// Two-time records (c, q2 along the periodic diagonals of H = S^T S, summed
+// over replicas) of configurations cfg0 .. cfg0+ncfg-1: int64 [ncfg][2][Lt].
+const char* timecorr_unsupported(const ShapeDev& sh);  // nullptr if supported
+size_t timecorr_record_bytes(const ShapeDev& sh, int ncfg);
+hipError_t launch_timecorr(const ShapeDev& sh, int cfg0, int ncfg, int64_t* rec, hipStream_t st);
 int sweep_variants();
 const char* sweep_variant_name(int v);
 }  // namespace tfim

@@ -41,6 +41,7 @@ SYMBOLS = [
     "tfim_last_error_detail", "tfim_set_variant", "tfim_set_timing", "tfim_get_timing",
     "tfim_measure_range", "tfim_set_measure_mode", "tfim_set_batch",
     "tfim_triples_workspace", "tfim_measure_triples", "tfim_xi3", "tfim_binder",
+    "tfim_measure_time",
 ]
 TFIM_MEASURE_REUSE_LAYOUT = 1
 
@@ -123,6 +124,7 @@ def lib():
             "tfim_measure_triples": [P, U32, U32, U32, U32, P, SZ, P, SZ],
             "tfim_xi3": [P, U32, U32, U32, U32, P],
             "tfim_binder": [P, U32, U32, U32, U32, P],
+            "tfim_measure_time": [P, U32, U32, U32, U32, P, SZ, P, SZ],
             "tfim_strerror": [ctypes.c_int32],
             "tfim_last_error_detail": [],
         }
@@ -204,6 +206,7 @@ class Plan:
         self.sizes = {n: getattr(sz, n) for n, _ in tfim_sizes._fields_}
         self.arena = None
         self._tws = None
+        self._tcws = None
         self.stream = None
         if bind:
             self.bind(device=device, stream=stream)
@@ -225,6 +228,7 @@ class Plan:
             self._h = None
         self.arena = None
         self._tws = None
+        self._tcws = None
 
     def __del__(self):
         try:
@@ -393,6 +397,28 @@ class Plan:
         _check(lib().tfim_measure_triples(self._h, shape, cfg0, ncfg, flags,
                                           ctypes.c_void_p(ws.data_ptr()), ws.numel(), _ptr(out),
                                           out.nbytes), "tfim_measure_triples")
+        return out
+
+    def measure_time(self, shape: int, cfg0: int, ncfg: int, flags: int = 0, copy: bool = True):
+        """Two-time records [ncfg][2][Ltau] (c and q2 summed over replicas) of
+        configurations cfg = i*S + s; the device workspace is a torch tensor
+        kept on the plan and grown on demand.  copy=False only enqueues."""
+        import torch
+        L, Lt, W, R, nk = self._dims(shape)
+        need = max(ncfg * 2 * Lt * 8, 256)
+        if getattr(self, "_tcws", None) is None or self._tcws.numel() < need:
+            self._tcws = None
+            self._tcws = torch.empty(need, dtype=torch.uint8, device=self.arena.device)
+        ws = self._tcws
+        if not copy:
+            _check(lib().tfim_measure_time(self._h, shape, cfg0, ncfg, flags,
+                                           ctypes.c_void_p(ws.data_ptr()), ws.numel(), None, 0),
+                   "tfim_measure_time")
+            return None
+        out = np.zeros((ncfg, 2, Lt), dtype=np.int64)
+        _check(lib().tfim_measure_time(self._h, shape, cfg0, ncfg, flags,
+                                       ctypes.c_void_p(ws.data_ptr()), ws.numel(), _ptr(out),
+                                       out.nbytes), "tfim_measure_time")
         return out
 
     def set_measure_mode(self, mode: int):

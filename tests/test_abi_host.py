@@ -66,6 +66,18 @@ def test_arena_sizes_cover_state():
     assert p.sizes["total"] >= sum(v for k, v in p.sizes.items() if k != "total")
 
 
+@pytest.mark.parametrize("R", [1, 2, 3])
+def test_measurement_region_holds_the_bit_layouts(R):
+    """The bit-transposed layouts along tau and along xy are sized for every
+    replica count: the two-time records transpose one-replica shapes too."""
+    L, Lt, W, nk = 10, 136, 1, 2
+    p = _plan([Shape(L, Lt, W, R, ladder(0.2, 0.3, nk))])
+    nc, nx = (Lt + 63) // 64, (L * L + 63) // 64
+    layouts = nk * 64 * W * R * (nc * 64 * nx + nx * Lt) * 8
+    assert p.sizes["measure"] >= layouts
+    p.close()
+
+
 def test_unbound_plan_refuses_device_calls():
     p = _plan([Shape(8, 32, 1, 2, [0.2, 0.3])])
     with pytest.raises(tfim.TfimError) as e:

@@ -13,9 +13,10 @@
 // {0,1} int8 operands (v_mfma_i32_32x32x32_i8) unpacked from the bit rows
 // along xy, as in the replica overlap.  One workgroup takes one
 // configuration at a time and walks the upper triangle of 64 x 64 tiles of
-// every replica's H; each element adds sum_r H^r and sum_r (H^r)^2 to LDS
-// buckets of its diagonal d (and of -d for the mirror element off the
-// diagonal tiles), which are stored once per configuration.
+// every replica's H; each element with t1 <= t2 adds sum_r H^r and
+// sum_r (H^r)^2 to LDS buckets U of its diagonal d = t2 - t1, and since H is
+// symmetric the record is c[d] = U[d] + U[Ltau - d] (c[0] = U[0]), stored
+// once per configuration.
 #include <algorithm>
 
 #include "tfim_internal.h"
@@ -143,22 +144,23 @@ __global__ void __launch_bounds__(256) k_timecorr_mfma(ShapeDev sh, int cfg0, in
                     hs += h;
                     h2 += h * h;
                 }
-                int d = tau2 - tau;
-                if (d < 0) d += Lt;
+                // upper triangle only (tau <= tau2): the mirror element lands on
+                // Ltau - d, added when the record is stored
+                if (tau2 < tau) continue;
+                const int d = tau2 - tau;
                 atomicAdd(&Cb[d], (unsigned long long)(long long)hs);
                 atomicAdd(&Cb[Lt + d], (unsigned long long)h2);
-                if (!diag) {  // the mirror element (tau2, tau)
-                    const int dm = Lt - d;  // d > 0 here
-                    atomicAdd(&Cb[dm], (unsigned long long)(long long)hs);
-                    atomicAdd(&Cb[Lt + dm], (unsigned long long)h2);
-                }
             }
         }
         __syncthreads();
+        // c[d] = U[d] + U[Ltau - d] for d > 0, c[0] = U[0] (likewise q2)
         for (int e = tid; e < 2 * Lt; e += 256) {
-            rec[(size_t)cl * 2 * Lt + e] = (int64_t)Cb[e];
-            Cb[e] = 0;
+            const int h = e / Lt, d = e % Lt;
+            const unsigned long long u = Cb[e] + (d ? Cb[h * Lt + Lt - d] : 0ull);
+            rec[(size_t)cl * 2 * Lt + e] = (int64_t)u;
         }
+        __syncthreads();
+        for (int e = tid; e < 2 * Lt; e += 256) Cb[e] = 0;
         __syncthreads();
     }
 }

@@ -202,6 +202,52 @@ def triples_leg(plan, sh, torch, args):
     }
 
 
+def timecorr_leg(plan, sh, torch, args):
+    """Two-time records of every configuration (the time Gram of each replica,
+    summed along its periodic diagonals), in chunks; C(tau) and Q2(tau) means
+    over samples at three k-indices."""
+    from paper_2310_07486_amd import tfim
+    ncfg = len(sh.k) * sh.n_samples
+    L2, Lt, R = sh.L * sh.L, sh.Ltau, sh.n_replicas
+    ntt = (Lt + 63) // 64
+    alg = Lt * (Lt + 1) * L2 * R                                   # symmetric H, mul + add
+    exe = (ntt * (ntt + 1) // 2) * 2 * 64 * 64 * 64 * ((L2 + 63) // 64) * R
+    chunk = min(args.triples_chunk, ncfg)
+    stream = torch.cuda.current_stream()
+    plan.measure_time(0, 0, chunk, copy=False)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for c0 in range(0, ncfg, chunk):
+        plan.measure_time(0, c0, min(chunk, ncfg - c0), flags=tfim.TFIM_MEASURE_REUSE_LAYOUT,
+                          copy=False)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    tops_alg = alg * ncfg / (ms * 1e-3) / 1e12
+    tops_exe = exe * ncfg / (ms * 1e-3) / 1e12
+    log("bench: two-time: %d configurations in chunks of %d: %.1f ms, %.1f TOP/s algorithmic, "
+        "%.1f TOP/s int8 executed" % (ncfg, chunk, ms, tops_alg, tops_exe))
+    taus = [t for t in (1, 4, 16, 64, 256, 1024) if t < Lt]
+    curves = {}
+    S = sh.n_samples
+    for i in sorted({0, len(sh.k) // 2, len(sh.k) - 1}):
+        rec = plan.measure_time(0, i * S, S, flags=tfim.TFIM_MEASURE_REUSE_LAYOUT)  # [S][2][Lt]
+        c = rec[:, 0].mean(axis=0) / (R * L2 * Lt)
+        q2 = rec[:, 1].mean(axis=0) / (R * L2 * L2 * Lt)
+        curves[str(i)] = {"k": sh.k[i], "C": [round(float(c[t]), 6) for t in taus],
+                          "Q2": [round(float(q2[t]), 6) for t in taus]}
+    plan._tcws = None
+    return {
+        "configurations": ncfg, "chunk": chunk, "ms": round(ms, 3),
+        "algorithmic_ops_per_configuration": alg, "int8_ops_per_configuration": exe,
+        "algorithmic_tops": round(tops_alg, 2), "int8_executed_tops": round(tops_exe, 2),
+        "frac_of_int8_peak": round(tops_exe / 5000.0, 4),
+        "tau": taus, "by_k_index": curves,
+    }
+
+
 def batched_leg(torch, args):
     """Five uneven sizes (L, Ltau) = (8,256) .. (24,2048), 512 samples each:
     the per-shape schedule (five sweep launches per sweep, one per size)
@@ -272,6 +318,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-measure", action="store_true")
     ap.add_argument("--no-triples", action="store_true")
+    ap.add_argument("--no-timecorr", action="store_true")
     ap.add_argument("--triples-chunk", type=int, default=4096)
     ap.add_argument("--unbatched-cfgs", type=int, default=64)
     ap.add_argument("--plain-cfgs", type=int, default=1)
@@ -378,6 +425,8 @@ def main():
         result["measure"] = measure_leg(plan, sh, torch, args)
     if not args.no_triples:
         result["xi3"] = triples_leg(plan, sh, torch, args)
+    if not args.no_timecorr:
+        result["two_time"] = timecorr_leg(plan, sh, torch, args)
     plan.close()
     del plan
     torch.cuda.empty_cache()

@@ -1,8 +1,10 @@
 """Physics check of the whole sampler on the GPU: the second-moment
-correlation length over the lattice size, xi^(2)/L (Methods, "One-time
-observables"), of the two smallest sizes of Table I (L = 8 and 12,
+correlation lengths over the lattice size, xi^(2)/L and xi^(3)/L (Methods,
+"One-time observables"), of the two smallest sizes of Table I (L = 8 and 12,
 Ltau = 512, k uniformly spaced over [0.265, 0.305]) must cross inside that
-k range, close to the critical coupling the paper locates near 0.29.
+k range, close to the critical coupling the paper locates near 0.29 (its
+xi^(3) crossing for this pair of sizes is near 0.291).  The Binder ratio
+must start near its Gaussian value 3 and the two sizes' curves cross once.
 
 Statistical, with a deliberately loose window: 512 disorder samples, 4
 replicas, tempering every sweep, 5*10^4 equilibration sweeps and 100
@@ -19,31 +21,64 @@ from paper_2310_07486_amd.workloads import Shape, ladder
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
 
-def _xi_over_L(L, nk, seed, n_eq=50000, n_meas=100, gap=200):
+def _run(L, nk, seed, n_eq=50000, n_meas=100, gap=200):
+    """xi^(2)/L, xi^(3)/L and the Binder ratio per k of one size."""
     sh = Shape(L, 512, 8, 4, ladder(0.265, 0.305, nk), pt_every=1)
     plan = tfim.Plan([sh], seed)
     plan.init()
     for _ in range(n_eq // 10000):
         plan.sweep(10000)
+    S = sh.n_samples
     A = np.zeros((nk, L), dtype=np.int64)
-    for _ in range(n_meas):
+    T = np.zeros((nk, n_meas, 2 * L), dtype=np.int64)  # per measurement: samples and triples summed
+    P = []
+    for m in range(n_meas):
         plan.sweep(gap)
-        A += plan.measure(0, tfim.TFIM_MEASURE_BUCKETS)[:, 0]
+        rec = plan.measure(0, tfim.TFIM_MEASURE_RECORDS)  # [k][s][pair][2L+3]
+        A += rec[:, :, :, :L].sum(axis=(1, 2))
+        P.append(rec[:, :, :, 2 * L + 1:].sum(axis=1))    # sum Q^2, sum Q^4 per k and pair
+        tr = plan.measure_triples(0, 0, nk * S, flags=tfim.TFIM_MEASURE_REUSE_LAYOUT)
+        T[:, m] = tr.reshape(nk, S, -1, 2 * L).sum(axis=(1, 2))
     plan.close()
-    return np.asarray(sh.k), tfim.tfim_xi2(np.ascontiguousarray(A), L) / L
+    q = np.stack(P, axis=1)  # [k][meas][pair][2]
+    pr = np.zeros((nk, q.shape[1] * q.shape[2], 2 * L + 3), dtype=np.int64)
+    pr[..., 2 * L + 1:] = q.reshape(nk, -1, 2)
+    # the Binder ratio of the means over samples: n_per_k counts every record
+    B = tfim.tfim_binder(pr, L, sh.Ltau) * S
+    k = np.asarray(sh.k)
+    return k, tfim.tfim_xi2(np.ascontiguousarray(A), L) / L, tfim.tfim_xi3(T, L, 2) / L, B
+
+
+def _crossings(c8, c12, lo, hi):
+    kk = np.linspace(lo, hi, 401)
+    d = np.interp(kk, *c12) - np.interp(kk, *c8)
+    return d, [float(kk[i]) for i in range(len(kk) - 1) if d[i] * d[i + 1] <= 0]
 
 
 def test_xi_over_L_crossing_of_the_two_smallest_sizes():
-    curves = {}
+    runs = {}
     for L, nk in ((8, 16), (12, 24)):
         print(f"physics: L={L} Ltau=512 512 samples, equilibrating", flush=True)
         sys.stdout.flush()
-        curves[L] = _xi_over_L(L, nk, 4200 + L)
-    for L, (k, x) in curves.items():
-        assert np.all(np.isfinite(x)) and np.all(np.diff(x) > 0), f"xi/L of L={L} not increasing in k"
-    kk = np.linspace(0.265, 0.305, 401)
-    d = np.interp(kk, *curves[12]) - np.interp(kk, *curves[8])
+        runs[L] = _run(L, nk, 4200 + L)
+    for L, (k, x2, x3, B) in runs.items():
+        print(f"physics: L={L} xi2/L {np.round(x2, 4).tolist()}", flush=True)
+        print(f"physics: L={L} xi3/L {np.round(x3, 4).tolist()}", flush=True)
+        print(f"physics: L={L} Binder {np.round(B, 4).tolist()}", flush=True)
+        assert np.all(np.isfinite(x2)) and np.all(np.diff(x2) > 0), f"xi/L of L={L} not increasing in k"
+        assert np.all(np.isfinite(x3)) and np.all(np.isfinite(B))
+    d, cross = _crossings((runs[8][0], runs[8][1]), (runs[12][0], runs[12][1]), 0.265, 0.305)
+    print(f"physics: xi2/L crossing at k = {cross}", flush=True)
+    d3, cross3 = _crossings((runs[8][0], runs[8][2]), (runs[12][0], runs[12][2]), 0.265, 0.305)
+    print(f"physics: xi3/L crossing at k = {cross3}", flush=True)
     assert d[0] < 0 < d[-1], "the larger lattice must start below and end above"
-    cross = [float(kk[i]) for i in range(len(kk) - 1) if d[i] * d[i + 1] <= 0]
-    print(f"physics: crossing at k = {cross}", flush=True)
     assert len(cross) == 1 and 0.28 <= cross[0] <= 0.30
+    # xi^(3)/L, the paper's headline length (Fig. 1b): the same crossing
+    for L, (k, x2, x3, B) in runs.items():
+        assert np.all(np.diff(x3) > 0), f"xi3/L of L={L} not increasing in k"
+        assert np.all((B > 1.0) & (B < 3.05)), f"Binder ratio of L={L} outside (1, 3]"
+    assert d3[0] < 0 < d3[-1] and len(cross3) == 1 and 0.28 <= cross3[0] <= 0.30
+    # the Binder ratio: near 3 (Gaussian) at small k, the larger lattice falls faster
+    db, crossb = _crossings((runs[8][0], runs[8][3]), (runs[12][0], runs[12][3]), 0.265, 0.305)
+    print(f"physics: Binder crossing at k = {crossb}", flush=True)
+    assert db[0] > 0 > db[-1] and len(crossb) == 1 and 0.28 <= crossb[0] <= 0.305

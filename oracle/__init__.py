@@ -43,7 +43,7 @@ class _Shape(ctypes.Structure):
         ("L", ctypes.c_int32), ("Ltau", ctypes.c_int32),
         ("n_replicas", ctypes.c_int32), ("n_k", ctypes.c_int32),
         ("word_offset", ctypes.c_uint32), ("stream_id", ctypes.c_uint32),
-        ("pt_every", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("pt_every", ctypes.c_int32), ("bc_tau", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
         ("k", ctypes.POINTER(ctypes.c_double)),
     ]
@@ -58,7 +58,7 @@ def lib():
         _lib.oracle_philox.argtypes = [P, ctypes.c_uint64, P]
         _lib.oracle_init_couplings.argtypes = [P, P, ctypes.c_int32, P, P]
         _lib.oracle_init_spins.argtypes = [P, P, ctypes.c_int32, P]
-        _lib.oracle_action.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P]
+        _lib.oracle_action.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P]
         _lib.oracle_action.restype = ctypes.c_int64
         _lib.oracle_metro_thresholds.argtypes = [P, ctypes.c_int, P]
         _lib.oracle_pt_threshold.argtypes = [ctypes.c_double, ctypes.c_int64]
@@ -68,7 +68,7 @@ def lib():
         _lib.oracle_run.argtypes = [P, ctypes.c_int32, P, ctypes.c_int64,
                                     P, P, P, P, P, P, P]
         _lib.oracle_reset_kidx.argtypes = [P, ctypes.c_int32, P]
-        _lib.oracle_local_dE.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P,
+        _lib.oracle_local_dE.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P,
                                          ctypes.c_int, ctypes.c_int]
     return _lib
 
@@ -99,12 +99,14 @@ def pt_threshold(dk: float, dE: int) -> int:
     return int(lib().oracle_pt_threshold(float(dk), int(dE)))
 
 
-def action(S_cfg: np.ndarray, Jx: np.ndarray, Jy: np.ndarray, L: int, Ltau: int) -> int:
-    """The Trotter action E(S) of one configuration (each bond once)."""
+def action(S_cfg: np.ndarray, Jx: np.ndarray, Jy: np.ndarray, L: int, Ltau: int,
+           bc_tau: int = 0) -> int:
+    """The Trotter action E(S) of one configuration (each bond once);
+    bc_tau = 1: antiperiodic along tau."""
     S_cfg = np.ascontiguousarray(S_cfg, dtype=np.int8)
     Jx = np.ascontiguousarray(Jx, dtype=np.int8)
     Jy = np.ascontiguousarray(Jy, dtype=np.int8)
-    return int(lib().oracle_action(L, Ltau, _ptr(S_cfg), _ptr(Jx), _ptr(Jy)))
+    return int(lib().oracle_action(L, Ltau, int(bc_tau), _ptr(S_cfg), _ptr(Jx), _ptr(Jy)))
 
 
 class Chain:
@@ -120,7 +122,7 @@ class Chain:
     """
 
     def __init__(self, L, Ltau, k, n_replicas, seed, samples, *, word_offset=0,
-                 stream_id=0, pt_every=1, init=True):
+                 stream_id=0, pt_every=1, init=True, bc_tau=0):
         self.L, self.Ltau = int(L), int(Ltau)
         self.k = np.ascontiguousarray(np.asarray(k, dtype=np.float64))
         self.n_k = len(self.k)
@@ -129,6 +131,7 @@ class Chain:
         self.samples = np.ascontiguousarray(np.asarray(samples, dtype=np.int32))
         self.ns = len(self.samples)
         self.word_offset, self.stream_id, self.pt_every = word_offset, stream_id, pt_every
+        self.bc_tau = int(bc_tau)
         L2 = self.L * self.L
         self.N = L2 * self.Ltau
         self.S = np.zeros((self.R, self.n_k, self.ns, self.Ltau, L2), dtype=np.int8)
@@ -139,7 +142,7 @@ class Chain:
         self.t = ctypes.c_uint32(0)
         self.m = ctypes.c_uint32(0)
         self._sh = _Shape(self.L, self.Ltau, self.R, self.n_k, word_offset, stream_id,
-                          pt_every, 0, ctypes.c_uint64(self.seed),
+                          pt_every, self.bc_tau, ctypes.c_uint64(self.seed),
                           self.k.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
         if init:
             self.init_couplings()

@@ -20,15 +20,21 @@ def all_states(n_spins: int) -> np.ndarray:
     return (1 - 2 * bits).astype(np.int8)
 
 
-def action_all(L: int, Ltau: int, Jx: np.ndarray, Jy: np.ndarray, states: np.ndarray) -> np.ndarray:
-    """E(S) for every state; site index lin = xy + L^2 tau, xy = x + L y."""
+def action_all(L: int, Ltau: int, Jx: np.ndarray, Jy: np.ndarray, states: np.ndarray,
+               bc_tau: int = 0) -> np.ndarray:
+    """E(S) for every state; site index lin = xy + L^2 tau, xy = x + L y.
+    bc_tau = 1: the temporal bonds between tau = Ltau-1 and 0 carry the sign
+    -1 (antiperiodic along tau, Methods, "The Trotter-Suzuki formula")."""
     L2 = L * L
     S = states.reshape(-1, Ltau, L, L).astype(np.int64)  # [state][tau][y][x]
     jx = Jx.reshape(L, L).astype(np.int64)               # [y][x]: (x,y)-(x+1,y)
     jy = Jy.reshape(L, L).astype(np.int64)               # [y][x]: (x,y)-(x,y+1)
     E = -(jx[None, None] * S * np.roll(S, -1, axis=3)).sum(axis=(1, 2, 3))
     E -= (jy[None, None] * S * np.roll(S, -1, axis=2)).sum(axis=(1, 2, 3))
-    E -= (S * np.roll(S, -1, axis=1)).sum(axis=(1, 2, 3))
+    T = S * np.roll(S, -1, axis=1)  # [state][tau]: bond (tau, tau+1)
+    if bc_tau:
+        T[:, Ltau - 1] *= -1
+    E -= T.sum(axis=(1, 2, 3))
     assert L2 * Ltau == states.shape[1]
     return E
 

@@ -15,7 +15,9 @@
  *     on an L x L x Ltau lattice, p(S) = exp(-k E(S)) / Z with the action
  *     E(S) = -sum_tau [ 1/2 sum_{x,y} J_xy S_x,tau S_y,tau
  *                       + sum_x S_x,tau S_x,tau+1 ],
- *     periodic along tau.  Each bond is counted once.
+ *     periodic along tau.  Each bond is counted once.  The same passage
+ *     also uses antiperiodic conditions along tau only: the temporal bond
+ *     between tau = Ltau-1 and tau = 0 then enters with the sign -1.
  *   - Methods, "Simulation details" and Table I: Metropolis full-lattice
  *     sweeps, parallel tempering (Hukushima-Nemoto) over k, independent
  *     real replicas.
@@ -92,7 +94,7 @@ typedef struct {
     int32_t n_replicas, n_k;
     uint32_t word_offset, stream_id;
     int32_t pt_every;
-    int32_t pad;
+    int32_t bc_tau; /* 0: periodic along tau, 1: antiperiodic */
     uint64_t seed;
     const double *k; /* n_k couplings, strictly increasing */
 } oracle_shape;
@@ -143,9 +145,10 @@ void oracle_init_spins(const oracle_shape *sh, const int32_t *samples,
 }
 
 /* ------------------------------------------------------------------ */
-/* The action E(S), each bond once, tau periodic.                      */
+/* The action E(S), each bond once; bc = 1 puts the sign -1 on the      */
+/* temporal bonds between tau = Ltau-1 and tau = 0 (antiperiodic).      */
 /* ------------------------------------------------------------------ */
-int64_t oracle_action(int L, int Ltau, const int8_t *S, const int8_t *Jx,
+int64_t oracle_action(int L, int Ltau, int bc, const int8_t *S, const int8_t *Jx,
                       const int8_t *Jy)
 {
     const int L2 = L * L;
@@ -153,6 +156,7 @@ int64_t oracle_action(int L, int Ltau, const int8_t *S, const int8_t *Jx,
     for (int tau = 0; tau < Ltau; ++tau) {
         const int8_t *P = S + (size_t)tau * L2;
         const int8_t *Pn = S + (size_t)((tau + 1) % Ltau) * L2;
+        const int64_t ct = (bc && tau == Ltau - 1) ? -1 : 1;
         for (int y = 0; y < L; ++y)
             for (int x = 0; x < L; ++x) {
                 int xy = x + L * y;
@@ -160,7 +164,7 @@ int64_t oracle_action(int L, int Ltau, const int8_t *S, const int8_t *Jx,
                 int yp = x + L * ((y + 1) % L);
                 E -= (int64_t)Jx[xy] * P[xy] * P[xp];
                 E -= (int64_t)Jy[xy] * P[xy] * P[yp];
-                E -= (int64_t)P[xy] * Pn[xy];
+                E -= ct * P[xy] * Pn[xy];
             }
     }
     return E;
@@ -235,15 +239,16 @@ void oracle_energy(const oracle_shape *sh, int32_t n_samples, const int8_t *S,
         for (int w = 0; w < nk; ++w)
             for (int si = 0; si < n_samples; ++si) {
                 const int8_t *cfg = S + ((size_t)(r * nk + w) * n_samples + si) * N;
-                int64_t E = oracle_action(sh->L, sh->Ltau, cfg, Jx + (size_t)si * L2,
+                int64_t E = oracle_action(sh->L, sh->Ltau, sh->bc_tau, cfg, Jx + (size_t)si * L2,
                                           Jy + (size_t)si * L2);
                 U[((size_t)r * n_samples + si) * nk + w] = unsat_from_action(E, N);
             }
 }
 
 /* Energy change of flipping site (xy, tau): dE = 2 S h, with h the local
- * field of the four spatial and two temporal neighbours. */
-int oracle_local_dE(int L, int Ltau, const int8_t *cfg, const int8_t *jx,
+ * field of the four spatial and two temporal neighbours (the neighbour
+ * across the tau wrap with the sign -1 when bc = 1). */
+int oracle_local_dE(int L, int Ltau, int bc, const int8_t *cfg, const int8_t *jx,
                     const int8_t *jy, int xy, int tau)
 {
     const int L2 = L * L;
@@ -252,8 +257,9 @@ int oracle_local_dE(int L, int Ltau, const int8_t *cfg, const int8_t *jx,
     int ym = x + L * ((y + L - 1) % L), yp = x + L * ((y + 1) % L);
     int tm = (tau + Ltau - 1) % Ltau, tp = (tau + 1) % Ltau;
     const int8_t *P = cfg + (size_t)tau * L2;
+    const int cm = (bc && tau == 0) ? -1 : 1, cp = (bc && tau == Ltau - 1) ? -1 : 1;
     int h = jx[xy] * P[xp] + jx[xm] * P[xm] + jy[xy] * P[yp] + jy[ym] * P[ym] +
-            cfg[(size_t)tm * L2 + xy] + cfg[(size_t)tp * L2 + xy];
+            cm * cfg[(size_t)tm * L2 + xy] + cp * cfg[(size_t)tp * L2 + xy];
     return 2 * P[xy] * h;
 }
 
@@ -282,7 +288,7 @@ static void half_sweep(const oracle_shape *sh, int32_t n_samples,
                             jR = j;
                         }
                         int8_t *cfg = S + ((size_t)(r * nk + w) * n_samples + si) * N;
-                        int dE = oracle_local_dE(L, Lt, cfg, Jx + (size_t)si * L2,
+                        int dE = oracle_local_dE(L, Lt, sh->bc_tau, cfg, Jx + (size_t)si * L2,
                                                  Jy + (size_t)si * L2, xy, tau);
                         int accept;
                         if (dE <= 0) {

@@ -1,7 +1,8 @@
 """Statistical pin of the oracle chain against exact enumeration.
 
 On the 2x2x4 Trotter lattice (16 spins, 65536 states) the Boltzmann weight
-exp(-k E(S))/Z of Methods, "The Trotter-Suzuki formula", is summed exactly.
+exp(-k E(S))/Z of Methods, "The Trotter-Suzuki formula", is summed exactly,
+with periodic and with antiperiodic conditions along tau.
 
 The pin is stationarity: configurations drawn exactly from exp(-k_i E)/Z at
 every k-index are given one oracle sweep (colour 0, colour 1, energy, then a
@@ -40,8 +41,9 @@ def _instances(rng):
              rng.choice(np.array([-1, 1], dtype=np.int8), size=L * L)) for _ in range(N_INST)]
 
 
-@pytest.fixture(scope="module")
-def stationarity():
+@pytest.fixture(scope="module", params=[0, 1], ids=["periodic", "antiperiodic"])
+def stationarity(request):
+    bc = request.param
     rng = np.random.default_rng(17)
     inst = _instances(rng)
     states = en.all_states(N)  # [state][lin]
@@ -53,7 +55,7 @@ def stationarity():
     exGG = np.zeros((N_INST, len(KS)))
     exAcc = np.zeros((N_INST, len(KS) - 1))
     for q, (jx, jy) in enumerate(inst):
-        E = en.action_all(L, LTAU, jx, jy, states)
+        E = en.action_all(L, LTAU, jx, jy, states, bc)
         for i, k in enumerate(KS):
             p = en.boltzmann(E, k)
             cdf[q, i] = np.cumsum(p)
@@ -63,7 +65,7 @@ def stationarity():
         for i in range(len(KS) - 1):
             exAcc[q, i] = en.exact_swap_acceptance(E, KS[i], KS[i + 1])
 
-    ch = Chain(L, LTAU, KS, 2, SEED, np.arange(ns), pt_every=1)
+    ch = Chain(L, LTAU, KS, 2, SEED, np.arange(ns), pt_every=1, bc_tau=bc)
     for si in range(ns):
         ch.Jx[si], ch.Jy[si] = inst[lane_inst[si]]
     devE = np.zeros((REPS, 2, N_WORDS, len(KS)))
@@ -159,3 +161,16 @@ def test_checkerboard_ring_has_extra_stationary_states():
     pb = np.exp(-k * E)
     pb /= pb.sum()
     assert np.allclose(pb @ T, pb)
+
+
+def test_antiperiodic_ground_states():
+    """All couplings +1 on 2x2x4: periodic along tau the two uniform states
+    reach E = -3N; antiperiodic, every tau ring keeps one unsatisfied bond, so
+    the minimum is -3N + 2 L^2, reached by the 2 Ltau states with uniform
+    planes and one domain wall along tau."""
+    states = en.all_states(N)
+    J = np.ones(L * L, dtype=np.int8)
+    Ep = en.action_all(L, LTAU, J, J, states, 0)
+    Ea = en.action_all(L, LTAU, J, J, states, 1)
+    assert Ep.min() == -3 * N and np.count_nonzero(Ep == Ep.min()) == 2
+    assert Ea.min() == -3 * N + 2 * L * L and np.count_nonzero(Ea == Ea.min()) == 2 * LTAU

@@ -91,7 +91,7 @@ def test_local_energy_change_matches_action_exhaustively(oracle_lib):
             S1 = S.copy()
             S1[tau, xy] = -S1[tau, xy]
             E1 = oracle_lib.action(S1, Jx, Jy, L, Ltau)
-            dE = lib.oracle_local_dE(L, Ltau, ctypes.c_void_p(S.ctypes.data),
+            dE = lib.oracle_local_dE(L, Ltau, 0, ctypes.c_void_p(S.ctypes.data),
                                      ctypes.c_void_p(Jx.ctypes.data),
                                      ctypes.c_void_p(Jy.ctypes.data), xy, tau)
             assert dE == E1 - E0
@@ -152,3 +152,28 @@ def test_tempering_threshold_is_exchange_ratio(oracle_lib):
             assert abs(T - ratio * 2**32) <= 1 + 1e-9 * ratio * 2**32
         # beyond the 32-bit resolution the threshold is zero
         assert oracle_lib.pt_threshold(dk, int(40 / dk)) == 0
+
+
+def test_antiperiodic_action_and_local_dE(oracle_lib):
+    """Antiperiodic along tau: E_APBC(S) = E_PBC(S) + 2 sum_x S_x,Ltau-1 S_x,0
+    (the wrap bond changes sign), and the local dE of every site, the two
+    planes next to the wrap included, equals the action difference."""
+    import ctypes
+    rng = np.random.default_rng(23)
+    L, Ltau = 4, 6
+    lib = oracle_lib.lib()
+    for _ in range(4):
+        S = rng.choice(np.array([-1, 1], dtype=np.int8), size=(Ltau, L * L))
+        Jx = rng.choice(np.array([-1, 1], dtype=np.int8), size=L * L)
+        Jy = rng.choice(np.array([-1, 1], dtype=np.int8), size=L * L)
+        Ep = oracle_lib.action(S, Jx, Jy, L, Ltau, 0)
+        Ea = oracle_lib.action(S, Jx, Jy, L, Ltau, 1)
+        assert Ea - Ep == 2 * int((S[Ltau - 1].astype(int) * S[0]).sum())
+        for tau in range(Ltau):
+            for xy in range(L * L):
+                S1 = S.copy()
+                S1[tau, xy] = -S1[tau, xy]
+                dE = lib.oracle_local_dE(L, Ltau, 1, ctypes.c_void_p(S.ctypes.data),
+                                         ctypes.c_void_p(Jx.ctypes.data),
+                                         ctypes.c_void_p(Jy.ctypes.data), xy, tau)
+                assert dE == oracle_lib.action(S1, Jx, Jy, L, Ltau, 1) - Ea

@@ -250,26 +250,29 @@ def time_gram(S: np.ndarray) -> np.ndarray:
     return (S.T @ S).astype(np.int64)
 
 
-def time_bands(H: np.ndarray):
+def time_bands(H: np.ndarray, bc_tau: int = 0):
     """c[d] and q2[d] for d = 0..Ltau-1: sums of H and H^2 along the periodic
-    diagonal t2 - t1 = d (mod Ltau)."""
+    diagonal t2 - t1 = d (mod Ltau).  With an antiperiodic boundary the
+    configuration continues past Ltau with the opposite sign, so the terms of
+    c with t1 + d >= Ltau (across the wrap) enter with the sign -1."""
     Lt = H.shape[0]
     c = np.zeros(Lt, dtype=np.int64)
     q2 = np.zeros(Lt, dtype=np.int64)
     t1 = np.arange(Lt)
     for d in range(Lt):
         band = H[t1, (t1 + d) % Lt]
-        c[d] = band.sum()
+        sign = np.where((t1 + d >= Lt) & (bc_tau == 1), -1, 1)
+        c[d] = (sign * band).sum()
         q2[d] = (band * band).sum()
     return c, q2
 
 
-def time_record(Ss) -> np.ndarray:
+def time_record(Ss, bc_tau: int = 0) -> np.ndarray:
     """[c[0..Ltau-1], q2[0..Ltau-1]] (int64) summed over the replicas' S."""
     Lt = Ss[0].shape[1]
     out = np.zeros(2 * Lt, dtype=np.int64)
     for S in Ss:
-        c, q2 = time_bands(time_gram(S))
+        c, q2 = time_bands(time_gram(S), bc_tau)
         out[:Lt] += c
         out[Lt:] += q2
     return out
@@ -285,5 +288,6 @@ def measure_time_chain(chain, k_indices=None, sample_indices=None) -> np.ndarray
     out = np.zeros((len(ks), len(ss), 2 * Lt), dtype=np.int64)
     for ii, i in enumerate(ks):
         for jj, si in enumerate(ss):
-            out[ii, jj] = time_record([spin_matrix(chain.S[r, winv[r, si, i], si]) for r in range(R)])
+            out[ii, jj] = time_record([spin_matrix(chain.S[r, winv[r, si, i], si]) for r in range(R)],
+                                      getattr(chain, "bc_tau", 0))
     return out

@@ -69,6 +69,7 @@ struct tfim_plan {
     std::vector<uint64_t> items;
     int max_nk = 0, n_cu = 0;
     bool any_pt = false;
+    bool batch_anti = false;  // some shape is antiperiodic: the batched kernel checks the tau mask
     hipStream_t cap_stream = nullptr;
     std::vector<hipStream_t> side;                // concurrent schedule: one branch per shape
     hipEvent_t ev_fork = nullptr;
@@ -96,6 +97,7 @@ tfim::ShapeDev dev_of(const tfim_plan* pl, int i) {
     d.sid = h.s.stream_id;
     d.word_offset = h.s.word_offset;
     d.pt_every = h.s.pt_every;
+    d.apm = h.s.bc_tau == TFIM_BC_ANTIPERIODIC ? ~0ull : 0ull;
     char* a = pl->arena;
     d.S = (uint64_t*)(a + h.oS);
     d.J = (uint64_t*)(a + h.oJ);
@@ -253,9 +255,8 @@ tfim_status validate(const tfim_shape* s, uint32_t n) {
         if (a.stream_id > 255) return fail(TFIM_EINVAL, "stream_id must be < 256");
         for (uint32_t q = 0; q < i; ++q)
             if (s[q].stream_id == a.stream_id) return fail(TFIM_EINVAL, "stream_id repeated in plan");
-        if (a.bc_tau == TFIM_BC_ANTIPERIODIC)
-            return fail(TFIM_EUNSUPPORTED, "antiperiodic tau boundary not provided");
-        if (a.bc_tau != TFIM_BC_PERIODIC) return fail(TFIM_EINVAL, "unknown bc_tau");
+        if (a.bc_tau != TFIM_BC_PERIODIC && a.bc_tau != TFIM_BC_ANTIPERIODIC)
+            return fail(TFIM_EINVAL, "unknown bc_tau");
         if (a.Ltau % 8 != 0)
             return fail(TFIM_EUNSUPPORTED, "the GPU sweep walks tau in chunks of 8: Ltau % 8 must be 0");
         // L^2 <= 1024 threads per workgroup
@@ -660,7 +661,7 @@ static tfim_status batch_setup(tfim_plan* pl, uint32_t threads, uint32_t bpc) {
     std::vector<tfim::ShapeDev> devs(ns);
     std::vector<uint32_t> first(ns + 1, 0);
     int max_nk = 0;
-    bool any_pt = false;
+    bool any_pt = false, any_anti = false;
     for (int i = 0; i < ns; ++i) {
         const tfim::ShapeDev d = dev_of(pl, i);
         devs[i] = d;
@@ -683,11 +684,12 @@ static tfim_status batch_setup(tfim_plan* pl, uint32_t threads, uint32_t bpc) {
         first[i + 1] = first[i] + (uint32_t)(d.R * d.W);
         max_nk = std::max(max_nk, d.nk);
         any_pt = any_pt || d.pt_every != 0;
+        any_anti = any_anti || d.apm != 0;
     }
     // longest items first (a sweep of a configuration takes time ~ Ltau)
     std::stable_sort(it.begin(), it.end(), [](const Item& a, const Item& b) { return a.Lt > b.Lt; });
     int per_cu = 0;
-    hipError_t e = tfim::sweep_batch_prepare(1, lds, (int)threads, &per_cu);
+    hipError_t e = tfim::sweep_batch_prepare(1, any_anti, lds, (int)threads, &per_cu);
     if (e != hipSuccess) return check_hip(pl, e, "batch prepare");
     if (per_cu <= 0) return fail(TFIM_EUNSUPPORTED, "batched workgroup cannot be resident");
     if (bpc) per_cu = std::min<int>(per_cu, (int)bpc);
@@ -706,6 +708,7 @@ static tfim_status batch_setup(tfim_plan* pl, uint32_t threads, uint32_t bpc) {
     pl->batch_bpc = bpc;
     pl->batch_blocks = (uint32_t)std::min<size_t>((size_t)pl->n_cu * per_cu, pl->items.size());
     pl->batch_lds = lds;
+    pl->batch_anti = any_anti;
     (void)first;
     (void)max_nk;
     (void)any_pt;
@@ -740,8 +743,8 @@ static hipError_t batch_graph(tfim_plan* pl, uint32_t g, hipGraphExec_t* out) {
                 if (le == hipSuccess) le = hipStreamWaitEvent(pl->cap_stream, pl->ev_join[i], 0);
             }
         } else {
-            le = tfim::launch_sweep_batch(a, 1, (int)pl->batch_blocks, (int)pl->batch_threads, pl->batch_lds,
-                                          pl->cap_stream);
+            le = tfim::launch_sweep_batch(a, 1, pl->batch_anti, (int)pl->batch_blocks, (int)pl->batch_threads,
+                                          pl->batch_lds, pl->cap_stream);
         }
         if (le == hipSuccess && pl->any_pt)
             le = tfim::launch_temper_batch(ta, (int)pl->temper_blocks, pl->max_nk, pl->cap_stream);

@@ -227,8 +227,11 @@ __global__ void __launch_bounds__(kMaxThreads) k_sweep_fused(ShapeDev sh, uint32
     const int nq = Lt / kChunk;
     Chunk cur, nxt, prv;
     // plane Ltau-1 (colour 1 when p = 0) before the sweep: the tau-wrap
-    // neighbour of the first colour-0 site of column parity 0
-    const uint64_t lastplane_old = active ? col[(size_t)(Lt - 1) * L2] : 0;
+    // neighbour of the first colour-0 site of column parity 0.  Words used
+    // across the tau wrap are complemented when the boundary is
+    // antiperiodic (apm = all ones): the wrap bond has the sign -1.
+    const uint64_t apm = sh.apm;
+    const uint64_t lastplane_old = active ? col[(size_t)(Lt - 1) * L2] ^ apm : 0;
     uint64_t A0_first_new = 0;   // chunk 0, A[0] after colour 0
     uint64_t B0_first_old = 0;   // chunk 0, B[0] before the sweep
     uint64_t App3 = 0;           // chunk q-2, A[3] (final)
@@ -260,7 +263,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_sweep_fused(ShapeDev sh, uint32
                 const uint64_t dn_p0 = m > 0 ? cur.B[m > 0 ? m - 1 : 0]
                                              : (q > 0 ? prv.B[3] : lastplane_old);
                 const uint64_t up_p1 = m < 3 ? cur.B[m < 3 ? m + 1 : 3]
-                                             : (q + 1 < nq ? nxt.B[0] : B0_first_old);
+                                             : (q + 1 < nq ? nxt.B[0] : B0_first_old ^ apm);
                 const uint64_t dn = p ? cur.B[m] : dn_p0;
                 const uint64_t up = p ? up_p1 : cur.B[m];
                 const uint64_t* P = c1_old + (planeA + 2 * m) * H;
@@ -317,7 +320,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_sweep_fused(ShapeDev sh, uint32
                 continue;
             }
             const uint64_t dn_p1 = m > 0 ? prv.A[m > 0 ? m - 1 : 0] : App3;
-            const uint64_t up_p0 = m < 3 ? prv.A[m < 3 ? m + 1 : 3] : A0_first_new;
+            const uint64_t up_p0 = m < 3 ? prv.A[m < 3 ? m + 1 : 3] : A0_first_new ^ apm;
             const uint64_t dn = p ? dn_p1 : prv.A[m];
             const uint64_t up = p ? prv.A[m] : up_p0;
             const uint64_t* P = c0_new + (planeB + 2 * m) * H;
@@ -338,9 +341,10 @@ __global__ void __launch_bounds__(kMaxThreads) k_sweep_fused(ShapeDev sh, uint32
         const uint64_t* P = c0_new;
 #pragma unroll
         for (int i = 0; i < kSmallBits; ++i) small[i] = 0;
-        // tau-1 = Ltau-1 is the last chunk's A[3]; tau+1 = 1 is chunk 0's A[0]
+        // tau-1 = Ltau-1 is the last chunk's A[3] (across the wrap); tau+1 = 1
+        // is chunk 0's A[0]
         const SiteOut o = metro(B0_first_old, P[g.hxp], P[g.hxm], P[g.hyp], P[g.hym], jxp, jxm,
-                                jyp, jym, A0_first_new, prv.A[3], Rdef, ml, Tu_lds, nk);
+                                jyp, jym, A0_first_new, prv.A[3] ^ apm, Rdef, ml, Tu_lds, nk);
         col[0] = o.s;
         add3(small, o.f0, o.f1, o.f2);
         add_small(vc, small);
@@ -385,7 +389,8 @@ __global__ void __launch_bounds__(kMaxThreads) k_energy(ShapeDev sh) {
                 const uint64_t s = P[xy];
                 const uint64_t bx = s ^ P[xp] ^ jx;
                 const uint64_t by = s ^ P[yp] ^ jy;
-                const uint64_t bt = s ^ base[(size_t)((tau + 1) % Lt) * L2 + xy];
+                const uint64_t bt = s ^ base[(size_t)((tau + 1) % Lt) * L2 + xy] ^
+                                    (tau == Lt - 1 ? sh.apm : 0ull);  // the wrap bond
                 add3(small, bx ^ by ^ bt, (bx & by) | (bt & (bx ^ by)), 0);
             }
         }

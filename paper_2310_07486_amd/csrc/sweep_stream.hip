@@ -284,7 +284,7 @@ __host__ __device__ inline int stream_cols(const ShapeDev& sh) { return ((sh.L2 
 // kPacked = false: one team filling the workgroup (g = nlive = 1,
 // cols = blockDim.x), so every wave is a live member.  kDeepLds: the energy
 // counters live in LDS rather than registers.
-template <bool kE, bool kPacked, bool kDeepLds>
+template <bool kE, bool kPacked, bool kDeepLds, bool kAnti>
 __device__ __forceinline__ void sweep_teams(const ShapeDev& sh, const int cfg0, const int g,
                                             const int nlive, const int cols, uint64_t* lds,
                                             const uint32_t key0, const uint32_t key1,
@@ -371,11 +371,20 @@ __device__ __forceinline__ void sweep_teams(const ShapeDev& sh, const int cfg0, 
     const int half = Lt >> 1;      // colour-0 steps
     const int nq = Lt >> 3;        // Philox groups per colour and column
     auto wrap = [Lt](int P) { return P >= Lt ? P - Lt : (P < 0 ? P + Lt : P); };
+    // a plane reached across the tau wrap (P < 0 or P >= Ltau) is read
+    // complemented and stored back complemented when the boundary is
+    // antiperiodic: the wrap bond then has the sign -1 (apm = all ones).
+    // kAnti = false compiles the periodic kernel without any of it.
+    const uint64_t apm = kAnti ? sh.apm : 0ull;
+    auto across = [Lt, apm](int P) -> uint64_t { return (kAnti && (P < 0 || P >= Lt)) ? apm : 0ull; };
     // uniform plane P; planes past Lt + 1 are never used: the load is
     // clamped, not skipped
-    auto ld = [&](int P) -> uint64_t { return buf_load(spins, voff, wrap(min(P, Lt + 1)) * plane); };
+    auto ld = [&](int P) -> uint64_t {
+        const int Q = min(P, Lt + 1);
+        return buf_load(spins, voff, wrap(Q) * plane) ^ across(Q);
+    };
     // per-lane plane P (prologue): the plane offset goes in the vector offset
-    auto ld_lane = [&](int P) -> uint64_t { return buf_load(spins, voff + wrap(P) * plane, 0); };
+    auto ld_lane = [&](int P) -> uint64_t { return buf_load(spins, voff + wrap(P) * plane, 0) ^ across(P); };
 
     // window: w0..w5 = planes A-4 .. A+1, pf = A+2, A+3, nx = A+4, A+5
     uint64_t w0 = 0, w1 = 0, w2 = 0, w3, w4, w5, pf0, pf1, nx0, nx1;
@@ -448,8 +457,9 @@ __device__ __forceinline__ void sweep_teams(const ShapeDev& sh, const int cfg0, 
         // parity 0 holds colour 1 (just updated) and colour 0 (one segment
         // old) there, parity 1 colour 0 (two segments old) and colour 1
         const int P1 = 2 * sigma - 3, P2 = 2 * sigma - 2;
-        if (active && P1 >= 0) buf_store(p ? w0 : w1, spins, voff, wrap(P1) * plane);
-        if (active && P2 >= 0) buf_store(p ? w1 : w2, spins, voff, wrap(P2) * plane);
+        const uint64_t a1 = kBulk ? 0ull : across(P1), a2 = kBulk ? 0ull : across(P2);
+        if (active && P1 >= 0) buf_store((p ? w0 : w1) ^ a1, spins, voff, wrap(P1) * plane);
+        if (active && P2 >= 0) buf_store((p ? w1 : w2) ^ a2, spins, voff, wrap(P2) * plane);
         if (active) {
             Y[(IS & 1) * H + hx] = p ? w2 : w4;
             X[((IS + 1) & 1) * H + hx] = p ? w5 : pf1;
@@ -519,7 +529,7 @@ __host__ __device__ inline int helped_words(const ShapeDev& sh) {
 
 // The body for configuration cfg = ((r*nk + w)*W + j), by a workgroup of
 // kHelpedThreads threads; lds at least helped_words(sh) words.
-template <bool kE>
+template <bool kE, bool kAnti>
 __device__ __forceinline__ void helped_body(const ShapeDev& sh, const int cfg, uint64_t* lds, const uint32_t key0,
                                             const uint32_t key1, const uint32_t t) {
     const int L = sh.L, L2 = sh.L2, Lt = sh.Lt, nk = sh.nk, W = sh.W;
@@ -589,8 +599,14 @@ __device__ __forceinline__ void helped_body(const ShapeDev& sh, const int cfg, u
     const int half = Lt >> 1;
     const int nq = Lt >> 3;
     auto wrap = [Lt](int P) { return P >= Lt ? P - Lt : (P < 0 ? P + Lt : P); };
-    auto ld = [&](int P) -> uint64_t { return buf_load(spins, voff, wrap(min(P, Lt + 1)) * plane); };
-    auto ld_lane = [&](int P) -> uint64_t { return buf_load(spins, voff + wrap(P) * plane, 0); };
+    // planes across the tau wrap are complemented when antiperiodic (above)
+    const uint64_t apm = kAnti ? sh.apm : 0ull;
+    auto across = [Lt, apm](int P) -> uint64_t { return (kAnti && (P < 0 || P >= Lt)) ? apm : 0ull; };
+    auto ld = [&](int P) -> uint64_t {
+        const int Q = min(P, Lt + 1);
+        return buf_load(spins, voff, wrap(Q) * plane) ^ across(Q);
+    };
+    auto ld_lane = [&](int P) -> uint64_t { return buf_load(spins, voff + wrap(P) * plane, 0) ^ across(P); };
     // [buffer][helper][mask][lane]: lane-contiguous, so every access is conflict-free
     auto hm = [&](int buf, int k) -> uint32_t* { return HM + ((buf * 3 + h) * 6 + k) * 64 + lane; };
 
@@ -712,8 +728,9 @@ __device__ __forceinline__ void helped_body(const ShapeDev& sh, const int cfg, u
                     if (kE) add3v(sm, f0, f1, f2);
                 }
                 const int P1 = 2 * sigma - 3, P2 = 2 * sigma - 2;
-                if (P1 >= 0) buf_store(p ? w0 : w1, spins, voff, wrap(P1) * plane);
-                if (P2 >= 0) buf_store(p ? w1 : w2, spins, voff, wrap(P2) * plane);
+                const uint64_t a1 = kBulk ? 0ull : across(P1), a2 = kBulk ? 0ull : across(P2);
+                if (P1 >= 0) buf_store((p ? w0 : w1) ^ a1, spins, voff, wrap(P1) * plane);
+                if (P2 >= 0) buf_store((p ? w1 : w2) ^ a2, spins, voff, wrap(P2) * plane);
                 Y[(IS & 1) * H + hx] = p ? w2 : w4;
                 X[((IS + 1) & 1) * H + hx] = p ? w5 : pf1;
                 __syncthreads();
@@ -773,22 +790,23 @@ __device__ __forceinline__ void helped_body(const ShapeDev& sh, const int cfg, u
     }
 }
 
-template <bool kE>
+template <bool kE, bool kAnti>
 __global__ void __launch_bounds__(kHelpedThreads)
 k_sweep_helped(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __restrict__ ctr) {
     extern __shared__ uint64_t lds[];
-    helped_body<kE>(sh, (int)blockIdx.x, lds, key0, key1, ctr->t);
+    helped_body<kE, kAnti>(sh, (int)blockIdx.x, lds, key0, key1, ctr->t);
 }
 
 // One configuration per workgroup (r, w, j) = blockIdx.x.
 // kOcc: minimum waves per SIMD the register allocation must allow (1 = no
 // constraint); a tuning knob, the results do not depend on it.  Above 1 the
 // energy counters move to LDS to fit the smaller register budget.
-template <bool kE, int kOcc>
+template <bool kE, int kOcc, bool kAnti>
 __global__ void __launch_bounds__(kMaxCols) __attribute__((amdgpu_waves_per_eu(kOcc)))
 k_sweep_stream(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __restrict__ ctr) {
     extern __shared__ uint64_t lds[];
-    sweep_teams<kE, false, (kOcc > 1)>(sh, (int)blockIdx.x, 1, 1, (int)blockDim.x, lds, key0, key1, ctr->t);
+    sweep_teams<kE, false, (kOcc > 1), kAnti>(sh, (int)blockIdx.x, 1, 1, (int)blockDim.x, lds, key0, key1,
+                                              ctr->t);
 }
 
 // Persistent sweep of every shape of a plan in one launch.  Work items
@@ -797,8 +815,9 @@ k_sweep_stream(ShapeDev sh, uint32_t key0, uint32_t key1, const Counters* __rest
 // item's configurations with g teams, then takes the next item.  U is
 // recounted in every sweep (it is exact whichever sweep last counted it), so
 // one captured graph serves every sweep.  The last block to finish rewinds
-// the queue for the next launch on the stream.
-template <int kOcc>
+// the queue for the next launch on the stream.  kAnti: some shape of the
+// plan is antiperiodic along tau (each shape's own mask then applies).
+template <int kOcc, bool kAnti>
 __global__ void __launch_bounds__(kMaxBatchThreads) __attribute__((amdgpu_waves_per_eu(kOcc)))
 k_sweep_batch(BatchArgs a) {
     extern __shared__ uint64_t lds[];
@@ -816,9 +835,9 @@ k_sweep_batch(BatchArgs a) {
         const ShapeDev& sh = a.shapes[s];
         const uint32_t t = __builtin_amdgcn_readfirstlane(a.ctr[s].t);
         if (sh.L2 == kHelpCols && blockDim.x == kHelpedThreads)
-            helped_body<true>(sh, cfg0, lds, a.key0, a.key1, t);  // one configuration, helper waves
+            helped_body<true, kAnti>(sh, cfg0, lds, a.key0, a.key1, t);  // one configuration, helper waves
         else
-            sweep_teams<true, true, false>(sh, cfg0, g, nlive, stream_cols(sh), lds, a.key0, a.key1, t);
+            sweep_teams<true, true, false, kAnti>(sh, cfg0, g, nlive, stream_cols(sh), lds, a.key0, a.key1, t);
     }
     if (threadIdx.x == 0) {
         __threadfence();
@@ -854,82 +873,107 @@ static hipError_t allow_lds(const void* fn, size_t bytes, size_t& done) {
     return e;
 }
 
-template <bool kE, int kOcc>
+template <bool kE, int kOcc, bool kAnti>
 static hipError_t prepare_one(const ShapeDev& sh) {
     static size_t lds_set = 0;
-    return allow_lds((const void*)k_sweep_stream<kE, kOcc>, sweep_stream_lds_bytes(sh, 1, stream_cols(sh), kOcc > 1),
-                     lds_set);
+    return allow_lds((const void*)k_sweep_stream<kE, kOcc, kAnti>,
+                     sweep_stream_lds_bytes(sh, 1, stream_cols(sh), kOcc > 1), lds_set);
+}
+
+template <bool kE, int kOcc>
+static hipError_t prepare_bc(const ShapeDev& sh) {
+    return sh.apm ? prepare_one<kE, kOcc, true>(sh) : prepare_one<kE, kOcc, false>(sh);
 }
 
 hipError_t prepare_sweep_stream(const ShapeDev& sh, bool energy, int occ) {
-    if (occ >= 5) return energy ? prepare_one<true, 5>(sh) : prepare_one<false, 5>(sh);
-    return energy ? prepare_one<true, 1>(sh) : prepare_one<false, 1>(sh);
+    if (occ >= 5) return energy ? prepare_bc<true, 5>(sh) : prepare_bc<false, 5>(sh);
+    return energy ? prepare_bc<true, 1>(sh) : prepare_bc<false, 1>(sh);
 }
 
-template <bool kE, int kOcc>
+template <bool kE, int kOcc, bool kAnti>
 static hipError_t launch_one(const ShapeDev& sh, uint64_t seed, const Counters* ctr, hipStream_t st) {
     const int nblk = sh.R * sh.nk * sh.W;
     const int threads = stream_cols(sh);
     const size_t lds = sweep_stream_lds_bytes(sh, 1, threads, kOcc > 1);
-    hipError_t e = prepare_one<kE, kOcc>(sh);
+    hipError_t e = prepare_one<kE, kOcc, kAnti>(sh);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_sweep_stream<kE, kOcc>), dim3(nblk), dim3(threads), lds, st, sh,
+    hipLaunchKernelGGL((k_sweep_stream<kE, kOcc, kAnti>), dim3(nblk), dim3(threads), lds, st, sh,
                        (uint32_t)seed, (uint32_t)(seed >> 32), ctr);
     return hipGetLastError();
+}
+
+template <bool kE, int kOcc>
+static hipError_t launch_bc(const ShapeDev& sh, uint64_t seed, const Counters* ctr, hipStream_t st) {
+    return sh.apm ? launch_one<kE, kOcc, true>(sh, seed, ctr, st) : launch_one<kE, kOcc, false>(sh, seed, ctr, st);
 }
 
 bool sweep_helped_ok(const ShapeDev& sh) { return sweep_stream_ok(sh) && sh.L2 == kHelpCols; }
 
-template <bool kE>
+template <bool kE, bool kAnti>
 static hipError_t launch_helped_one(const ShapeDev& sh, uint64_t seed, const Counters* ctr, hipStream_t st,
                                     bool launch) {
     static size_t lds_set = 0;
     const size_t lds = (size_t)helped_words(sh) * 8;
-    hipError_t e = allow_lds((const void*)k_sweep_helped<kE>, lds, lds_set);
+    hipError_t e = allow_lds((const void*)k_sweep_helped<kE, kAnti>, lds, lds_set);
     if (e != hipSuccess || !launch) return e;
-    hipLaunchKernelGGL((k_sweep_helped<kE>), dim3(sh.R * sh.nk * sh.W), dim3(kHelpedThreads), lds, st, sh,
-                       (uint32_t)seed, (uint32_t)(seed >> 32), ctr);
+    hipLaunchKernelGGL((k_sweep_helped<kE, kAnti>), dim3(sh.R * sh.nk * sh.W), dim3(kHelpedThreads), lds, st,
+                       sh, (uint32_t)seed, (uint32_t)(seed >> 32), ctr);
     return hipGetLastError();
+}
+
+template <bool kE>
+static hipError_t launch_helped_bc(const ShapeDev& sh, uint64_t seed, const Counters* ctr, hipStream_t st,
+                                   bool launch) {
+    return sh.apm ? launch_helped_one<kE, true>(sh, seed, ctr, st, launch)
+                  : launch_helped_one<kE, false>(sh, seed, ctr, st, launch);
 }
 
 hipError_t launch_sweep_helped(const ShapeDev& sh, uint64_t seed, const Counters* ctr, bool energy,
                                hipStream_t st) {
-    return energy ? launch_helped_one<true>(sh, seed, ctr, st, true)
-                  : launch_helped_one<false>(sh, seed, ctr, st, true);
+    return energy ? launch_helped_bc<true>(sh, seed, ctr, st, true)
+                  : launch_helped_bc<false>(sh, seed, ctr, st, true);
 }
 
 hipError_t prepare_sweep_helped(const ShapeDev& sh, bool energy) {
-    return energy ? launch_helped_one<true>(sh, 0, nullptr, nullptr, false)
-                  : launch_helped_one<false>(sh, 0, nullptr, nullptr, false);
+    return energy ? launch_helped_bc<true>(sh, 0, nullptr, nullptr, false)
+                  : launch_helped_bc<false>(sh, 0, nullptr, nullptr, false);
 }
 
 hipError_t launch_sweep_stream(const ShapeDev& sh, uint64_t seed, const Counters* ctr,
                                bool energy, int occ, hipStream_t st) {
     if (occ >= 5)
-        return energy ? launch_one<true, 5>(sh, seed, ctr, st) : launch_one<false, 5>(sh, seed, ctr, st);
-    return energy ? launch_one<true, 1>(sh, seed, ctr, st) : launch_one<false, 1>(sh, seed, ctr, st);
+        return energy ? launch_bc<true, 5>(sh, seed, ctr, st) : launch_bc<false, 5>(sh, seed, ctr, st);
+    return energy ? launch_bc<true, 1>(sh, seed, ctr, st) : launch_bc<false, 1>(sh, seed, ctr, st);
 }
 
-static const void* batch_fn(int occ) {
-    return occ >= 2 ? (const void*)k_sweep_batch<2> : (const void*)k_sweep_batch<1>;
+static const void* batch_fn(int occ, bool anti) {
+    if (anti) return occ >= 2 ? (const void*)k_sweep_batch<2, true> : (const void*)k_sweep_batch<1, true>;
+    return occ >= 2 ? (const void*)k_sweep_batch<2, false> : (const void*)k_sweep_batch<1, false>;
 }
 
-hipError_t sweep_batch_prepare(int occ, size_t lds_bytes, int threads, int* blocks_per_cu) {
-    static size_t set1 = 0, set2 = 0;
-    hipError_t e = allow_lds(batch_fn(occ), lds_bytes, occ >= 2 ? set2 : set1);
+hipError_t sweep_batch_prepare(int occ, bool anti, size_t lds_bytes, int threads, int* blocks_per_cu) {
+    static size_t set[2][2] = {{0, 0}, {0, 0}};
+    hipError_t e = allow_lds(batch_fn(occ, anti), lds_bytes, set[anti ? 1 : 0][occ >= 2 ? 1 : 0]);
     if (e != hipSuccess || !blocks_per_cu) return e;
     int nb = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_fn(occ), threads, lds_bytes);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_fn(occ, anti), threads, lds_bytes);
     *blocks_per_cu = nb;
     return e;
 }
 
-hipError_t launch_sweep_batch(const BatchArgs& a, int occ, int blocks, int threads, size_t lds_bytes,
-                              hipStream_t st) {
-    if (occ >= 2)
-        hipLaunchKernelGGL((k_sweep_batch<2>), dim3(blocks), dim3(threads), lds_bytes, st, a);
-    else
-        hipLaunchKernelGGL((k_sweep_batch<1>), dim3(blocks), dim3(threads), lds_bytes, st, a);
+hipError_t launch_sweep_batch(const BatchArgs& a, int occ, bool anti, int blocks, int threads,
+                              size_t lds_bytes, hipStream_t st) {
+    if (anti) {
+        if (occ >= 2)
+            hipLaunchKernelGGL((k_sweep_batch<2, true>), dim3(blocks), dim3(threads), lds_bytes, st, a);
+        else
+            hipLaunchKernelGGL((k_sweep_batch<1, true>), dim3(blocks), dim3(threads), lds_bytes, st, a);
+    } else {
+        if (occ >= 2)
+            hipLaunchKernelGGL((k_sweep_batch<2, false>), dim3(blocks), dim3(threads), lds_bytes, st, a);
+        else
+            hipLaunchKernelGGL((k_sweep_batch<1, false>), dim3(blocks), dim3(threads), lds_bytes, st, a);
+    }
     return hipGetLastError();
 }
 

@@ -14,6 +14,9 @@ struct ShapeDev {
     int L, L2, Lt, nk, W, R, P;  // P = replica pairs
     uint32_t sid, word_offset;
     uint32_t pt_every;
+    // all ones when the tau boundary is antiperiodic: a spin word read
+    // across the tau wrap enters complemented (the wrap bond has the sign -1)
+    uint64_t apm;
     uint64_t* S;            // spins  [R][nk][W][Lt][L2]
     uint64_t* J;            // couplings [W][2][L2]
     uint8_t* kidx;          // [R][W*64][nk]  k-index of walker w
@@ -165,9 +168,10 @@ int sweep_stream_cols(const ShapeDev& sh);
 size_t sweep_helped_lds_bytes(const ShapeDev& sh);
 // Batched persistent sweep: allow its LDS and report resident blocks per CU
 // (occ: 1 or 2 = minimum waves per SIMD the kernel was compiled for).
-hipError_t sweep_batch_prepare(int occ, size_t lds_bytes, int threads, int* blocks_per_cu);
-hipError_t launch_sweep_batch(const BatchArgs& a, int occ, int blocks, int threads, size_t lds_bytes,
-                              hipStream_t st);
+// anti: some shape of the plan is antiperiodic along tau
+hipError_t sweep_batch_prepare(int occ, bool anti, size_t lds_bytes, int threads, int* blocks_per_cu);
+hipError_t launch_sweep_batch(const BatchArgs& a, int occ, bool anti, int blocks, int threads,
+                              size_t lds_bytes, hipStream_t st);
 // Tempering (when due, read from the counters) of every shape, then the
 // counter advance t += 1, m += due.
 hipError_t launch_temper_batch(const TemperBatchArgs& a, int blocks, int max_nk, hipStream_t st);

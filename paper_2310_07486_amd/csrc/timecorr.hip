@@ -153,10 +153,14 @@ __global__ void __launch_bounds__(256) k_timecorr_mfma(ShapeDev sh, int cfg0, in
             }
         }
         __syncthreads();
-        // c[d] = U[d] + U[Ltau - d] for d > 0, c[0] = U[0] (likewise q2)
+        // c[d] = U[d] + U[Ltau - d] for d > 0, c[0] = U[0] (likewise q2).  The
+        // terms of U[Ltau - d] cross the tau wrap: with an antiperiodic
+        // boundary they enter c with the sign -1 (q2 squares the sign away).
+        const bool anti = sh.apm != 0ull;
         for (int e = tid; e < 2 * Lt; e += 256) {
             const int h = e / Lt, d = e % Lt;
-            const unsigned long long u = Cb[e] + (d ? Cb[h * Lt + Lt - d] : 0ull);
+            const unsigned long long w = d ? Cb[h * Lt + Lt - d] : 0ull;
+            const unsigned long long u = (anti && h == 0) ? Cb[e] - w : Cb[e] + w;
             rec[(size_t)cl * 2 * Lt + e] = (int64_t)u;
         }
         __syncthreads();

@@ -33,6 +33,7 @@ class Shape:
     pt_every: int = 1
     stream_id: int = 0
     word_offset: int = 0
+    bc_tau: int = 0  # 0 periodic along tau, 1 antiperiodic
 
     @property
     def n_samples(self) -> int:

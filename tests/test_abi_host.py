@@ -46,12 +46,14 @@ def test_plan_validation(bad, status):
     assert e.value.status == status
 
 
-def test_antiperiodic_unsupported_and_stream_ids():
+def test_boundary_conditions_and_stream_ids():
     s = Shape(8, 32, 1, 2, [0.2, 0.3])
     s.bc_tau = tfim.TFIM_BC_ANTIPERIODIC
+    _plan([s]).close()  # accepted
+    s.bc_tau = 2
     with pytest.raises(tfim.TfimError) as e:
         _plan([s])
-    assert e.value.status == tfim.TFIM_EUNSUPPORTED
+    assert e.value.status == tfim.TFIM_EINVAL
     with pytest.raises(tfim.TfimError) as e:
         _plan([Shape(8, 32, 1, 2, [0.2], stream_id=3), Shape(8, 64, 1, 2, [0.2], stream_id=3)])
     assert e.value.status == tfim.TFIM_EINVAL

@@ -308,3 +308,25 @@ def test_time_bands_closed_forms():
         q += om.time_record([om.spin_matrix(_rand_S(rng, L, Lt))])[Lt:]
     mean = q[1:] / n
     assert np.all(np.abs(mean - Lt * L * L) < 0.1 * Lt * L * L)
+
+
+def test_time_bands_antiperiodic():
+    """Antiperiodic along tau: c[d] = sum_t1 S(t1) S~(t1 + d) with the
+    antiperiodic continuation S~(t + Ltau) = -S(t), so c[0] = L^2 Ltau,
+    c[Ltau - d] = -c[d] and c[Ltau/2] = 0; q2 is unchanged.  A product state
+    S = a b^T gives L^2 times the antiperiodic autocorrelation of b."""
+    rng = np.random.default_rng(24)
+    L, Lt = 3, 12
+    S = om.spin_matrix(_rand_S(rng, L, Lt))
+    p = om.time_record([S], 0)
+    a = om.time_record([S], 1)
+    c = a[:Lt]
+    neg = (-np.arange(Lt)) % Lt
+    assert c[0] == L * L * Lt and np.array_equal(c[1:], -c[neg][1:]) and c[Lt // 2] == 0
+    assert np.array_equal(a[Lt:], p[Lt:])
+    b = rng.choice([-1, 1], size=Lt)
+    av = rng.choice([-1, 1], size=L * L)
+    ext = np.concatenate([b, -b])
+    auto = np.array([sum(b[t] * ext[t + d] for t in range(Lt)) for d in range(Lt)])
+    rec = om.time_record([np.outer(av, b).astype(np.float64)], 1)
+    assert np.array_equal(rec[:Lt], L * L * auto)

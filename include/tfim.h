@@ -65,7 +65,7 @@ typedef int32_t tfim_status;
 
 /* Boundary condition along tau (Methods, "The Trotter-Suzuki formula"). */
 #define TFIM_BC_PERIODIC 0u
-#define TFIM_BC_ANTIPERIODIC 1u /* returns TFIM_EUNSUPPORTED */
+#define TFIM_BC_ANTIPERIODIC 1u /* the temporal bond tau = Ltau-1 -- 0 has the sign -1 */
 
 /* One problem shape: n_words*64 disorder samples of an L x L x Ltau lattice,
  * n_replicas independent real replicas, each with n_k walkers that share the
@@ -78,7 +78,8 @@ typedef struct {
     uint32_t n_replicas;  /* 1..64 */
     uint32_t n_k;         /* 1..255 */
     const double *k;      /* n_k couplings, > 0, strictly increasing; copied */
-    uint32_t bc_tau;      /* TFIM_BC_PERIODIC */
+    uint32_t bc_tau;      /* TFIM_BC_PERIODIC or TFIM_BC_ANTIPERIODIC (Methods,
+                             "The Trotter-Suzuki formula": antiperiodic along tau only) */
     uint32_t pt_every;    /* tempering after every pt_every-th sweep; 0 = never */
     uint32_t stream_id;   /* 0..255, distinct within a plan */
 } tfim_shape;
@@ -97,7 +98,7 @@ typedef struct {
 
 /* Create a plan for n_shapes shapes sampled together with one seed.
  * TFIM_EINVAL: odd or out-of-range L/Ltau, n_words = 0, bad ladder,
- * repeated stream_id.  TFIM_EUNSUPPORTED: antiperiodic bc_tau. */
+ * repeated stream_id, unknown bc_tau. */
 tfim_status tfim_plan_create(const tfim_shape *shapes, uint32_t n_shapes, uint64_t seed,
                              tfim_plan **plan_out);
 void tfim_plan_destroy(tfim_plan *plan);
@@ -209,7 +210,9 @@ tfim_status tfim_measure_triples(tfim_plan *plan, uint32_t shape, uint32_t cfg0,
  *   q2[d] = sum_r sum_t1 (H^r_t1,(t1+d) mod Ltau)^2,   d = 0..Ltau-1,
  * as int64 [ncfg][2][Ltau] = [c[0..Ltau-1], q2[0..Ltau-1]], exact.
  * C(tau) = c[tau] / (R L^2 Ltau) and Q2(tau) = q2[tau] / (R L^4 Ltau)
- * (C(0) = Q2(0) = 1).  Needs 1..4 replicas, L <= 32, Ltau <= 4096 (else
+ * (C(0) = Q2(0) = 1).  With bc_tau = TFIM_BC_ANTIPERIODIC the configuration
+ * continues past Ltau with the opposite sign, so the terms of c with
+ * t1 + d >= Ltau enter with the sign -1 (c[Ltau - d] = -c[d]).  Needs 1..4 replicas, L <= 32, Ltau <= 4096 (else
  * TFIM_EUNSUPPORTED).  ws: caller-owned device memory, 256-byte aligned, at
  * least ncfg*2*Ltau*8 bytes, holding the records afterwards.  flags as for
  * tfim_measure_range.  out == NULL: enqueue only (asynchronous); otherwise

@@ -174,8 +174,14 @@ def test_triples_workspace_and_limits():
     p = _plan([Shape(10, 64, 1, 3, ladder(0.2, 0.3, 2))])
     assert p.triples_workspace_bytes(0, 3) == 256 * ((3 * 1 * 20 * 8 + 255) // 256) + 3 * 3 * 2 * 256 * 256
     p.close()
+    # at the largest L = 24 the int64 bound 3 L^6 Ltau^3 < 2^63 allows Ltau <= 2520
+    assert 3 * 576 ** 3 * 2520 ** 3 < 2 ** 63 <= 3 * 576 ** 3 * 2528 ** 3
+    p = _plan([Shape(24, 2520, 1, 4, ladder(0.2, 0.3, 2))])
+    assert p.triples_workspace_bytes(0, 1) > 0
+    p.close()
     for sh in (Shape(8, 64, 1, 2, ladder(0.2, 0.3, 2)),      # two replicas
-               Shape(24, 4096, 1, 4, ladder(0.2, 0.3, 2))):  # L^2 (Ltau/2)^2 >= 2^31
+               Shape(24, 2528, 1, 4, ladder(0.2, 0.3, 2)),   # 3 L^6 Ltau^3 >= 2^63
+               Shape(24, 4096, 1, 4, ladder(0.2, 0.3, 2))):  # both bounds exceeded
         p = _plan([sh])
         with pytest.raises(tfim.TfimError) as ei:
             p.triples_workspace_bytes(0, 1)

@@ -3,8 +3,11 @@ correlation lengths over the lattice size, xi^(2)/L and xi^(3)/L (Methods,
 "One-time observables"), of the two smallest sizes of Table I (L = 8 and 12,
 Ltau = 512, k uniformly spaced over [0.265, 0.305]) must cross inside that
 k range, close to the critical coupling the paper locates near 0.29 (its
-xi^(3) crossing for this pair of sizes is near 0.291).  The Binder ratio
-must start near its Gaussian value 3 and the two sizes' curves cross once.
+xi^(3) crossing for this pair of sizes is 0.2910(15)); with bootstrap errors
+over the disorder samples, as the paper estimates them, the xi^(3) crossing
+must agree with that value within three standard deviations.  The Binder
+ratio must start near its Gaussian value 3 and the two sizes' curves cross
+once.
 
 Statistical, with a deliberately loose window: 512 disorder samples, 4
 replicas, tempering every sweep, 5*10^4 equilibration sweeps and 100
@@ -31,6 +34,7 @@ def _run(L, nk, seed, n_eq=50000, n_meas=100, gap=200):
     S = sh.n_samples
     A = np.zeros((nk, L), dtype=np.int64)
     T = np.zeros((nk, n_meas, 2 * L), dtype=np.int64)  # per measurement: samples and triples summed
+    Ts = np.zeros((nk, S, 2 * L), dtype=np.int64)      # per sample: triples and measurements summed
     P = []
     for m in range(n_meas):
         plan.sweep(gap)
@@ -38,7 +42,9 @@ def _run(L, nk, seed, n_eq=50000, n_meas=100, gap=200):
         A += rec[:, :, :, :L].sum(axis=(1, 2))
         P.append(rec[:, :, :, 2 * L + 1:].sum(axis=1))    # sum Q^2, sum Q^4 per k and pair
         tr = plan.measure_triples(0, 0, nk * S, flags=tfim.TFIM_MEASURE_REUSE_LAYOUT)
-        T[:, m] = tr.reshape(nk, S, -1, 2 * L).sum(axis=(1, 2))
+        tr = tr.reshape(nk, S, -1, 2 * L).sum(axis=2)
+        T[:, m] = tr.sum(axis=1)
+        Ts += tr
     plan.close()
     q = np.stack(P, axis=1)  # [k][meas][pair][2]
     pr = np.zeros((nk, q.shape[1] * q.shape[2], 2 * L + 3), dtype=np.int64)
@@ -46,7 +52,22 @@ def _run(L, nk, seed, n_eq=50000, n_meas=100, gap=200):
     # the Binder ratio of the means over samples: n_per_k counts every record
     B = tfim.tfim_binder(pr, L, sh.Ltau) * S
     k = np.asarray(sh.k)
-    return k, tfim.tfim_xi2(np.ascontiguousarray(A), L) / L, tfim.tfim_xi3(T, L, 2) / L, B
+    return k, tfim.tfim_xi2(np.ascontiguousarray(A), L) / L, tfim.tfim_xi3(T, L, 2) / L, B, Ts
+
+
+def _xi3_boot(Ts, L, rng, n_boot):
+    """xi^(3)/L per k for n_boot resamplings of the disorder samples (with
+    replacement), from per-sample records [k][s][2L] (both directions)."""
+    nk, S, _ = Ts.shape
+    A = (Ts[:, :, :L] + Ts[:, :, L:]).astype(np.float64)  # [k][s][d]
+    cosw = np.cos(2 * np.pi * np.arange(L) / L)
+    out = np.zeros((n_boot, nk))
+    for b in range(n_boot):
+        w = np.bincount(rng.integers(0, S, size=S), minlength=S).astype(np.float64)
+        Ab = np.einsum("s,ksd->kd", w, A)
+        ratio = Ab.sum(axis=1) / (Ab @ cosw)
+        out[b] = np.sqrt(np.maximum(ratio - 1.0, 0.0)) / (2 * np.sin(np.pi / L)) / L
+    return out
 
 
 def _crossings(c8, c12, lo, hi):
@@ -61,7 +82,7 @@ def test_xi_over_L_crossing_of_the_two_smallest_sizes():
         print(f"physics: L={L} Ltau=512 512 samples, equilibrating", flush=True)
         sys.stdout.flush()
         runs[L] = _run(L, nk, 4200 + L)
-    for L, (k, x2, x3, B) in runs.items():
+    for L, (k, x2, x3, B, _) in runs.items():
         print(f"physics: L={L} xi2/L {np.round(x2, 4).tolist()}", flush=True)
         print(f"physics: L={L} xi3/L {np.round(x3, 4).tolist()}", flush=True)
         print(f"physics: L={L} Binder {np.round(B, 4).tolist()}", flush=True)
@@ -74,7 +95,7 @@ def test_xi_over_L_crossing_of_the_two_smallest_sizes():
     assert d[0] < 0 < d[-1], "the larger lattice must start below and end above"
     assert len(cross) == 1 and 0.28 <= cross[0] <= 0.30
     # xi^(3)/L, the paper's headline length (Fig. 1b): the same crossing
-    for L, (k, x2, x3, B) in runs.items():
+    for L, (k, x2, x3, B, _) in runs.items():
         assert np.all(np.diff(x3) > 0), f"xi3/L of L={L} not increasing in k"
         assert np.all((B > 1.0) & (B < 3.05)), f"Binder ratio of L={L} outside (1, 3]"
     assert d3[0] < 0 < d3[-1] and len(cross3) == 1 and 0.28 <= cross3[0] <= 0.30
@@ -82,3 +103,19 @@ def test_xi_over_L_crossing_of_the_two_smallest_sizes():
     db, crossb = _crossings((runs[8][0], runs[8][3]), (runs[12][0], runs[12][3]), 0.265, 0.305)
     print(f"physics: Binder crossing at k = {crossb}", flush=True)
     assert db[0] > 0 > db[-1] and len(crossb) == 1 and 0.28 <= crossb[0] <= 0.305
+    # bootstrap over disorder samples (the paper's error method for the
+    # crossing points): k*(8, 12) of xi^(3)/L against the paper's 0.2910(15)
+    rng = np.random.default_rng(2310)
+    b8 = _xi3_boot(runs[8][4], 8, rng, 200)
+    b12 = _xi3_boot(runs[12][4], 12, rng, 200)
+    ks = []
+    for b in range(200):
+        _, cb = _crossings((runs[8][0], b8[b]), (runs[12][0], b12[b]), 0.265, 0.305)
+        if len(cb) == 1:
+            ks.append(cb[0])
+    ks = np.array(ks)
+    sigma = float(ks.std(ddof=1))
+    print(f"physics: xi3/L crossing {cross3[0]:.4f} +- {sigma:.4f} (bootstrap, {len(ks)} of 200 with one crossing)",
+          flush=True)
+    assert len(ks) >= 180 and 0.0 < sigma < 0.01
+    assert abs(cross3[0] - 0.2910) < 3.0 * np.hypot(sigma, 0.0015)

@@ -239,6 +239,31 @@ tfim_status tfim_xi3(const int64_t *rec, uint32_t L, uint32_t n_k, uint32_t n_pe
 tfim_status tfim_binder(const int64_t *rec, uint32_t L, uint32_t Ltau, uint32_t n_k,
                         uint32_t n_per_k, double *B_out);
 
+/* Transfer matrix of one plane (Methods, "The Trotter-Suzuki formula":
+ * Z = Tr T^Ltau, the antiperiodic boundary as Tr P T^Ltau with the global
+ * flip P; "Simulation details": exact diagonalisation in parity sectors).
+ * For one sample's couplings Jx, Jy (host int8, +-1, L*L each, the canonical
+ * coupling layout of a lane) and 2 <= L <= 5 (else TFIM_EUNSUPPORTED):
+ *   T[s,s'] = exp(k/2 E0(s)) exp(k sum_x s_x s'_x) exp(k/2 E0(s')),
+ *   E0(s) = sum over spatial bonds (each once) of J_b s_x s_y,
+ * on 2^(L^2) states, bit x of the index set when s_x = -1.  T equals the
+ * paper's exp(-k/2 H0) exp(-k H1) exp(-k/2 H0) up to a constant factor.
+ * tfim_tm_apply: w = T v for device vectors of 2^(L^2) doubles (distinct),
+ *   asynchronous on hip_stream.
+ * tfim_tm_top: largest eigenvalue of the even (sector 0, P = +1) or odd
+ *   (sector 1) sector by power iteration from a fixed start vector, until
+ *   two successive Rayleigh quotients differ by at most tol relative or
+ *   max_iter products; the normalised eigenvector is left at the start of
+ *   ws (2^(L^2) doubles).  ws: caller-owned device memory of at least
+ *   tfim_tm_workspace bytes, 256-byte aligned.  Synchronous.  Returns the
+ *   eigenvalue and the number of products used. */
+tfim_status tfim_tm_workspace(uint32_t L, size_t *bytes_out);
+tfim_status tfim_tm_apply(uint32_t L, double k, const int8_t *Jx, const int8_t *Jy,
+                          const double *v, double *w, void *hip_stream);
+tfim_status tfim_tm_top(uint32_t L, double k, const int8_t *Jx, const int8_t *Jy, uint32_t sector,
+                        double tol, uint32_t max_iter, void *workspace, size_t workspace_bytes,
+                        void *hip_stream, double *lambda_out, uint32_t *iters_out);
+
 /* Threshold tables of a shape (host-only): Tm[n_k][3] with
  * Tm[i][u] = floor(2^32 exp(-k_i (12 - 4u))) for u = 0,1,2 unsatisfied
  * bonds of six; dmax[n_k-1]; Tpt[sum dmax] with, for pair i, entries

@@ -927,6 +927,50 @@ tfim_status tfim_get_thresholds(const tfim_plan* pl, uint32_t shape, uint32_t* T
     return TFIM_OK;
 }
 
+static tfim_status tm_args(uint32_t L, double k, const int8_t* Jx, const int8_t* Jy) {
+    if (const char* why = tfim::tm_unsupported((int)L)) return fail(TFIM_EUNSUPPORTED, why);
+    if (!(k > 0.0) || !std::isfinite(k)) return fail(TFIM_EINVAL, "k must be finite and > 0");
+    if (!Jx || !Jy) return fail(TFIM_EINVAL, "null couplings");
+    for (uint32_t i = 0; i < L * L; ++i)
+        if ((Jx[i] != 1 && Jx[i] != -1) || (Jy[i] != 1 && Jy[i] != -1))
+            return fail(TFIM_EINVAL, "couplings must be +1 or -1");
+    return TFIM_OK;
+}
+
+tfim_status tfim_tm_workspace(uint32_t L, size_t* bytes) {
+    if (!bytes) return fail(TFIM_EINVAL, "null argument");
+    if (const char* why = tfim::tm_unsupported((int)L)) return fail(TFIM_EUNSUPPORTED, why);
+    *bytes = tfim::tm_workspace_bytes((int)L);
+    return TFIM_OK;
+}
+
+tfim_status tfim_tm_apply(uint32_t L, double k, const int8_t* Jx, const int8_t* Jy, const double* v,
+                          double* w, void* hip_stream) {
+    tfim_status st = tm_args(L, k, Jx, Jy);
+    if (st != TFIM_OK) return st;
+    if (!v || !w || v == w) return fail(TFIM_EINVAL, "v and w must be distinct device vectors");
+    const hipError_t e = tfim::tm_apply((int)L, k, Jx, Jy, v, w, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return fail(TFIM_EDEVICE, std::string("transfer matrix: ") + hipGetErrorString(e));
+    return TFIM_OK;
+}
+
+tfim_status tfim_tm_top(uint32_t L, double k, const int8_t* Jx, const int8_t* Jy, uint32_t sector,
+                        double tol, uint32_t max_iter, void* ws, size_t ws_bytes, void* hip_stream,
+                        double* lambda_out, uint32_t* iters_out) {
+    tfim_status st = tm_args(L, k, Jx, Jy);
+    if (st != TFIM_OK) return st;
+    if (sector > 1) return fail(TFIM_EINVAL, "sector must be 0 (even) or 1 (odd)");
+    if (!(tol > 0.0) || max_iter == 0 || !lambda_out) return fail(TFIM_EINVAL, "bad iteration arguments");
+    if (!ws || ((uintptr_t)ws & 255)) return fail(TFIM_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < tfim::tm_workspace_bytes((int)L)) return fail(TFIM_EINVAL, "workspace too small");
+    int it = 0;
+    const hipError_t e = tfim::tm_top((int)L, k, Jx, Jy, (int)sector, tol, (int)std::min<uint32_t>(max_iter, 1u << 30),
+                                      ws, lambda_out, &it, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return fail(TFIM_EDEVICE, std::string("transfer matrix: ") + hipGetErrorString(e));
+    if (iters_out) *iters_out = (uint32_t)it;
+    return TFIM_OK;
+}
+
 tfim_status tfim_xi3(const int64_t* rec, uint32_t L, uint32_t n_k, uint32_t n_per_k,
                      uint32_t direction, double* xi) {
     if (!rec || !xi || L < 2 || direction > 2) return fail(TFIM_EINVAL, "bad xi3 arguments");

@@ -41,7 +41,7 @@ SYMBOLS = [
     "tfim_last_error_detail", "tfim_set_variant", "tfim_set_timing", "tfim_get_timing",
     "tfim_measure_range", "tfim_set_measure_mode", "tfim_set_batch",
     "tfim_triples_workspace", "tfim_measure_triples", "tfim_xi3", "tfim_binder",
-    "tfim_measure_time",
+    "tfim_measure_time", "tfim_tm_workspace", "tfim_tm_apply", "tfim_tm_top",
 ]
 TFIM_MEASURE_REUSE_LAYOUT = 1
 
@@ -125,6 +125,9 @@ def lib():
             "tfim_xi3": [P, U32, U32, U32, U32, P],
             "tfim_binder": [P, U32, U32, U32, U32, P],
             "tfim_measure_time": [P, U32, U32, U32, U32, P, SZ, P, SZ],
+            "tfim_tm_workspace": [U32, P],
+            "tfim_tm_apply": [U32, ctypes.c_double, P, P, P, P, P],
+            "tfim_tm_top": [U32, ctypes.c_double, P, P, U32, ctypes.c_double, U32, P, SZ, P, P, P],
             "tfim_strerror": [ctypes.c_int32],
             "tfim_last_error_detail": [],
         }
@@ -176,6 +179,42 @@ def tfim_binder(rec: np.ndarray, L: int, Ltau: int) -> np.ndarray:
     out = np.zeros(n_k, dtype=np.float64)
     _check(lib().tfim_binder(_ptr(rec), L, Ltau, n_k, n_per_k, _ptr(out)), "tfim_binder")
     return out
+
+
+def _stream_ptr(stream):
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(st.cuda_stream)
+
+
+def tm_apply(L: int, k: float, Jx, Jy, v, w, stream=None):
+    """w = T v for torch float64 device vectors of 2^(L^2) entries (the
+    transfer matrix of one plane with couplings Jx, Jy; asynchronous)."""
+    Jx = np.ascontiguousarray(Jx, dtype=np.int8)
+    Jy = np.ascontiguousarray(Jy, dtype=np.int8)
+    _check(lib().tfim_tm_apply(L, float(k), _ptr(Jx), _ptr(Jy), ctypes.c_void_p(v.data_ptr()),
+                               ctypes.c_void_p(w.data_ptr()), _stream_ptr(stream)), "tfim_tm_apply")
+
+
+def tm_top(L: int, k: float, Jx, Jy, sector: int, tol: float = 1e-13, max_iter: int = 100000,
+           stream=None, return_vector: bool = False):
+    """Largest eigenvalue of the even (0) or odd (1) parity sector of the
+    transfer matrix, by power iteration on the device: (lambda, products)."""
+    import torch
+    Jx = np.ascontiguousarray(Jx, dtype=np.int8)
+    Jy = np.ascontiguousarray(Jy, dtype=np.int8)
+    n = ctypes.c_size_t(0)
+    _check(lib().tfim_tm_workspace(L, ctypes.byref(n)), "tfim_tm_workspace")
+    ws = torch.empty(n.value, dtype=torch.uint8, device="cuda")
+    lam = ctypes.c_double(0.0)
+    it = ctypes.c_uint32(0)
+    _check(lib().tfim_tm_top(L, float(k), _ptr(Jx), _ptr(Jy), sector, float(tol), max_iter,
+                             ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream),
+                             ctypes.byref(lam), ctypes.byref(it)), "tfim_tm_top")
+    if return_vector:
+        vec = ws[: 8 << (L * L)].view(torch.float64).cpu().numpy()
+        return lam.value, it.value, vec
+    return lam.value, it.value
 
 
 class Plan:

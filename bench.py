@@ -14,6 +14,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -248,6 +249,51 @@ def timecorr_leg(plan, sh, torch, args):
     }
 
 
+def transfer_leg(torch, args):
+    """Transfer matrix of one plane at L = 5 (2^25 states, one seeded sample
+    of +-1 couplings, k = 0.29): the matrix-free product, timed, and the
+    largest eigenvalue of each parity sector by power iteration."""
+    from paper_2310_07486_amd import tfim
+    L, k = 5, 0.29
+    rng = np.random.default_rng(2310074865)
+    Jx = rng.choice(np.array([-1, 1], dtype=np.int8), size=L * L)
+    Jy = rng.choice(np.array([-1, 1], dtype=np.int8), size=L * L)
+    n = 1 << (L * L)
+    v = torch.rand(n, dtype=torch.float64, device="cuda")
+    w = torch.empty_like(v)
+    stream = torch.cuda.current_stream()
+    tfim.tm_apply(L, k, Jx, Jy, v, w)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = 20
+    e0.record(stream)
+    for _ in range(reps):
+        tfim.tm_apply(L, k, Jx, Jy, v, w)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    alg = 2 * 8 * n          # read v once, write w once
+    moved = 3 * alg          # three passes over the vector
+    gbs = alg / (ms * 1e-3) / 1e9
+    log("bench: transfer: L=5 product %.3f ms, %.0f GB/s algorithmic (%.0f GB/s moved by 3 passes)"
+        % (ms, gbs, moved / (ms * 1e-3) / 1e9))
+    del v, w
+    lam = []
+    for sector in (0, 1):
+        t0 = time.time()
+        lv, it = tfim.tm_top(L, k, Jx, Jy, sector, tol=1e-13, max_iter=100000)
+        lam.append({"sector": "even" if sector == 0 else "odd", "lambda": lv, "products": it,
+                    "seconds": round(time.time() - t0, 3)})
+    split = (math.log(lam[0]["lambda"]) - math.log(lam[1]["lambda"])) / k
+    return {
+        "L": L, "k": k, "states": n, "product_ms": round(ms, 4),
+        "algorithmic_bytes_per_product": alg, "bytes_moved_per_product": moved,
+        "algorithmic_gbs": round(gbs, 1), "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+        "top_eigenvalues": lam, "sector_splitting_E0odd_minus_E0even": round(split, 9),
+    }
+
+
 def batched_leg(torch, args):
     """Five uneven sizes (L, Ltau) = (8,256) .. (24,2048), 512 samples each:
     the per-shape schedule (five sweep launches per sweep, one per size)
@@ -319,6 +365,7 @@ def main():
     ap.add_argument("--no-measure", action="store_true")
     ap.add_argument("--no-triples", action="store_true")
     ap.add_argument("--no-timecorr", action="store_true")
+    ap.add_argument("--no-transfer", action="store_true")
     ap.add_argument("--triples-chunk", type=int, default=4096)
     ap.add_argument("--unbatched-cfgs", type=int, default=64)
     ap.add_argument("--plain-cfgs", type=int, default=1)
@@ -430,6 +477,8 @@ def main():
     plan.close()
     del plan
     torch.cuda.empty_cache()
+    if not args.no_transfer:
+        result["transfer"] = transfer_leg(torch, args)
     if not args.no_batched:
         result["batched"] = batched_leg(torch, args)
     if not args.no_cpu_baseline:

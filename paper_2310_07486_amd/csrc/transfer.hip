@@ -11,13 +11,16 @@
 //   T = D^1/2 K D^1/2,  D = diag(exp(k E0)),  K = (x)_x [[e^k, e^-k], [e^-k, e^k]],
 // on 2^N states (N = L^2; bit x of the index is set when s_x = -1).  K is
 // applied as N two-term butterflies, one per bit: w[s] <- e^k w[s] +
-// e^-k w[s ^ 2^x].  The first pass takes bits 0..11 of contiguous chunks of
-// 4096 states in LDS (and the D^1/2 scale on the way in); further passes take
-// up to 8 bits each on tiles of 16 consecutive low indices (128-byte rows),
-// in place, the last one scaling by D^1/2 on the way out.  E0(s) comes from
-// popcounts of s xor its neighbour-permuted copies against the masks of the
-// +1 and -1 couplings; exp(k E0 / 2) is a table of 4N + 1 entries.  The
-// product is HBM-bound: each pass reads and writes the whole vector.
+// e^-k w[s ^ 2^x].  For N >= 16 every pass works on tiles of 4096 states (32
+// KB of LDS): the first on bits 0..11 of contiguous chunks (and the D^1/2
+// scale on the way in), the others on up to 8 bits with 16 to 256 columns
+// of consecutive lower indices (128-byte or longer rows), in place, the last
+// one scaling by D^1/2 on the way out.  Each thread applies four butterflies
+// at a time in registers between LDS exchanges.  N <= 12 (L = 2, 3) takes
+// one block per 2^N states.  E0(s) comes from popcounts of s xor its
+// neighbour-permuted copies against the masks of the +1 and -1 couplings;
+// exp(k E0 / 2) is a table of 4N + 1 entries.  The product is HBM-bound:
+// each pass reads and writes the whole vector (three passes at L = 5).
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -29,7 +32,6 @@ namespace {
 
 constexpr int kLowBits = 12;   // bits of the first pass (4096 states per block)
 constexpr int kMidBits = 8;    // bits per later pass
-constexpr int kCols = 16;      // consecutive low indices per later-pass tile
 constexpr int kMaxN = 25;      // L <= 5
 
 struct TmParams {
@@ -75,40 +77,76 @@ __global__ void __launch_bounds__(256) k_tm_low(TmParams P, const double* __rest
     for (int e = tid; e < chunk; e += 256) out[base + e] = last ? sh[e] * half_diag(P, base + e, dt) : sh[e];
 }
 
-// In place: butterflies of bits bit0 .. bit0+nb-1.  A block takes kCols
-// consecutive low indices (below bit0) and every value of the nb bits, for
-// one value of the bits above.
-__global__ void __launch_bounds__(256) k_tm_mid(TmParams P, double* __restrict__ v, int bit0, int nb,
-                                                int last) {
-    __shared__ double sh[(1 << kMidBits) * kCols];
+// One pass over tiles of 4096 states: rows g = the nb bits bit0 .. bit0+nb-1
+// of the index, columns c = C = 4096 / 2^nb consecutive indices below bit0
+// (C = 1 in the first pass), one tile per value of the bits above.  Each
+// thread holds 16 states whose row indices differ in four bits and applies
+// those four butterflies in registers; LDS exchanges the states between
+// groups of four bits (bits left over when nb is not a multiple of 4 take one
+// LDS round trip each).  Optional D^1/2 scale on the way in and on the way
+// out; in and out may be the same vector (each tile is read whole first).
+__global__ void __launch_bounds__(256) k_tm_tile(TmParams P, const double* in, double* out, int bit0, int nb,
+                                                 int first, int last) {
+    __shared__ double sh[4096 + 4096 / 32];
     __shared__ double dt[4 * kMaxN + 1];
     const int tid = threadIdx.x;
-    const int ng = 1 << nb;
-    const uint32_t nlo = 1u << bit0;
-    const uint32_t lo0 = (blockIdx.x % (nlo / kCols)) * kCols;
-    const uint32_t hi = blockIdx.x / (nlo / kCols);
+    const int C = 4096 >> nb;
+    const int nlo = 1 << bit0;                 // indices below bit0
+    const uint32_t tiles_lo = (uint32_t)(nlo / C);
+    const uint32_t lo0 = (blockIdx.x % tiles_lo) * (uint32_t)C;
+    const uint32_t hi = blockIdx.x / tiles_lo;
     const uint32_t base = lo0 + (hi << (bit0 + nb));
+    auto pad = [](int e) { return e + (e >> 5); };  // one spare slot per 32 doubles
+    auto gidx = [&](int e) -> uint32_t { return base + (uint32_t)(e % C) + ((uint32_t)(e / C) << bit0); };
     for (int e = tid; e < 4 * P.N + 1; e += 256) dt[e] = P.dtab[e];
-    for (int e = tid; e < ng * kCols; e += 256) {
-        const int g = e / kCols, c = e % kCols;
-        sh[e] = v[base + c + ((uint32_t)g << bit0)];
+    if (first) __syncthreads();
+    double r[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int e = tid + 256 * i;
+        const uint32_t s = gidx(e);
+        r[i] = first ? in[s] * half_diag(P, s, dt) : in[s];
     }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) sh[pad(tid + 256 * i)] = r[i];
     __syncthreads();
-    for (int j = 0; j < nb; ++j) {
-        for (int p = tid; p < (ng / 2) * kCols; p += 256) {
-            const int c = p % kCols, q = p / kCols;
-            const int g0 = ((q >> j) << (j + 1)) | (q & ((1 << j) - 1));
-            const int i0 = g0 * kCols + c, i1 = (g0 | (1 << j)) * kCols + c;
+    int b0 = nb;
+    while (b0 >= 4) {  // groups of four row bits, from the top
+        b0 -= 4;
+        const int o = tid / C, c = tid % C;
+        const int g0 = ((o >> b0) << (b0 + 4)) | (o & ((1 << b0) - 1));
+#pragma unroll
+        for (int i = 0; i < 16; ++i) r[i] = sh[pad((g0 | (i << b0)) * C + c)];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                if (!(i & (1 << j))) {
+                    const double x0 = r[i], x1 = r[i | (1 << j)];
+                    r[i] = P.a * x0 + P.b * x1;
+                    r[i | (1 << j)] = P.b * x0 + P.a * x1;
+                }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) sh[pad((g0 | (i << b0)) * C + c)] = r[i];
+        __syncthreads();
+    }
+    for (int j = 0; j < b0; ++j) {  // leftover row bits 0 .. b0-1
+        for (int q = tid; q < 2048; q += 256) {
+            const int c = q % C, gq = q / C;
+            const int g = ((gq >> j) << (j + 1)) | (gq & ((1 << j) - 1));
+            const int i0 = pad(g * C + c), i1 = pad((g | (1 << j)) * C + c);
             const double x0 = sh[i0], x1 = sh[i1];
             sh[i0] = P.a * x0 + P.b * x1;
             sh[i1] = P.b * x0 + P.a * x1;
         }
         __syncthreads();
     }
-    for (int e = tid; e < ng * kCols; e += 256) {
-        const int g = e / kCols, c = e % kCols;
-        const uint32_t s = base + c + ((uint32_t)g << bit0);
-        v[s] = last ? sh[e] * half_diag(P, s, dt) : sh[e];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int e = tid + 256 * i;
+        const uint32_t s = gidx(e);
+        const double x = sh[pad(e)];
+        out[s] = last ? x * half_diag(P, s, dt) : x;
     }
 }
 
@@ -123,7 +161,7 @@ __global__ void k_tm_project(double* __restrict__ w, uint32_t n, double sign) {
 }
 
 // Per-block partial sums of <x, y> and <y, y> (summed on the host in block order).
-constexpr int kDotBlocks = 256;
+constexpr int kDotBlocks = 1024;
 __global__ void __launch_bounds__(256) k_tm_dots(const double* __restrict__ x, const double* __restrict__ y,
                                                  uint32_t n, double* __restrict__ part) {
     __shared__ double r0[256], r1[256];
@@ -190,17 +228,26 @@ static TmParams tm_params(int L, double k, const int8_t* Jx, const int8_t* Jy) {
 }
 
 static hipError_t tm_apply_params(const TmParams& P, const double* v, double* w, hipStream_t st) {
-    const int nlow = std::min(P.N, kLowBits);
     const uint32_t n = 1u << P.N;
-    hipLaunchKernelGGL(k_tm_low, dim3(n >> nlow), dim3(256), 0, st, P, v, w, nlow, (int)(P.N == nlow));
-    hipError_t e = hipGetLastError();
-    for (int bit0 = nlow; e == hipSuccess && bit0 < P.N; bit0 += kMidBits) {
-        const int nb = std::min(kMidBits, P.N - bit0);
-        const uint32_t blocks = ((1u << bit0) / kCols) << (P.N - bit0 - nb);
-        hipLaunchKernelGGL(k_tm_mid, dim3(blocks), dim3(256), 0, st, P, w, bit0, nb, (int)(bit0 + nb == P.N));
-        e = hipGetLastError();
+    if (P.N >= kLowBits + 4) {
+        // tiles of 4096 states: 12 bits, then passes of 8 bits (rows) x 16
+        // columns, the last pass taking what is left (at least 4 bits)
+        hipError_t e = hipSuccess;
+        int bit0 = 0;
+        while (e == hipSuccess && bit0 < P.N) {
+            int nb = bit0 == 0 ? kLowBits : std::min(kMidBits, P.N - bit0);
+            if (bit0 > 0 && P.N - bit0 - nb > 0 && P.N - bit0 - nb < 4) nb = P.N - bit0 - 4;  // keep >= 4 for the last
+            const uint32_t blocks = n / 4096;
+            hipLaunchKernelGGL(k_tm_tile, dim3(blocks), dim3(256), 0, st, P, bit0 == 0 ? v : (const double*)w, w,
+                               bit0, nb, (int)(bit0 == 0), (int)(bit0 + nb == P.N));
+            e = hipGetLastError();
+            bit0 += nb;
+        }
+        return e;
     }
-    return e;
+    if (P.N > kLowBits) return hipErrorInvalidValue;  // N = L^2 is 4, 9, 16 or 25
+    hipLaunchKernelGGL(k_tm_low, dim3(n >> P.N), dim3(256), 0, st, P, v, w, P.N, 1);
+    return hipGetLastError();
 }
 
 hipError_t tm_apply(int L, double k, const int8_t* Jx, const int8_t* Jy, const double* v, double* w,
@@ -216,7 +263,7 @@ hipError_t tm_top(int L, double k, const int8_t* Jx, const int8_t* Jy, int odd, 
     double* w = v + n;
     double* part = w + n;
     const double sign = odd ? -1.0 : 1.0;
-    const int grid = (int)std::min<uint32_t>(1024, (n + 255) / 256);
+    const int grid = (int)std::min<uint32_t>(8192, (n + 255) / 256);
     std::vector<double> hp(2 * kDotBlocks);
     hipLaunchKernelGGL(k_tm_start, dim3(grid), dim3(256), 0, st, v, n, sign);
     hipError_t e = hipGetLastError();

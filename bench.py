@@ -282,15 +282,18 @@ def transfer_leg(torch, args):
     lam = []
     for sector in (0, 1):
         t0 = time.time()
-        lv, it = tfim.tm_top(L, k, Jx, Jy, sector, tol=1e-13, max_iter=100000)
+        lv, it = tfim.tm_top(L, k, Jx, Jy, sector, n_eig=2, tol=1e-13, max_iter=100000)
         lam.append({"sector": "even" if sector == 0 else "odd", "lambda": lv, "products": it,
                     "seconds": round(time.time() - t0, 3)})
-    split = (math.log(lam[0]["lambda"]) - math.log(lam[1]["lambda"])) / k
+    # eigenvalues e^(k E): energies E = ln(lambda)/k, gaps in units of the action
+    E = {(s["sector"], q): math.log(s["lambda"][q]) / k for s in lam for q in (0, 1)}
     return {
         "L": L, "k": k, "states": n, "product_ms": round(ms, 4),
         "algorithmic_bytes_per_product": alg, "bytes_moved_per_product": moved,
         "algorithmic_gbs": round(gbs, 1), "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
-        "top_eigenvalues": lam, "sector_splitting_E0odd_minus_E0even": round(split, 9),
+        "top_eigenvalues": lam,
+        "E0even_minus_E0odd": round(E[("even", 0)] - E[("odd", 0)], 9),
+        "E0even_minus_E1even": round(E[("even", 0)] - E[("even", 1)], 9),
     }
 
 

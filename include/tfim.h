@@ -250,19 +250,22 @@ tfim_status tfim_binder(const int64_t *rec, uint32_t L, uint32_t Ltau, uint32_t 
  * paper's exp(-k/2 H0) exp(-k H1) exp(-k/2 H0) up to a constant factor.
  * tfim_tm_apply: w = T v for device vectors of 2^(L^2) doubles (distinct),
  *   asynchronous on hip_stream.
- * tfim_tm_top: largest eigenvalue of the even (sector 0, P = +1) or odd
- *   (sector 1) sector by power iteration from a fixed start vector, until
- *   two successive Rayleigh quotients differ by at most tol relative or
- *   max_iter products; the normalised eigenvector is left at the start of
- *   ws (2^(L^2) doubles).  ws: caller-owned device memory of at least
- *   tfim_tm_workspace bytes, 256-byte aligned.  Synchronous.  Returns the
- *   eigenvalue and the number of products used. */
+ * tfim_tm_top: the n_eig (1 or 2) largest eigenvalues of the even (sector
+ *   0, P = +1) or odd (sector 1) sector, e^(k E_0) and e^(k E_1) of that
+ *   sector, by power iteration from fixed start vectors (the second with
+ *   the first eigenvector removed from every product), each until two
+ *   successive Rayleigh quotients differ by at most tol relative or max_iter
+ *   products; the normalised eigenvectors are left at the start of ws
+ *   (2^(L^2) doubles each).  ws: caller-owned device memory of at least
+ *   tfim_tm_workspace bytes, 256-byte aligned.  Synchronous.  lambda_out
+ *   and iters_out (may be NULL) take n_eig values. */
 tfim_status tfim_tm_workspace(uint32_t L, size_t *bytes_out);
 tfim_status tfim_tm_apply(uint32_t L, double k, const int8_t *Jx, const int8_t *Jy,
                           const double *v, double *w, void *hip_stream);
 tfim_status tfim_tm_top(uint32_t L, double k, const int8_t *Jx, const int8_t *Jy, uint32_t sector,
-                        double tol, uint32_t max_iter, void *workspace, size_t workspace_bytes,
-                        void *hip_stream, double *lambda_out, uint32_t *iters_out);
+                        uint32_t n_eig, double tol, uint32_t max_iter, void *workspace,
+                        size_t workspace_bytes, void *hip_stream, double *lambda_out,
+                        uint32_t *iters_out);
 
 /* Threshold tables of a shape (host-only): Tm[n_k][3] with
  * Tm[i][u] = floor(2^32 exp(-k_i (12 - 4u))) for u = 0,1,2 unsatisfied

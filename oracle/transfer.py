@@ -73,26 +73,29 @@ def flip(v: np.ndarray) -> np.ndarray:
     return np.asarray(v)[::-1].copy()
 
 
-def top_eigenvalues(L: int, k: float, Jx, Jy):
-    """(largest eigenvalue in the even sector P = +1, largest in the odd
-    sector P = -1) from a dense symmetric eigensolver (L <= 3)."""
+def top_eigenvalues(L: int, k: float, Jx, Jy, n_eig: int = 1):
+    """Largest eigenvalues of the even sector P = +1 and of the odd sector
+    P = -1 from a dense symmetric eigensolver (L <= 3): (even, odd), each a
+    float (n_eig = 1) or the n_eig largest in decreasing order."""
     T = dense(L, k, Jx, Jy)
     n = T.shape[0]
-    I = np.eye(n)
-    Pm = I[::-1]
+    s = np.arange(n)
     out = []
     for sign in (1.0, -1.0):
-        Q = 0.5 * (I + sign * Pm)                 # projector onto the sector
-        B = np.linalg.qr(Q)[0][:, : n // 2]       # orthonormal basis of the sector
-        ev = np.linalg.eigvalsh(B.T @ T @ B)
-        out.append(float(ev[-1]))
+        # orthonormal basis of the sector: (e_s + sign e_~s)/sqrt(2), s < n/2
+        B = np.zeros((n, n // 2))
+        B[s[: n // 2], np.arange(n // 2)] = 1.0 / np.sqrt(2.0)
+        B[n - 1 - s[: n // 2], np.arange(n // 2)] = sign / np.sqrt(2.0)
+        ev = np.linalg.eigvalsh(B.T @ T @ B)[::-1]
+        out.append(float(ev[0]) if n_eig == 1 else [float(x) for x in ev[:n_eig]])
     return tuple(out)
 
 
-def top_eigenvalues_mf(L: int, k: float, Jx, Jy, tol: float = 1e-13):
-    """Matrix-free form of `top_eigenvalues` (L <= 4): the largest eigenvalue
-    of P_+- T P_+- with P_+- = (1 +- P)/2, from scipy's Lanczos solver (eigsh)
-    on the matrix-free apply."""
+def top_eigenvalues_mf(L: int, k: float, Jx, Jy, tol: float = 1e-13, n_eig: int = 1):
+    """Matrix-free form of `top_eigenvalues` (L <= 4): the largest
+    eigenvalues of P_+- T P_+- with P_+- = (1 +- P)/2 (the other sector
+    contributes zeros), from scipy's Lanczos solver (eigsh) on the
+    matrix-free apply."""
     from scipy.sparse.linalg import LinearOperator, eigsh
     n = 1 << (L * L)
     out = []
@@ -104,6 +107,6 @@ def top_eigenvalues_mf(L: int, k: float, Jx, Jy, tol: float = 1e-13):
             return 0.5 * (w + sign * flip(w))
         op = LinearOperator((n, n), matvec=mv, dtype=np.float64)
         v0 = np.ones(n) if sign > 0 else np.where(np.arange(n) < n // 2, 1.0, -1.0)
-        ev = eigsh(op, k=1, which="LA", v0=v0, tol=tol, return_eigenvectors=False)
-        out.append(float(ev[-1]))
+        ev = np.sort(eigsh(op, k=n_eig, which="LA", v0=v0, tol=tol, return_eigenvectors=False))[::-1]
+        out.append(float(ev[0]) if n_eig == 1 else [float(x) for x in ev[:n_eig]])
     return tuple(out)

@@ -955,19 +955,25 @@ tfim_status tfim_tm_apply(uint32_t L, double k, const int8_t* Jx, const int8_t* 
 }
 
 tfim_status tfim_tm_top(uint32_t L, double k, const int8_t* Jx, const int8_t* Jy, uint32_t sector,
-                        double tol, uint32_t max_iter, void* ws, size_t ws_bytes, void* hip_stream,
-                        double* lambda_out, uint32_t* iters_out) {
+                        uint32_t n_eig, double tol, uint32_t max_iter, void* ws, size_t ws_bytes,
+                        void* hip_stream, double* lambda_out, uint32_t* iters_out) {
     tfim_status st = tm_args(L, k, Jx, Jy);
     if (st != TFIM_OK) return st;
     if (sector > 1) return fail(TFIM_EINVAL, "sector must be 0 (even) or 1 (odd)");
+    if (n_eig < 1 || n_eig > 2) return fail(TFIM_EINVAL, "n_eig must be 1 or 2");
     if (!(tol > 0.0) || max_iter == 0 || !lambda_out) return fail(TFIM_EINVAL, "bad iteration arguments");
     if (!ws || ((uintptr_t)ws & 255)) return fail(TFIM_EINVAL, "workspace must be 256-byte aligned");
     if (ws_bytes < tfim::tm_workspace_bytes((int)L)) return fail(TFIM_EINVAL, "workspace too small");
-    int it = 0;
-    const hipError_t e = tfim::tm_top((int)L, k, Jx, Jy, (int)sector, tol, (int)std::min<uint32_t>(max_iter, 1u << 30),
-                                      ws, lambda_out, &it, (hipStream_t)hip_stream);
+    double lam[2] = {0.0, 0.0};
+    int it[2] = {0, 0};
+    const hipError_t e = tfim::tm_top((int)L, k, Jx, Jy, (int)sector, (int)n_eig, tol,
+                                      (int)std::min<uint32_t>(max_iter, 1u << 30), ws, lam, it,
+                                      (hipStream_t)hip_stream);
     if (e != hipSuccess) return fail(TFIM_EDEVICE, std::string("transfer matrix: ") + hipGetErrorString(e));
-    if (iters_out) *iters_out = (uint32_t)it;
+    for (uint32_t q = 0; q < n_eig; ++q) {
+        lambda_out[q] = lam[q];
+        if (iters_out) iters_out[q] = (uint32_t)it[q];
+    }
     return TFIM_OK;
 }
 

@@ -202,14 +202,15 @@ const char* timecorr_unsupported(const ShapeDev& sh);  // nullptr if supported
 size_t timecorr_record_bytes(const ShapeDev& sh, int ncfg);
 hipError_t launch_timecorr(const ShapeDev& sh, int cfg0, int ncfg, int64_t* rec, hipStream_t st);
 // Transfer matrix of one plane (2 <= L <= 5): w = T v on 2^(L^2) doubles,
-// and the largest eigenvalue of the even (odd = 0) or odd parity sector by
-// power iteration in a workspace of two vectors and reduction partials.
+// and the nev = 1 or 2 largest eigenvalues of the even (odd = 0) or odd
+// parity sector by power iteration (the second with the first eigenvector
+// deflated) in a workspace of three vectors and reduction partials.
 const char* tm_unsupported(int L);  // nullptr if supported
 size_t tm_workspace_bytes(int L);
 hipError_t tm_apply(int L, double k, const int8_t* Jx, const int8_t* Jy, const double* v, double* w,
                     hipStream_t st);
-hipError_t tm_top(int L, double k, const int8_t* Jx, const int8_t* Jy, int odd, double tol, int max_iter,
-                  void* ws, double* lambda, int* iters, hipStream_t st);
+hipError_t tm_top(int L, double k, const int8_t* Jx, const int8_t* Jy, int odd, int nev, double tol,
+                  int max_iter, void* ws, double* lambda, int* iters, hipStream_t st);
 int sweep_variants();
 const char* sweep_variant_name(int v);
 }  // namespace tfim

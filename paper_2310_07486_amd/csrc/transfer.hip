@@ -160,40 +160,60 @@ __global__ void k_tm_project(double* __restrict__ w, uint32_t n, double sign) {
     }
 }
 
-// Per-block partial sums of <x, y> and <y, y> (summed on the host in block order).
+// Per-block partial sums of <x, y>, <y, y> and, when z is given, <z, y>
+// (summed on the host in block order).
 constexpr int kDotBlocks = 1024;
 __global__ void __launch_bounds__(256) k_tm_dots(const double* __restrict__ x, const double* __restrict__ y,
-                                                 uint32_t n, double* __restrict__ part) {
-    __shared__ double r0[256], r1[256];
-    double a = 0.0, c = 0.0;
+                                                 const double* __restrict__ z, uint32_t n,
+                                                 double* __restrict__ part) {
+    __shared__ double r0[256], r1[256], r2[256];
+    double a = 0.0, c = 0.0, d = 0.0;
     for (uint32_t s = blockIdx.x * 256 + threadIdx.x; s < n; s += kDotBlocks * 256) {
-        a += x[s] * y[s];
-        c += y[s] * y[s];
+        const double ys = y[s];
+        a += x[s] * ys;
+        c += ys * ys;
+        if (z) d += z[s] * ys;
     }
     r0[threadIdx.x] = a;
     r1[threadIdx.x] = c;
+    r2[threadIdx.x] = d;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
         if ((int)threadIdx.x < o) {
             r0[threadIdx.x] += r0[threadIdx.x + o];
             r1[threadIdx.x] += r1[threadIdx.x + o];
+            r2[threadIdx.x] += r2[threadIdx.x + o];
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
         part[blockIdx.x] = r0[0];
         part[kDotBlocks + blockIdx.x] = r1[0];
+        part[2 * kDotBlocks + blockIdx.x] = r2[0];
     }
 }
 
-__global__ void k_tm_scale(const double* __restrict__ x, double* __restrict__ y, uint32_t n, double f) {
-    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += gridDim.x * blockDim.x) y[s] = x[s] * f;
+// v = (w - c z) f  (z may be null: v = w f); v may be w
+__global__ void k_tm_next(const double* w, const double* __restrict__ z, double c, double f, uint32_t n,
+                          double* v) {
+    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += gridDim.x * blockDim.x)
+        v[s] = (z ? w[s] - c * z[s] : w[s]) * f;
 }
 
-__global__ void k_tm_start(double* __restrict__ v, uint32_t n, double sign) {
-    // the even sector starts from all ones, the odd one from +1 / -1 halves
-    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += gridDim.x * blockDim.x)
-        v[s] = (sign > 0.0 || s < n / 2) ? 1.0 : -1.0;
+__global__ void k_tm_start(double* __restrict__ v, uint32_t n, double sign, int second) {
+    // the top: all ones (even sector) or +1 / -1 halves (odd sector); the
+    // second: a fixed pseudo-random vector, projected on the sector below
+    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += gridDim.x * blockDim.x) {
+        if (second) {
+            uint32_t h = s * 0x9E3779B1u;
+            h ^= h >> 15;
+            h *= 0x85EBCA77u;
+            h ^= h >> 13;
+            v[s] = (double)(h & 0xFFFFu) / 32768.0 - 1.0;
+        } else {
+            v[s] = (sign > 0.0 || s < n / 2) ? 1.0 : -1.0;
+        }
+    }
 }
 
 }  // namespace
@@ -205,7 +225,7 @@ const char* tm_unsupported(int L) {
 
 size_t tm_workspace_bytes(int L) {
     const size_t n = (size_t)1 << (L * L);
-    return 2 * n * 8 + 2 * kDotBlocks * 8 + 256;
+    return 3 * n * 8 + 3 * kDotBlocks * 8 + 256;
 }
 
 static TmParams tm_params(int L, double k, const int8_t* Jx, const int8_t* Jy) {
@@ -255,44 +275,44 @@ hipError_t tm_apply(int L, double k, const int8_t* Jx, const int8_t* Jy, const d
     return tm_apply_params(tm_params(L, k, Jx, Jy), v, w, st);
 }
 
-hipError_t tm_top(int L, double k, const int8_t* Jx, const int8_t* Jy, int odd, double tol, int max_iter,
-                  void* ws, double* lambda, int* iters, hipStream_t st) {
-    const TmParams P = tm_params(L, k, Jx, Jy);
+// Power iteration in one parity sector; with defl, every product has the
+// component along the unit vector defl removed (the second eigenvalue).
+static hipError_t tm_power(const TmParams& P, double sign, double tol, int max_iter, double* v, double* w,
+                           const double* defl, double* part, std::vector<double>& hp, double* lambda,
+                           int* iters, hipStream_t st) {
     const uint32_t n = 1u << P.N;
-    double* v = (double*)ws;
-    double* w = v + n;
-    double* part = w + n;
-    const double sign = odd ? -1.0 : 1.0;
     const int grid = (int)std::min<uint32_t>(8192, (n + 255) / 256);
-    std::vector<double> hp(2 * kDotBlocks);
-    hipLaunchKernelGGL(k_tm_start, dim3(grid), dim3(256), 0, st, v, n, sign);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess) {  // normalise the start vector
-        hipLaunchKernelGGL(k_tm_dots, dim3(kDotBlocks), dim3(256), 0, st, v, v, n, part);
-        e = hipMemcpyAsync(hp.data(), part, hp.size() * 8, hipMemcpyDeviceToHost, st);
+    auto sums = [&](const double* x, const double* y, const double* z, double out[3]) -> hipError_t {
+        hipLaunchKernelGGL(k_tm_dots, dim3(kDotBlocks), dim3(256), 0, st, x, y, z, n, part);
+        hipError_t e = hipMemcpyAsync(hp.data(), part, hp.size() * 8, hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
-        double nn = 0.0;
-        for (int i = 0; i < kDotBlocks; ++i) nn += hp[kDotBlocks + i];
-        if (e == hipSuccess) hipLaunchKernelGGL(k_tm_scale, dim3(grid), dim3(256), 0, st, v, v, n, 1.0 / std::sqrt(nn));
+        out[0] = out[1] = out[2] = 0.0;
+        for (int q = 0; q < 3; ++q)
+            for (int i = 0; i < kDotBlocks; ++i) out[q] += hp[q * kDotBlocks + i];
+        return e;
+    };
+    hipLaunchKernelGGL(k_tm_start, dim3(grid), dim3(256), 0, st, v, n, sign, defl ? 1 : 0);
+    hipLaunchKernelGGL(k_tm_project, dim3(grid), dim3(256), 0, st, v, n, sign);
+    double d[3];
+    hipError_t e = sums(v, v, defl, d);  // |v|^2 and <defl, v>
+    if (e != hipSuccess) return e;
+    {
+        const double c = defl ? d[2] : 0.0;
+        const double nn = d[1] - c * c;
+        hipLaunchKernelGGL(k_tm_next, dim3(grid), dim3(256), 0, st, v, defl, c, 1.0 / std::sqrt(nn), n, v);
     }
     double lam = 0.0, prev = 0.0;
     int it = 0;
-    for (; e == hipSuccess && it < max_iter; ++it) {
+    for (; it < max_iter; ++it) {
         e = tm_apply_params(P, v, w, st);
         if (e != hipSuccess) break;
         hipLaunchKernelGGL(k_tm_project, dim3(grid), dim3(256), 0, st, w, n, sign);
-        hipLaunchKernelGGL(k_tm_dots, dim3(kDotBlocks), dim3(256), 0, st, v, w, n, part);
-        e = hipMemcpyAsync(hp.data(), part, hp.size() * 8, hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e != hipSuccess) break;
-        double vw = 0.0, ww = 0.0;
-        for (int i = 0; i < kDotBlocks; ++i) {
-            vw += hp[i];
-            ww += hp[kDotBlocks + i];
-        }
+        if ((e = sums(v, w, defl, d)) != hipSuccess) break;
         prev = lam;
-        lam = vw;  // Rayleigh quotient: v has unit norm
-        hipLaunchKernelGGL(k_tm_scale, dim3(grid), dim3(256), 0, st, w, v, n, 1.0 / std::sqrt(ww));
+        lam = d[0];  // Rayleigh quotient: v is a unit vector orthogonal to defl
+        const double c = defl ? d[2] : 0.0;
+        hipLaunchKernelGGL(k_tm_next, dim3(grid), dim3(256), 0, st, w, defl, c,
+                           1.0 / std::sqrt(d[1] - c * c), n, v);
         if (it >= 2 && std::fabs(lam - prev) <= tol * std::fabs(lam)) {
             ++it;
             break;
@@ -302,6 +322,22 @@ hipError_t tm_top(int L, double k, const int8_t* Jx, const int8_t* Jy, int odd, 
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     *lambda = lam;
     *iters = it;
+    return e;
+}
+
+hipError_t tm_top(int L, double k, const int8_t* Jx, const int8_t* Jy, int odd, int nev, double tol,
+                  int max_iter, void* ws, double* lambda, int* iters, hipStream_t st) {
+    const TmParams P = tm_params(L, k, Jx, Jy);
+    const uint32_t n = 1u << P.N;
+    double* v0 = (double*)ws;   // the sector's top eigenvector
+    double* v1 = v0 + n;        // the second
+    double* w = v1 + n;
+    double* part = w + n;
+    const double sign = odd ? -1.0 : 1.0;
+    std::vector<double> hp(3 * kDotBlocks);
+    hipError_t e = tm_power(P, sign, tol, max_iter, v0, w, nullptr, part, hp, &lambda[0], &iters[0], st);
+    if (e == hipSuccess && nev > 1)
+        e = tm_power(P, sign, tol, max_iter, v1, w, v0, part, hp, &lambda[1], &iters[1], st);
     return e;
 }
 

@@ -127,7 +127,7 @@ def lib():
             "tfim_measure_time": [P, U32, U32, U32, U32, P, SZ, P, SZ],
             "tfim_tm_workspace": [U32, P],
             "tfim_tm_apply": [U32, ctypes.c_double, P, P, P, P, P],
-            "tfim_tm_top": [U32, ctypes.c_double, P, P, U32, ctypes.c_double, U32, P, SZ, P, P, P],
+            "tfim_tm_top": [U32, ctypes.c_double, P, P, U32, U32, ctypes.c_double, U32, P, SZ, P, P, P],
             "tfim_strerror": [ctypes.c_int32],
             "tfim_last_error_detail": [],
         }
@@ -196,25 +196,27 @@ def tm_apply(L: int, k: float, Jx, Jy, v, w, stream=None):
                                ctypes.c_void_p(w.data_ptr()), _stream_ptr(stream)), "tfim_tm_apply")
 
 
-def tm_top(L: int, k: float, Jx, Jy, sector: int, tol: float = 1e-13, max_iter: int = 100000,
-           stream=None, return_vector: bool = False):
-    """Largest eigenvalue of the even (0) or odd (1) parity sector of the
-    transfer matrix, by power iteration on the device: (lambda, products)."""
+def tm_top(L: int, k: float, Jx, Jy, sector: int, n_eig: int = 1, tol: float = 1e-13,
+           max_iter: int = 100000, stream=None, return_vectors: bool = False):
+    """The n_eig (1 or 2) largest eigenvalues of the even (0) or odd (1)
+    parity sector of the transfer matrix, by power iteration on the device:
+    (eigenvalues, products used), lists of n_eig."""
     import torch
     Jx = np.ascontiguousarray(Jx, dtype=np.int8)
     Jy = np.ascontiguousarray(Jy, dtype=np.int8)
     n = ctypes.c_size_t(0)
     _check(lib().tfim_tm_workspace(L, ctypes.byref(n)), "tfim_tm_workspace")
     ws = torch.empty(n.value, dtype=torch.uint8, device="cuda")
-    lam = ctypes.c_double(0.0)
-    it = ctypes.c_uint32(0)
-    _check(lib().tfim_tm_top(L, float(k), _ptr(Jx), _ptr(Jy), sector, float(tol), max_iter,
-                             ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream),
-                             ctypes.byref(lam), ctypes.byref(it)), "tfim_tm_top")
-    if return_vector:
-        vec = ws[: 8 << (L * L)].view(torch.float64).cpu().numpy()
-        return lam.value, it.value, vec
-    return lam.value, it.value
+    lam = (ctypes.c_double * 2)()
+    it = (ctypes.c_uint32 * 2)()
+    _check(lib().tfim_tm_top(L, float(k), _ptr(Jx), _ptr(Jy), sector, n_eig, float(tol), max_iter,
+                             ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream), lam, it),
+           "tfim_tm_top")
+    out = ([lam[q] for q in range(n_eig)], [it[q] for q in range(n_eig)])
+    if return_vectors:
+        vecs = ws[: n_eig * (8 << (L * L))].view(torch.float64).reshape(n_eig, -1).cpu().numpy()
+        return out + (vecs,)
+    return out
 
 
 class Plan:

@@ -84,14 +84,17 @@ def test_product_at_L5_sampled_entries_and_symmetry():
 
 @pytest.mark.parametrize("L", [2, 3, 4])
 def test_top_eigenvalues_match_oracle(L):
+    """The two largest eigenvalues of each sector (e^(k E_0), e^(k E_1))."""
     rng = np.random.default_rng(40 + L)
     Jx, Jy = _J(rng, L)
     _say(f"transfer eigenvalues L={L}")
     for k in (0.25, 0.31):
-        want = otm.top_eigenvalues(L, k, Jx, Jy) if L <= 3 else otm.top_eigenvalues_mf(L, k, Jx, Jy)
+        want = (otm.top_eigenvalues(L, k, Jx, Jy, n_eig=2) if L <= 3
+                else otm.top_eigenvalues_mf(L, k, Jx, Jy, n_eig=2))
         for sector in (0, 1):
-            lam, it = tfim.tm_top(L, k, Jx, Jy, sector, tol=1e-14, max_iter=200000)
-            assert lam == pytest.approx(want[sector], rel=1e-10), (L, k, sector, lam, want, it)
+            lam, it = tfim.tm_top(L, k, Jx, Jy, sector, n_eig=2, tol=1e-14, max_iter=200000)
+            assert lam[0] == pytest.approx(want[sector][0], rel=1e-10), (L, k, sector, lam, want, it)
+            assert lam[1] == pytest.approx(want[sector][1], rel=1e-8), (L, k, sector, lam, want, it)
 
 
 def test_transfer_argument_errors():

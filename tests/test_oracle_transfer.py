@@ -90,3 +90,24 @@ def test_matrix_free_top_eigenvalues_equal_dense():
         le, lo = tm.top_eigenvalues(L, k, Jx, Jy)
         me, mo = tm.top_eigenvalues_mf(L, k, Jx, Jy)
         assert me == pytest.approx(le, rel=1e-11) and mo == pytest.approx(lo, rel=1e-11)
+
+
+def test_sector_bases_and_second_eigenvalues():
+    """The two largest eigenvalues of both sectors, from the sector bases,
+    are the four largest of T (sorted), and the matrix-free Lanczos solver
+    finds the same pairs."""
+    rng = np.random.default_rng(17)
+    L = 3
+    Jx, Jy = _J(rng, L)
+    for k in (0.25, 0.4):
+        (e0, e1), (o0, o1) = tm.top_eigenvalues(L, k, Jx, Jy, n_eig=2)
+        ev = np.sort(np.linalg.eigvalsh(tm.dense(L, k, Jx, Jy)))[::-1]
+        top4 = np.sort([e0, e1, o0, o1])[::-1]
+        full = np.sort(np.concatenate([np.linalg.eigvalsh(tm.dense(L, k, Jx, Jy))]))[::-1]
+        # each sector's pair is in the spectrum; the overall top is the larger sector top
+        for x in (e0, e1, o0, o1):
+            assert np.min(np.abs(full - x)) <= 1e-9 * abs(x)
+        assert max(e0, o0) == pytest.approx(ev[0], rel=1e-12)
+        assert e0 > e1 and o0 > o1
+        (me0, me1), (mo0, mo1) = tm.top_eigenvalues_mf(L, k, Jx, Jy, n_eig=2)
+        assert [me0, me1, mo0, mo1] == pytest.approx([e0, e1, o0, o1], rel=1e-10)

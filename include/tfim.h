@@ -138,7 +138,8 @@ tfim_status tfim_pt_swap(tfim_plan *plan);
  *   [D_x[0..L-1], D_y[0..L-1], trQ, sum Q^2, sum Q^4] where, for the
  *   configurations S^a, S^b (L^2 x Ltau, +-1) at k-index i,
  *   G = S S^T, D_x[d] = sum_{(x1-y1) mod L = d} G^a_xy G^b_xy,
- *   Q = S^aT S^b.  Needs n_replicas >= 2.
+ *   Q = S^aT S^b.  Needs 2..6 replicas and L <= 32 (else TFIM_EUNSUPPORTED;
+ *   the paper's runs use 6).
  * what = TFIM_MEASURE_BUCKETS: int64 A[n_k][2][L] = records' D_x and D_y
  *   summed over samples and pairs.
  * what = TFIM_MEASURE_ENERGY: u32 U[r][s][i] of the walker at k-index i.
@@ -187,7 +188,7 @@ tfim_status tfim_xi2(const int64_t *A, uint32_t L, uint32_t n_k, double *xi_out)
  * and sum_d T_x[d] cos(2 pi d/L) ~ Tr[M-hat M^2] (phase on the carrier,
  * averaged over the three choices).  Records are int64
  * [ncfg][n_triples][2L] = [T_x[0..L-1], T_y[0..L-1]], exact.
- * Needs 3 or 4 replicas, L <= 32, L^2 (Ltau/2)^2 < 2^31 and
+ * Needs 3 to 6 replicas, L <= 32, L^2 (Ltau/2)^2 < 2^31 and
  * 3 L^6 Ltau^3 < 2^63 (else TFIM_EUNSUPPORTED).
  * tfim_triples_workspace: bytes of device workspace for ncfg configurations
  *   (records, then int8 planes of G/2 for every replica; about
@@ -212,7 +213,7 @@ tfim_status tfim_measure_triples(tfim_plan *plan, uint32_t shape, uint32_t cfg0,
  * C(tau) = c[tau] / (R L^2 Ltau) and Q2(tau) = q2[tau] / (R L^4 Ltau)
  * (C(0) = Q2(0) = 1).  With bc_tau = TFIM_BC_ANTIPERIODIC the configuration
  * continues past Ltau with the opposite sign, so the terms of c with
- * t1 + d >= Ltau enter with the sign -1 (c[Ltau - d] = -c[d]).  Needs 1..4 replicas, L <= 32, Ltau <= 4096 (else
+ * t1 + d >= Ltau enter with the sign -1 (c[Ltau - d] = -c[d]).  Needs 1..6 replicas, L <= 32, Ltau <= 4096 (else
  * TFIM_EUNSUPPORTED).  ws: caller-owned device memory, 256-byte aligned, at
  * least ncfg*2*Ltau*8 bytes, holding the records afterwards.  flags as for
  * tfim_measure_range.  out == NULL: enqueue only (asynchronous); otherwise

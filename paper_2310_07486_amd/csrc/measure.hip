@@ -25,8 +25,9 @@
 // 2. k_gram_mfma: one workgroup per configuration at a time, 64x64 tiles of
 //    G (upper triangle of tile pairs), all replicas at once, bucket sums in
 //    LDS, flushed once per configuration.
-// 3. k_overlap_mfma: 64x64 tiles of every Q^ab, all pairs at once; per-lane
-//    int64 sums flushed once per configuration.
+// 3. k_overlap_mfma: 64x64 tiles of every Q^ab, all pairs at once for up to
+//    4 replicas (5 or 6: one launch per group of 5 pairs); per-lane int64
+//    sums flushed once per configuration.
 // The plain per-sample form (k_*_plain) computes one matrix element per
 // thread with an int32 multiply-accumulate loop over unpacked spins, one
 // launch per configuration: the reference point for the batched form.
@@ -41,7 +42,7 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
 constexpr int kRowPitch = 80;  // bytes per unpacked 64-element row in LDS (16-byte aligned)
-constexpr int kMaxR = 4;       // replicas handled by the MFMA kernels
+constexpr int kMaxR = 6;       // replicas handled by the MFMA kernels
 constexpr int kMaxP = kMaxR * (kMaxR - 1) / 2;
 
 constexpr int kTP = 65;  // padded row pitch (words) of the transpose tiles
@@ -218,30 +219,32 @@ __global__ void __launch_bounds__(256) k_gram_mfma(ShapeDev sh, int cfg0, int nc
 }
 
 // ---------------------------------------------------------------------------
-// Q tiles: trQ, sum Q^2, sum Q^4 for every pair.
+// Q tiles: trQ, sum Q^2, sum Q^4 for the pairs P0 .. P0 + NP - 1 (pairs a < b
+// in lexicographic order).  Up to 4 replicas one launch takes every pair;
+// with 5 or 6 one launch per group of 5 pairs keeps the accumulators of a
+// tile (16 per pair and lane) within the register budget.
 // ---------------------------------------------------------------------------
-template <int RR>
+template <int RR, int P0, int NP>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 k_overlap_mfma(ShapeDev sh, int cfg0, int ncfg) {
-    constexpr int PP = RR * (RR - 1) / 2;
     extern __shared__ __align__(16) uint8_t smem[];
     uint8_t* Al = smem;
     uint8_t* Bl = smem + RR * 64 * kRowPitch;
     int* mA = (int*)(Bl + RR * 64 * kRowPitch);
     int* mB = mA + RR * 64;
-    unsigned long long* red = (unsigned long long*)(mB + RR * 64);  // [PP][2]: trQ, sum Q^4
+    unsigned long long* red = (unsigned long long*)(mB + RR * 64);  // [NP][2]: trQ, sum Q^4
     const int L2 = sh.L2, Lt = sh.Lt;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int wx = wv & 1, wy = wv >> 1;
     const int ntt = (Lt + 63) / 64;
     constexpr int kRows = 2 * RR * 64;        // operand rows of one K chunk (A and B)
     constexpr int kPer = (kRows + 255) / 256;  // rows per thread
-    for (int e = tid; e < PP * 2; e += 256) red[e] = 0;
+    for (int e = tid; e < NP * 2; e += 256) red[e] = 0;
     for (int cfg = cfg0 + blockIdx.x; cfg < cfg0 + ncfg; cfg += gridDim.x) {
-        unsigned long long s4u[PP];
-        long long tr[PP];
+        unsigned long long s4u[NP];
+        long long tr[NP];
 #pragma unroll
-        for (int p = 0; p < PP; ++p) {
+        for (int p = 0; p < NP; ++p) {
             s4u[p] = 0;
             tr[p] = 0;
         }
@@ -266,9 +269,9 @@ k_overlap_mfma(ShapeDev sh, int cfg0, int ncfg) {
                     }
                 }
             };
-            v16i acc[PP];
+            v16i acc[NP];
 #pragma unroll
-            for (int p = 0; p < PP; ++p)
+            for (int p = 0; p < NP; ++p)
 #pragma unroll
                 for (int q = 0; q < 16; ++q) acc[p][q] = 0;
             uint64_t vn[kPer];
@@ -302,8 +305,9 @@ k_overlap_mfma(ShapeDev sh, int cfg0, int ncfg) {
                     for (int ra = 0; ra < RR; ++ra)
 #pragma unroll
                         for (int rb = ra + 1; rb < RR; ++rb, ++p)
-                            acc[p] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[ra], b[rb - 1], acc[p],
-                                                                           0, 0, 0);
+                            if (p >= P0 && p < P0 + NP)
+                                acc[p - P0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[ra], b[rb - 1],
+                                                                                    acc[p - P0], 0, 0, 0);
                 }
             }
             __syncthreads();
@@ -328,9 +332,10 @@ k_overlap_mfma(ShapeDev sh, int cfg0, int ncfg) {
                     for (int ra = 0; ra < RR; ++ra)
 #pragma unroll
                         for (int rb = ra + 1; rb < RR; ++rb, ++p) {
-                            const int qv = cr[ra] + cc[rb] + 4 * acc[p][q];
+                            if (p < P0 || p >= P0 + NP) continue;
+                            const int qv = cr[ra] + cc[rb] + 4 * acc[p - P0][q];
                             const uint32_t q2 = (uint32_t)(qv * qv);
-                            s4u[p] += (unsigned long long)q2 * q2;
+                            s4u[p - P0] += (unsigned long long)q2 * q2;
                         }
                 }
             } else {
@@ -347,17 +352,18 @@ k_overlap_mfma(ShapeDev sh, int cfg0, int ncfg) {
                     for (int ra = 0; ra < RR; ++ra)
 #pragma unroll
                         for (int rb = ra + 1; rb < RR; ++rb, ++p) {
-                            const int qv = cr[ra] + cc[rb] + 4 * acc[p][q];
+                            if (p < P0 || p >= P0 + NP) continue;
+                            const int qv = cr[ra] + cc[rb] + 4 * acc[p - P0][q];
                             const uint32_t q2 = (uint32_t)__mul24(qv, qv);
-                            s4u[p] += (unsigned long long)q2 * q2;
-                            if (diag && tau == tau2) tr[p] += qv;
+                            s4u[p - P0] += (unsigned long long)q2 * q2;
+                            if (diag && tau == tau2) tr[p - P0] += qv;
                         }
                 }
             }
         }
         // per-configuration flush: wave reduction, then one atomic per value
 #pragma unroll
-        for (int p = 0; p < PP; ++p) {
+        for (int p = 0; p < NP; ++p) {
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) {
                 s4u[p] += (unsigned long long)__shfl_xor((long long)s4u[p], off, 64);
@@ -366,7 +372,7 @@ k_overlap_mfma(ShapeDev sh, int cfg0, int ncfg) {
         }
         if (lane == 0) {
 #pragma unroll
-            for (int p = 0; p < PP; ++p) {
+            for (int p = 0; p < NP; ++p) {
                 atomicAdd(&red[p * 2 + 0], (unsigned long long)tr[p]);
                 atomicAdd(&red[p * 2 + 1], s4u[p]);
             }
@@ -375,9 +381,10 @@ k_overlap_mfma(ShapeDev sh, int cfg0, int ncfg) {
         // sum Q^2 = sum_xy G^a_xy G^b_xy = sum_d D_x[d]: the Gram kernel's
         // buckets of this configuration are complete (earlier launch)
         const int rl = 2 * sh.L + 3;
-        for (int e = tid; e < PP * 3; e += 256) {
+        constexpr int PP = RR * (RR - 1) / 2;
+        for (int e = tid; e < NP * 3; e += 256) {
             const int p = e / 3, k = e % 3;
-            int64_t* rp = sh.rec + ((size_t)cfg * PP + p) * rl;
+            int64_t* rp = sh.rec + ((size_t)cfg * PP + P0 + p) * rl;
             if (k == 1) {
                 int64_t q2 = 0;
                 for (int d = 0; d < sh.L; ++d) q2 += rp[d];
@@ -387,7 +394,7 @@ k_overlap_mfma(ShapeDev sh, int cfg0, int ncfg) {
             }
         }
         __syncthreads();
-        for (int e = tid; e < PP * 2; e += 256) red[e] = 0;
+        for (int e = tid; e < NP * 2; e += 256) red[e] = 0;
     }
 }
 
@@ -507,9 +514,21 @@ size_t gram_lds(int RR, int L) {
     const int PP = RR * (RR - 1) / 2;
     return (size_t)2 * RR * 64 * kRowPitch + (size_t)2 * RR * 64 * 4 + (size_t)PP * 2 * L * 8;
 }
-size_t overlap_lds(int RR) {
-    const int PP = RR * (RR - 1) / 2;
-    return (size_t)2 * RR * 64 * kRowPitch + (size_t)2 * RR * 64 * 4 + (size_t)PP * 3 * 8;
+size_t overlap_lds(int RR, int NP) {
+    return (size_t)2 * RR * 64 * kRowPitch + (size_t)2 * RR * 64 * 4 + (size_t)NP * 2 * 8;
+}
+
+// Pairs P0 .. PP - 1 of RR replicas in launches of at most NP pairs.
+template <int RR, int P0, int NP>
+hipError_t launch_overlap(const ShapeDev& sh, int cfg0, int ncfg, int grid, hipStream_t st) {
+    constexpr int PP = RR * (RR - 1) / 2;
+    constexpr int n = PP - P0 < NP ? PP - P0 : NP;
+    hipLaunchKernelGGL((k_overlap_mfma<RR, P0, n>), dim3(grid), dim3(256), overlap_lds(RR, n), st, sh, cfg0,
+                       ncfg);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if constexpr (P0 + n < PP) return launch_overlap<RR, P0 + n, NP>(sh, cfg0, ncfg, grid, st);
+    return hipSuccess;
 }
 
 template <int RR>
@@ -518,11 +537,18 @@ hipError_t launch_mfma(const ShapeDev& sh, int cfg0, int ncfg, hipStream_t st) {
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     const int grid = std::min(ncfg, 4 * ncu);
+    static bool lds_set = false;  // 6 replicas at L = 32 take above 64 KiB
+    if (!lds_set) {
+        const hipError_t e = hipFuncSetAttribute((const void*)k_gram_mfma<RR>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)gram_lds(RR, 32));
+        if (e != hipSuccess) return e;
+        lds_set = true;
+    }
     hipLaunchKernelGGL(k_gram_mfma<RR>, dim3(grid), dim3(256), gram_lds(RR, sh.L), st, sh, cfg0, ncfg);
-    hipError_t e = hipGetLastError();
+    const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_overlap_mfma<RR>, dim3(grid), dim3(256), overlap_lds(RR), st, sh, cfg0, ncfg);
-    return hipGetLastError();
+    return launch_overlap<RR, 0, (RR <= 4 ? RR * (RR - 1) / 2 : 5)>(sh, cfg0, ncfg, grid, st);
 }
 
 }  // namespace
@@ -552,6 +578,8 @@ hipError_t launch_measure(const ShapeDev& sh, int mode, int cfg0, int ncfg, hipS
             case 2: return launch_mfma<2>(sh, cfg0, ncfg, st);
             case 3: return launch_mfma<3>(sh, cfg0, ncfg, st);
             case 4: return launch_mfma<4>(sh, cfg0, ncfg, st);
+            case 5: return launch_mfma<5>(sh, cfg0, ncfg, st);
+            case 6: return launch_mfma<6>(sh, cfg0, ncfg, st);
             default: return hipErrorInvalidValue;
         }
     }

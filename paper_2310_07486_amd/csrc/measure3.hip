@@ -26,7 +26,9 @@
 //    each lane's 16 products into four x-buckets and four y-buckets of the
 //    triple {e, f, g}.  A work item is one output tile of one configuration
 //    with every replica pair unrolled, so these sums stay in registers
-//    across the pairs and reach the LDS buckets once per tile.  Records are
+//    across the pairs and reach the LDS buckets once per tile.  With 5 or 6
+//    replicas (10 or 20 triples) one launch per group of 2 triples forms the
+//    pair products that group needs.  Records are
 //    scaled by 8 at the flush (G = 2 G').  Work items are handed out so that
 //    the workgroups with the same blockIdx.x mod 8 (one XCD under round-robin
 //    dispatch) share one configuration at a time.
@@ -233,11 +235,21 @@ constexpr int triple_of(int R, int e, int f, int g) {  // index of the sorted tr
     return 0;
 }
 
-template <int RR>
+// Whether pair P has a carrier whose triple lies in [T0, T0 + NTG).
+constexpr bool pair_needed(int R, int P, int T0, int NTG) {
+    const int f = pair_f(R, P), g = pair_g(R, P);
+    for (int ci = 0; ci < R - 2; ++ci) {
+        const int t = triple_of(R, carrier_of(R, f, g, ci), f, g);
+        if (t >= T0 && t < T0 + NTG) return true;
+    }
+    return false;
+}
+
+// Accumulators of the triples T0 .. T0 + NTG - 1 over one output tile.
+template <int RR, int NTG>
 struct TriAcc {
-    static constexpr int NT = RR * (RR - 1) * (RR - 2) / 6;
-    long long tx[NT][4], ty[NT][4];  // x-buckets by j, y-buckets by g4
-    uint32_t cw[RR][2][4];           // G'^e digits at (x = column slot, y = row slots)
+    long long tx[NTG][4], ty[NTG][4];  // x-buckets by j, y-buckets by g4
+    uint32_t cw[RR][2][4];             // G'^e digits at (x = column slot, y = row slots)
 };
 
 struct TriGeom {
@@ -247,29 +259,35 @@ struct TriGeom {
     uint8_t* stg;
 };
 
-template <int RR, int C, int P>
+template <int RR, int T0, int NTG, int C, int P>
 struct CarrierStep {
-    static __device__ __forceinline__ void run(TriAcc<RR>& a, int q, int Pv) {
+    static __device__ __forceinline__ void run(TriAcc<RR, NTG>& a, int q, int Pv) {
         constexpr int f = pair_f(RR, P), g = pair_g(RR, P);
         constexpr int e = carrier_of(RR, f, g, C);
         constexpr int t = triple_of(RR, e, f, g);
-        const int j = q & 3, g4 = q >> 2;
-        const int hb = (int)(int8_t)(a.cw[e][0][g4] >> (8 * j));
-        const int lb = (int)(int8_t)(a.cw[e][1][g4] >> (8 * j));
-        const long long v = (long long)(64 * hb + lb) * (long long)Pv;
-        a.tx[t][j] += v;
-        a.ty[t][g4] += v;
-        CarrierStep<RR, C + 1, P>::run(a, q, Pv);
+        if constexpr (t >= T0 && t < T0 + NTG) {
+            const int j = q & 3, g4 = q >> 2;
+            const int hb = (int)(int8_t)(a.cw[e][0][g4] >> (8 * j));
+            const int lb = (int)(int8_t)(a.cw[e][1][g4] >> (8 * j));
+            const long long v = (long long)(64 * hb + lb) * (long long)Pv;
+            a.tx[t - T0][j] += v;
+            a.ty[t - T0][g4] += v;
+        }
+        CarrierStep<RR, T0, NTG, C + 1, P>::run(a, q, Pv);
     }
 };
-template <int RR, int P>
-struct CarrierStep<RR, RR - 2, P> {
-    static __device__ __forceinline__ void run(TriAcc<RR>&, int, int) {}
+template <int RR, int T0, int NTG, int P>
+struct CarrierStep<RR, T0, NTG, RR - 2, P> {
+    static __device__ __forceinline__ void run(TriAcc<RR, NTG>&, int, int) {}
 };
 
-template <int RR, int P>
+template <int RR, int T0, int NTG, int P>
 struct PairStep {
-    static __device__ __forceinline__ void run(TriAcc<RR>& a, const TriGeom& G) {
+    static __device__ __forceinline__ void run(TriAcc<RR, NTG>& a, const TriGeom& G) {
+        if constexpr (pair_needed(RR, P, T0, NTG)) product(a, G);
+        PairStep<RR, T0, NTG, P + 1>::run(a, G);
+    }
+    static __device__ __forceinline__ void product(TriAcc<RR, NTG>& a, const TriGeom& G) {
         constexpr int f = pair_f(RR, P), g = pair_g(RR, P);
         const int8_t* pf = G.base + (size_t)(2 * f) * G.plane;  // rows of tile Y
         const int8_t* pg = G.base + (size_t)(2 * g) * G.plane;  // rows of tile X
@@ -310,23 +328,26 @@ struct PairStep {
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int Pv = 4096 * hh[q] + 64 * xx[q] + ll[q];
-            CarrierStep<RR, 0, P>::run(a, q, Pv);
+            CarrierStep<RR, T0, NTG, 0, P>::run(a, q, Pv);
         }
-        PairStep<RR, P + 1>::run(a, G);
     }
 };
-template <int RR>
-struct PairStep<RR, RR * (RR - 1) / 2> {
-    static __device__ __forceinline__ void run(TriAcc<RR>&, const TriGeom&) {}
+template <int RR, int T0, int NTG>
+struct PairStep<RR, T0, NTG, RR * (RR - 1) / 2> {
+    static __device__ __forceinline__ void run(TriAcc<RR, NTG>&, const TriGeom&) {}
 };
 
-template <int RR>
+// Records of the triples T0 .. T0 + NTG - 1 (lexicographic order a < b < c):
+// up to 4 replicas one launch takes every triple; with 5 or 6, one launch per
+// group of 2 keeps the int64 sums of a tile in registers, and each group
+// forms only the pair products its triples need.
+template <int RR, int T0, int NTG>
 __global__ void __launch_bounds__(256) k_triple_mfma(int L, int ncfg, int nb,
                                                      const int8_t* __restrict__ ws,
                                                      int64_t* __restrict__ rec) {
-    constexpr int NT = TriAcc<RR>::NT;
+    constexpr int NT = RR * (RR - 1) * (RR - 2) / 6;
     __shared__ __align__(16) uint8_t stg[4 * 64 * kPitch];  // f high, f low, g high, g low
-    __shared__ unsigned long long Tb[NT * 2 * kMaxL];
+    __shared__ unsigned long long Tb[NTG * 2 * kMaxL];
     const int nt = nb * nb, Np = 64 * nt;
     const size_t plane = (size_t)Np * Np;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -334,8 +355,8 @@ __global__ void __launch_bounds__(256) k_triple_mfma(int L, int ncfg, int nb,
     const int ipc = nt * nt;  // output tiles per configuration, all pairs each
     const int grp = blockIdx.x & 7, ngrp_blocks = (int)(gridDim.x >> 3), kk = (int)(blockIdx.x >> 3);
     const int ncg = grp < ncfg ? (ncfg - grp + 7) / 8 : 0;  // configurations grp, grp + 8, ...
-    const int rl = NT * 2 * L;
-    for (int e = tid; e < rl; e += 256) Tb[e] = 0;
+    const int rl = NT * 2 * L, nl = NTG * 2 * L, r0 = T0 * 2 * L;  // record, group slice
+    for (int e = tid; e < nl; e += 256) Tb[e] = 0;
     int cur = -1;
     for (long long s = kk; s < (long long)ncg * ipc; s += ngrp_blocks) {
         const int cfg = grp + 8 * (int)(s / ipc);
@@ -343,8 +364,8 @@ __global__ void __launch_bounds__(256) k_triple_mfma(int L, int ncfg, int nb,
         if (cfg != cur) {  // uniform over the workgroup
             __syncthreads();
             if (cur >= 0)
-                for (int e = tid; e < rl; e += 256) {
-                    atomicAdd((unsigned long long*)&rec[(size_t)cur * rl + e], Tb[e] * 8ull);
+                for (int e = tid; e < nl; e += 256) {
+                    atomicAdd((unsigned long long*)&rec[(size_t)cur * rl + r0 + e], Tb[e] * 8ull);
                     Tb[e] = 0;
                 }
             __syncthreads();
@@ -353,9 +374,9 @@ __global__ void __launch_bounds__(256) k_triple_mfma(int L, int ncfg, int nb,
         const int Y = it / nt, X = it % nt;
         const int8_t* base = ws + (size_t)cfg * RR * 2 * plane;
         const int col = 32 * wy + (lane & 31);
-        TriAcc<RR> a;
+        TriAcc<RR, NTG> a;
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
+        for (int t = 0; t < NTG; ++t)
 #pragma unroll
             for (int j = 0; j < 4; ++j) a.tx[t][j] = a.ty[t][j] = 0;
 #pragma unroll
@@ -368,11 +389,11 @@ __global__ void __launch_bounds__(256) k_triple_mfma(int L, int ncfg, int nb,
                                                          (size_t)(64 * X + col) * Np + 64 * Y + 32 * wx +
                                                          8 * g4 + 4 * h5);
         const TriGeom G{base, plane, Np, nt, X, Y, tid, lane, wx, wy, h5, stg};
-        PairStep<RR, 0>::run(a, G);
+        PairStep<RR, T0, NTG, 0>::run(a, G);
         const int x1 = 8 * (X % nb) + slot_d1(col), x2 = 8 * (X / nb) + slot_d2(col);
         const int y1b = 8 * (Y % nb) + 4 * h5, y2b = 8 * (Y / nb) + 4 * wx;
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
+        for (int t = 0; t < NTG; ++t) {
 #pragma unroll
             for (int j = 0; j < 4; ++j)
                 atomicAdd(&Tb[(t * 2 + 0) * L + mod_l(x1 - y1b - j, L)], (unsigned long long)a.tx[t][j]);
@@ -383,8 +404,23 @@ __global__ void __launch_bounds__(256) k_triple_mfma(int L, int ncfg, int nb,
     }
     __syncthreads();
     if (cur >= 0)
-        for (int e = tid; e < rl; e += 256)
-            atomicAdd((unsigned long long*)&rec[(size_t)cur * rl + e], Tb[e] * 8ull);
+        for (int e = tid; e < nl; e += 256)
+            atomicAdd((unsigned long long*)&rec[(size_t)cur * rl + r0 + e], Tb[e] * 8ull);
+}
+
+// Triples T0 .. NT - 1 in launches of at most 4 (2 with 5 or 6 replicas,
+// whose carrier digits take 16 more registers per replica).
+template <int RR, int T0>
+hipError_t launch_triple_groups(int L, int ncfg, int nb, const int8_t* gw, int64_t* rec, int grid,
+                                hipStream_t st) {
+    constexpr int NT = RR * (RR - 1) * (RR - 2) / 6;
+    constexpr int kGroup = RR <= 4 ? 4 : 2;
+    constexpr int n = NT - T0 < kGroup ? NT - T0 : kGroup;
+    hipLaunchKernelGGL((k_triple_mfma<RR, T0, n>), dim3(grid), dim3(256), 0, st, L, ncfg, nb, gw, rec);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if constexpr (T0 + n < NT) return launch_triple_groups<RR, T0 + n>(L, ncfg, nb, gw, rec, grid, st);
+    return hipSuccess;
 }
 
 size_t store_lds(int RR) { return (size_t)2 * RR * 64 * kPitch + (size_t)2 * RR * 64 * 4 + 2 * 64 * 4; }
@@ -408,9 +444,7 @@ hipError_t launch_triples_rr(const ShapeDev& sh, int cfg0, int ncfg, const Tripl
     const long long ipc = (long long)lay.nt * lay.nt;
     const long long per_grp = std::max<long long>(1, (long long)((ncfg + 7) / 8) * ipc);
     const int g2 = 8 * (int)std::min<long long>(per_grp, (long long)(4 * ncu) / 8);
-    hipLaunchKernelGGL(k_triple_mfma<RR>, dim3(g2), dim3(256), 0, st, sh.L, ncfg, lay.nb,
-                       (const int8_t*)gw, rec);
-    return hipGetLastError();
+    return launch_triple_groups<RR, 0>(sh.L, ncfg, lay.nb, (const int8_t*)gw, rec, g2, st);
 }
 
 }  // namespace
@@ -427,7 +461,7 @@ TripleLayout triple_layout(const ShapeDev& sh, int ncfg) {
 }
 
 const char* triples_unsupported(const ShapeDev& sh) {
-    if (sh.R < 3 || sh.R > 4) return "three-replica records need 3 or 4 replicas";
+    if (sh.R < 3 || sh.R > 6) return "three-replica records need 3 to 6 replicas";
     if (sh.L > kMaxL) return "three-replica records need L <= 32";
     // |G'^f G'^g| <= L^2 (Ltau/2)^2 must fit the int32 accumulators
     const unsigned long long half = (unsigned long long)sh.Lt / 2;
@@ -446,6 +480,8 @@ hipError_t launch_triples(const ShapeDev& sh, int cfg0, int ncfg, void* ws, hipS
     switch (sh.R) {
         case 3: return launch_triples_rr<3>(sh, cfg0, ncfg, lay, ws, st);
         case 4: return launch_triples_rr<4>(sh, cfg0, ncfg, lay, ws, st);
+        case 5: return launch_triples_rr<5>(sh, cfg0, ncfg, lay, ws, st);
+        case 6: return launch_triples_rr<6>(sh, cfg0, ncfg, lay, ws, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -1327,7 +1327,7 @@ static tfim_status measure_core(tfim_plan* pl, uint32_t shape, uint32_t mode, ui
     ShapeHost& h = pl->shapes[shape];
     if (!h.S_ready) return fail(TFIM_ESTATE, "spins of this shape are not initialised");
     const tfim::ShapeDev d = dev_of(pl, shape);
-    if (!tfim::measure_ok(d)) return fail(TFIM_EUNSUPPORTED, "measurement needs 2..4 replicas");
+    if (!tfim::measure_ok(d)) return fail(TFIM_EUNSUPPORTED, "measurement needs 2..6 replicas and L <= 32");
     const uint64_t ncfg_all = (uint64_t)h.s.n_k * 64 * h.s.n_words;
     if ((uint64_t)cfg0 + ncfg > ncfg_all) return fail(TFIM_EINVAL, "configuration range out of bounds");
     if (mode > 1) return fail(TFIM_EINVAL, "unknown measurement mode");

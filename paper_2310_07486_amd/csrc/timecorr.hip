@@ -195,7 +195,7 @@ hipError_t launch_timecorr_rr(const ShapeDev& sh, int cfg0, int ncfg, int64_t* r
 }  // namespace
 
 const char* timecorr_unsupported(const ShapeDev& sh) {
-    if (sh.R < 1 || sh.R > 4) return "two-time records need 1 to 4 replicas";
+    if (sh.R < 1 || sh.R > 6) return "two-time records need 1 to 6 replicas";
     if (sh.L > 32) return "two-time records need L <= 32";
     if (sh.Lt > kMaxLtTime) return "two-time records need Ltau <= 4096";
     return nullptr;
@@ -210,6 +210,8 @@ hipError_t launch_timecorr(const ShapeDev& sh, int cfg0, int ncfg, int64_t* rec,
         case 2: return launch_timecorr_rr<2>(sh, cfg0, ncfg, rec, st);
         case 3: return launch_timecorr_rr<3>(sh, cfg0, ncfg, rec, st);
         case 4: return launch_timecorr_rr<4>(sh, cfg0, ncfg, rec, st);
+        case 5: return launch_timecorr_rr<5>(sh, cfg0, ncfg, rec, st);
+        case 6: return launch_timecorr_rr<6>(sh, cfg0, ncfg, rec, st);
         default: return hipErrorInvalidValue;
     }
 }

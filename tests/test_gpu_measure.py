@@ -33,7 +33,8 @@ def _oracle_records(sh, seed, lanes, sweeps, k_indices=None):
 
 
 @pytest.mark.parametrize("L,Lt,R,nk", [(4, 16, 2, 3), (6, 40, 3, 2), (8, 64, 4, 3),
-                                       (10, 136, 4, 2), (12, 24, 2, 4)])
+                                       (10, 136, 4, 2), (12, 24, 2, 4), (8, 64, 6, 2),
+                                       (10, 72, 5, 2), (24, 16, 6, 1)])
 @pytest.mark.parametrize("mode", [0, 1])
 def test_records_match_oracle(L, Lt, R, nk, mode):
     sh = Shape(L, Lt, 1, R, ladder(0.2, 0.45, nk), pt_every=1)
@@ -104,4 +105,14 @@ def test_full_shape_sampled_configs_and_identities():
     cfg = 31 * S + 999
     plain = plan.measure_range(0, 1, cfg, 1, flags=tfim.TFIM_MEASURE_REUSE_LAYOUT)
     assert np.array_equal(plain[0], rec[31, 999])
+    plan.close()
+
+
+def test_records_refuse_seven_replicas():
+    sh = Shape(4, 16, 1, 7, ladder(0.2, 0.3, 2), pt_every=1)
+    plan = tfim.Plan([sh], 5)
+    plan.init()
+    with pytest.raises(tfim.TfimError) as ei:
+        plan.measure(0, tfim.TFIM_MEASURE_RECORDS)
+    assert ei.value.status == tfim.TFIM_EUNSUPPORTED
     plan.close()

@@ -242,3 +242,22 @@ def test_zero_sweeps_is_a_no_op():
     plan.sync()
     after = (plan.export_spins(0), *plan.get_state(0), plan.counters())
     assert all(np.array_equal(a, b) for a, b in zip(before[:3], after[:3])) and before[3] == after[3]
+
+
+@pytest.mark.parametrize("variant", [0, 3])
+def test_paper_schedule_six_replicas_tempering_every_30_sweeps(variant):
+    """The paper's schedule (Simulation details, Table I caption): 6 real
+    replicas and a tempering attempt after every 30 Metropolis sweeps, on the
+    16-value k ladder of Table I for L = 8; 65 sweeps hold two tempering
+    steps, the second after a call boundary."""
+    sh = Shape(8, 32, 1, 6, ladder(0.265, 0.305, 16), pt_every=30)
+    seed = 3010 + variant
+    _say(f"paper-schedule parity variant={variant} L=8 Lt=32 R=6 nk=16 pt=30")
+    plan = tfim.Plan([sh], seed)
+    plan.set_variant(variant)
+    plan.init()
+    plan.sweep(45)
+    plan.sweep(20)
+    plan.sync()
+    _compare(plan, 0, sh, seed, list(range(64)), 65)
+    assert plan.counters() == (65, 2)

@@ -26,7 +26,8 @@ def _say(msg):
 
 
 @pytest.mark.parametrize("L,Lt,R,nk", [(4, 16, 1, 2), (6, 40, 2, 2), (8, 64, 4, 2),
-                                       (10, 136, 3, 2), (16, 72, 4, 1), (2, 8, 4, 1)])
+                                       (10, 136, 3, 2), (16, 72, 4, 1), (2, 8, 4, 1),
+                                       (8, 64, 6, 2), (10, 136, 5, 1)])
 def test_time_records_match_oracle(L, Lt, R, nk):
     sh = Shape(L, Lt, 1, R, ladder(0.2, 0.45, nk), pt_every=1)
     seed = 1700 + L + Lt
@@ -74,4 +75,14 @@ def test_time_full_shape_sampled_configs_and_identities():
     want = om.measure_time_chain(ch, k_indices=[0, 31])  # [2][2][2Lt]
     assert np.array_equal(picks[0].reshape(-1), want[0, 0])
     assert np.array_equal(picks[31 * S + 999].reshape(-1), want[1, 1])
+    plan.close()
+
+
+def test_time_records_refuse_seven_replicas():
+    sh = Shape(4, 16, 1, 7, ladder(0.2, 0.3, 2), pt_every=1)
+    plan = tfim.Plan([sh], 5)
+    plan.init()
+    with pytest.raises(tfim.TfimError) as ei:
+        plan.measure_time(0, 0, 4)
+    assert ei.value.status == tfim.TFIM_EUNSUPPORTED
     plan.close()

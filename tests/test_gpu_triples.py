@@ -29,7 +29,8 @@ def _say(msg):
 
 
 @pytest.mark.parametrize("L,Lt,R,nk", [(4, 16, 3, 2), (6, 40, 4, 2), (8, 64, 4, 2),
-                                       (10, 136, 4, 2), (16, 72, 3, 1), (2, 8, 4, 1)])
+                                       (10, 136, 4, 2), (16, 72, 3, 1), (2, 8, 4, 1),
+                                       (6, 40, 6, 2), (8, 64, 5, 2), (10, 72, 6, 1)])
 def test_triple_records_match_oracle(L, Lt, R, nk):
     sh = Shape(L, Lt, 1, R, ladder(0.2, 0.45, nk), pt_every=1)
     seed = 1300 + L + Lt
@@ -51,8 +52,9 @@ def test_triple_records_match_oracle(L, Lt, R, nk):
     plan.close()
 
 
-def test_triple_records_refuse_two_replicas():
-    sh = Shape(4, 16, 1, 2, ladder(0.2, 0.3, 2), pt_every=1)
+@pytest.mark.parametrize("R", [2, 7])
+def test_triple_records_refuse_replica_counts_outside_3_to_6(R):
+    sh = Shape(4, 16, 1, R, ladder(0.2, 0.3, 2), pt_every=1)
     plan = tfim.Plan([sh], 5)
     plan.init()
     with pytest.raises(tfim.TfimError) as ei:

@@ -297,6 +297,47 @@ def transfer_leg(torch, args):
     }
 
 
+def paper_leg(torch, args):
+    """The paper's production row for L = 24 (Table I: Ltau = 2048, 60 k
+    uniformly over [0.265, 0.292]) on its schedule (6 replicas, a tempering
+    attempt after every 30 sweeps) with 1280 disorder samples, the count the
+    paper equilibrates per size: 68 GB of spin words, 204 GB of arena with the
+    measurement layouts.  Timed over 60 sweeps (two tempering steps)."""
+    from paper_2310_07486_amd import tfim
+    from paper_2310_07486_amd.workloads import table_i, SEED_BASE
+    sh = table_i(24, n_words=20)
+    upd = sh.updates_per_sweep()
+    out = {"workload": "table-I-L24-paper-schedule", "L": sh.L, "Ltau": sh.Ltau, "samples": sh.n_samples,
+           "replicas": sh.n_replicas, "n_k": len(sh.k), "k_range": [sh.k[0], sh.k[-1]],
+           "pt_every": sh.pt_every, "updates_per_sweep": upd}
+    try:
+        plan = tfim.Plan([sh], SEED_BASE + 6)
+    except torch.cuda.OutOfMemoryError as e:  # a box with less free HBM than the arena
+        out["skipped"] = f"arena does not fit: {e}"
+        return out
+    out["arena_gb"] = round(plan.sizes["total"] / 1e9, 2)
+    plan.init()
+    plan.sweep(args.warmup)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    n = 60
+    e0.record(stream)
+    plan.sweep(n)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / n
+    out.update({"sweeps": n, "ms_per_sweep": round(ms, 3), "spin_updates_per_ns": round(upd / (ms * 1e6), 1),
+                "ps_per_update": round(ms * 1e9 / upd, 5), "ms_per_elementary_step": round(30 * ms, 2)})
+    log(f"bench: paper schedule L=24 (1280 samples, 6 replicas, 60 k, tempering every 30): "
+        f"{ms:.3f} ms/sweep, {upd / (ms * 1e6):.1f} spin-updates/ns, arena {out['arena_gb']} GB")
+    plan.close()
+    del plan
+    torch.cuda.empty_cache()
+    return out
+
+
 def batched_leg(torch, args):
     """Five uneven sizes (L, Ltau) = (8,256) .. (24,2048), 512 samples each:
     the per-shape schedule (five sweep launches per sweep, one per size)
@@ -369,6 +410,7 @@ def main():
     ap.add_argument("--no-triples", action="store_true")
     ap.add_argument("--no-timecorr", action="store_true")
     ap.add_argument("--no-transfer", action="store_true")
+    ap.add_argument("--no-paper", action="store_true", help="skip the paper-schedule L=24 leg")
     ap.add_argument("--triples-chunk", type=int, default=4096)
     ap.add_argument("--unbatched-cfgs", type=int, default=64)
     ap.add_argument("--plain-cfgs", type=int, default=1)
@@ -482,6 +524,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_transfer:
         result["transfer"] = transfer_leg(torch, args)
+    if not args.no_paper:
+        result["paper_schedule"] = paper_leg(torch, args)
     if not args.no_batched:
         result["batched"] = batched_leg(torch, args)
     if not args.no_cpu_baseline:

@@ -81,6 +81,17 @@ def c3_large() -> Workload:
 
 TABLE_I_RANGES = {8: (0.265, 0.305), 12: (0.265, 0.305), 16: (0.265, 0.295986),
                   20: (0.265, 0.295986), 24: (0.265, 0.292)}
+# Table I: L -> (Ltau, number of k values uniformly over the range above)
+TABLE_I = {8: (512, 16), 12: (512, 24), 16: (2048, 48), 20: (2048, 56), 24: (2048, 60)}
+
+
+def table_i(L: int, n_words: int, n_replicas: int = 6, pt_every: int = 30, stream_id: int = 0) -> Shape:
+    """One Table I row with the paper's schedule (Simulation details and the
+    Table I caption): 6 real replicas and a tempering attempt after every 30
+    Metropolis sweeps, 64 * n_words disorder samples."""
+    Lt, nk = TABLE_I[L]
+    return Shape(L, Lt, n_words, n_replicas, ladder(*TABLE_I_RANGES[L], nk), pt_every=pt_every,
+                 stream_id=stream_id)
 
 
 def c4_batched() -> Workload:

@@ -187,3 +187,19 @@ def test_triples_workspace_and_limits():
             p.triples_workspace_bytes(0, 1)
         assert ei.value.status == tfim.TFIM_EUNSUPPORTED
         p.close()
+
+
+def test_paper_schedule_rows_and_the_L24_arena():
+    """Table I rows on the paper's schedule; the L = 24 row with 1280 samples
+    (the bench's paper-schedule leg) fits one GPU's 288 GB."""
+    from paper_2310_07486_amd.workloads import table_i
+    rows = {L: table_i(L, n_words=1) for L in (8, 12, 16, 20, 24)}
+    assert [(s.Ltau, len(s.k)) for s in rows.values()] == [(512, 16), (512, 24), (2048, 48), (2048, 56),
+                                                           (2048, 60)]
+    assert all(s.n_replicas == 6 and s.pt_every == 30 for s in rows.values())
+    assert rows[16].k[-1] == 0.295986 and rows[24].k[0] == 0.265 and rows[24].k[-1] == 0.292
+    s = table_i(24, n_words=20)
+    p = _plan([s])
+    assert p.sizes["spins"] == 6 * 60 * 20 * 24 ** 2 * 2048 * 8  # 67.95 GB
+    assert p.sizes["total"] < 250e9
+    p.close()

@@ -27,7 +27,8 @@ pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 def _run(L, nk, seed, n_eq=50000, n_meas=100, gap=200, R=4, pt_every=1, halves=False):
     """xi^(2)/L, xi^(3)/L and the Binder ratio per k of one size (and, with
     halves, the per-sample three-replica buckets of the first and the second
-    half of the measurements, [2][k][s][2L])."""
+    half of the measurements, [2][k][s][2L], and the per-sample sums of the
+    pair records' D_x over pairs, measurements and d, [k][s])."""
     sh = Shape(L, 512, 8, R, ladder(0.265, 0.305, nk), pt_every=pt_every)
     plan = tfim.Plan([sh], seed)
     plan.init()
@@ -38,11 +39,13 @@ def _run(L, nk, seed, n_eq=50000, n_meas=100, gap=200, R=4, pt_every=1, halves=F
     T = np.zeros((nk, n_meas, 2 * L), dtype=np.int64)  # per measurement: samples and triples summed
     Ts = np.zeros((nk, S, 2 * L), dtype=np.int64)      # per sample: triples and measurements summed
     Th = np.zeros((2, nk, S, 2 * L), dtype=np.int64)   # the same per half of the measurements
+    Ds = np.zeros((nk, S), dtype=np.int64)              # per sample: sum_xy G^a G^b, all pairs
     P = []
     for m in range(n_meas):
         plan.sweep(gap)
         rec = plan.measure(0, tfim.TFIM_MEASURE_RECORDS)  # [k][s][pair][2L+3]
         A += rec[:, :, :, :L].sum(axis=(1, 2))
+        Ds += rec[:, :, :, :L].sum(axis=(2, 3))
         P.append(rec[:, :, :, 2 * L + 1:].sum(axis=1))    # sum Q^2, sum Q^4 per k and pair
         tr = plan.measure_triples(0, 0, nk * S, flags=tfim.TFIM_MEASURE_REUSE_LAYOUT)
         tr = tr.reshape(nk, S, -1, 2 * L).sum(axis=2)
@@ -57,7 +60,7 @@ def _run(L, nk, seed, n_eq=50000, n_meas=100, gap=200, R=4, pt_every=1, halves=F
     B = tfim.tfim_binder(pr, L, sh.Ltau) * S
     k = np.asarray(sh.k)
     out = (k, tfim.tfim_xi2(np.ascontiguousarray(A), L) / L, tfim.tfim_xi3(T, L, 2) / L, B, Ts)
-    return out + (Th,) if halves else out
+    return out + (Th, Ds) if halves else out
 
 
 def _xi3_over_L(Ab, L):
@@ -81,6 +84,38 @@ def _xi3_boot(Ts, L, rng, n_boot, Ts2=None):
         if A2 is not None:
             out[b] -= _xi3_over_L(np.einsum("s,ksd->kd", w, A2), L)
     return out
+
+
+def _quotients(runs, w, deg=3):
+    """The quotient method (Methods, "The critical point and critical
+    exponents") for L = 8, 12 with sample weights w[L]: k* where the two
+    sizes' xi^(3)/L cross, and at k* the effective exponents
+    x/nu = log(A_8 / A_12) / log(8 / 12) of A = d(xi^(3)/L)/dk (1/nu),
+    A = chi^(2) and A = chi^(3) (gamma^(r)/nu), all from cubic fits in k of
+    each size's curve.  chi^(r) = Tr[M^r] / L^2 with M the tau-averaged
+    equal-time correlation: the record sums over L^2, the other factors
+    (Ltau, replica pairs or triples, measurements, samples) are the same for
+    both sizes and cancel in the quotients.  None unless the fitted curves
+    cross exactly once in the k range."""
+    cur = {}
+    for L in (8, 12):
+        k, Ts, Ds = runs[L][0], runs[L][4].astype(np.float64), runs[L][6].astype(np.float64)
+        x = _xi3_over_L(np.einsum("s,ksd->kd", w[L], Ts[:, :, :L] + Ts[:, :, L:]), L)
+        c2 = np.einsum("s,ks->k", w[L], Ds) / L ** 2
+        c3 = np.einsum("s,ks->k", w[L], Ts[:, :, :L].sum(axis=2)) / L ** 2
+        cur[L] = (k, np.polyfit(k, x, deg), np.polyfit(k, np.log(c2), deg), np.polyfit(k, np.log(c3), deg))
+    kk = np.linspace(0.265, 0.305, 4001)
+    d = np.polyval(cur[12][1], kk) - np.polyval(cur[8][1], kk)
+    idx = np.nonzero(np.sign(d[:-1]) != np.sign(d[1:]))[0]
+    if len(idx) != 1:
+        return None
+    ks = float(kk[idx[0]])
+    q = np.log(8 / 12)
+    return {"k*": ks,
+            "1/nu": float(np.log(np.polyval(np.polyder(cur[8][1]), ks) /
+                                 np.polyval(np.polyder(cur[12][1]), ks)) / q),
+            "gamma2/nu": float((np.polyval(cur[8][2], ks) - np.polyval(cur[12][2], ks)) / q),
+            "gamma3/nu": float((np.polyval(cur[8][3], ks) - np.polyval(cur[12][3], ks)) / q)}
 
 
 def _crossings(c8, c12, lo, hi):
@@ -142,7 +177,8 @@ def test_paper_schedule_six_replicas_tempering_every_30_sweeps():
     at 512 disorder samples.  The xi^(3)/L crossing with bootstrap errors
     over the samples must agree with the paper's 0.2910(15) within three
     combined standard deviations, and the measurements of the first and the
-    second half of the run must agree (no drift left from equilibration)."""
+    second half of the run must agree (no drift left from equilibration).
+    The quotient method then gives effective exponents at the crossing."""
     runs = {}
     for L, nk in ((8, 16), (12, 24)):
         print(f"physics (paper schedule): L={L} Ltau=512 512 samples, 6 replicas, tempering every 30",
@@ -180,3 +216,27 @@ def test_paper_schedule_six_replicas_tempering_every_30_sweeps():
           f"(bootstrap, {len(ks)} of 200 with one crossing)", flush=True)
     assert len(ks) >= 180 and 0.0 < sigma < 0.01
     assert abs(cross3[0] - 0.2910) < 3.0 * np.hypot(sigma, 0.0015)
+    # effective exponents of the quotient method at k*(8, 12), bootstrap over
+    # the samples of each size; the checks are those the paper's text fixes
+    # (chi^(2) barely divergent, gamma^(r) growing with r) and agreement
+    # within three combined standard deviations with its extrapolated
+    # exponents (statistical and systematic errors of the paper added)
+    ones = {L: np.ones(runs[L][4].shape[1]) for L in (8, 12)}
+    ex = _quotients(runs, ones)
+    assert ex is not None
+    rng = np.random.default_rng(2312)
+    bs = []
+    for b in range(200):
+        w = {L: np.bincount(rng.integers(0, len(ones[L]), size=len(ones[L])),
+                            minlength=len(ones[L])).astype(np.float64) for L in (8, 12)}
+        r = _quotients(runs, w)
+        if r is not None:
+            bs.append([r[key] for key in ex])
+    assert len(bs) >= 180
+    sd = dict(zip(ex, np.array(bs).std(axis=0, ddof=1)))
+    print("physics (paper schedule): quotient method at k*(8,12): " +
+          ", ".join(f"{key} = {ex[key]:.4f} +- {sd[key]:.4f}" for key in ex), flush=True)
+    assert 0.0 < ex["gamma2/nu"] < 1.0 and ex["gamma2/nu"] < ex["gamma3/nu"] and ex["1/nu"] > 0.0
+    paper = {"1/nu": (0.71, 0.24, 0.09), "gamma2/nu": (0.27, 0.08, 0.08), "gamma3/nu": (1.39, 0.23, 0.11)}
+    for key, (val, e_stat, e_sys) in paper.items():
+        assert abs(ex[key] - val) < 3.0 * np.sqrt(sd[key] ** 2 + e_stat ** 2 + e_sys ** 2), key

@@ -187,7 +187,7 @@ def test_paper_schedule_six_replicas_tempering_every_30_sweeps():
         runs[L] = _run(L, nk, 5200 + L, n_eq=60000, n_meas=80, gap=210, R=6, pt_every=30, halves=True)
     rng = np.random.default_rng(2311)
     boots = {}
-    for L, (k, x2, x3, B, Ts, _) in runs.items():
+    for L, (k, x2, x3, B, Ts, _, _) in runs.items():
         print(f"physics (paper schedule): L={L} xi3/L {np.round(x3, 4).tolist()}", flush=True)
         assert np.all(np.isfinite(x3)) and np.all(np.diff(x3) > 0), f"xi3/L of L={L} not increasing in k"
         assert np.all((B > 1.0) & (B < 3.05)), f"Binder ratio of L={L} outside (1, 3]"

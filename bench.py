@@ -332,6 +332,39 @@ def paper_leg(torch, args):
                 "ps_per_update": round(ms * 1e9 / upd, 5), "ms_per_elementary_step": round(30 * ms, 2)})
     log(f"bench: paper schedule L=24 (1280 samples, 6 replicas, 60 k, tempering every 30): "
         f"{ms:.3f} ms/sweep, {upd / (ms * 1e6):.1f} spin-updates/ns, arena {out['arena_gb']} GB")
+    # the measurements with 6 replicas (15 pairs, 20 triples) on the first
+    # 2048 configurations: pair records, three-replica records, two-time records
+    n = 2048
+    flags = tfim.TFIM_MEASURE_REUSE_LAYOUT
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b)
+
+    plan.measure_range(0, 0, 0, 1, copy=False)  # bit layouts of every configuration
+    plan.measure_triples(0, 0, n, flags=flags, copy=False)  # workspaces
+    plan.measure_time(0, 0, n, flags=flags, copy=False)
+    _, g_ops, q_ops = measure_ops(sh)
+    t_alg, t_exe = triples_ops(sh)
+    c_alg = sh.Ltau * (sh.Ltau + 1) * sh.L ** 2 * sh.n_replicas
+    ms_p = timed(lambda: plan.measure_range(0, 0, 0, n, flags=flags, copy=False))
+    ms_t = timed(lambda: plan.measure_triples(0, 0, n, flags=flags, copy=False))
+    ms_c = timed(lambda: plan.measure_time(0, 0, n, flags=flags, copy=False))
+    out["measure_6_replicas"] = {
+        "configurations": n,
+        "pairs_ms": round(ms_p, 3), "pairs_algorithmic_tops": round((g_ops + q_ops) * n / (ms_p * 1e9), 2),
+        "triples_ms": round(ms_t, 3), "triples_algorithmic_tops": round(t_alg * n / (ms_t * 1e9), 2),
+        "two_time_ms": round(ms_c, 3), "two_time_algorithmic_tops": round(c_alg * n / (ms_c * 1e9), 2)}
+    log(f"bench: paper schedule, 6-replica measurements of {n} configurations: pairs {ms_p:.1f} ms, "
+        f"triples {ms_t:.1f} ms, two-time {ms_c:.1f} ms")
+    plan._tws = None
+    plan._tcws = None
     plan.close()
     del plan
     torch.cuda.empty_cache()

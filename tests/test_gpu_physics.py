@@ -24,12 +24,13 @@ from paper_2310_07486_amd.workloads import Shape, ladder
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
 
-def _run(L, nk, seed, n_eq=50000, n_meas=100, gap=200, R=4, pt_every=1, halves=False, n_words=8):
+def _run(L, nk, seed, n_eq=50000, n_meas=100, gap=200, R=4, pt_every=1, halves=False, n_words=8,
+         Ltau=512, k_range=(0.265, 0.305)):
     """xi^(2)/L, xi^(3)/L and the Binder ratio per k of one size (and, with
     halves, the per-sample three-replica buckets of the first and the second
     half of the measurements, [2][k][s][2L], and the per-sample sums of the
     pair records' D_x over pairs, measurements and d, [k][s])."""
-    sh = Shape(L, 512, n_words, R, ladder(0.265, 0.305, nk), pt_every=pt_every)
+    sh = Shape(L, Ltau, n_words, R, ladder(*k_range, nk), pt_every=pt_every)
     plan = tfim.Plan([sh], seed)
     plan.init()
     for e in range(n_eq // 10000):
@@ -39,9 +40,12 @@ def _run(L, nk, seed, n_eq=50000, n_meas=100, gap=200, R=4, pt_every=1, halves=F
     S = sh.n_samples
     A = np.zeros((nk, L), dtype=np.int64)
     T = np.zeros((nk, n_meas, 2 * L), dtype=np.int64)  # per measurement: samples and triples summed
-    Ts = np.zeros((nk, S, 2 * L), dtype=np.int64)      # per sample: triples and measurements summed
-    Th = np.zeros((2, nk, S, 2 * L), dtype=np.int64)   # the same per half of the measurements
-    Ds = np.zeros((nk, S), dtype=np.int64)              # per sample: sum_xy G^a G^b, all pairs
+    # per-sample sums go to float64: at Ltau = 2048 they pass 2^63 (the
+    # library's own tfim_xi3 adds records in 128-bit integers)
+    Ts = np.zeros((nk, S, 2 * L))       # per sample: triples and measurements summed
+    Th = np.zeros((2, nk, S, 2 * L))    # the same per half of the measurements
+    Ds = np.zeros((nk, S))              # per sample: sum_xy G^a G^b, all pairs
+    Tf = np.zeros((nk, n_meas, 2 * L))  # T in float64, to check that T's int64 sums did not wrap
     P = []
     for m in range(n_meas):
         if m % 20 == 0:
@@ -49,14 +53,17 @@ def _run(L, nk, seed, n_eq=50000, n_meas=100, gap=200, R=4, pt_every=1, halves=F
         plan.sweep(gap)
         rec = plan.measure(0, tfim.TFIM_MEASURE_RECORDS)  # [k][s][pair][2L+3]
         A += rec[:, :, :, :L].sum(axis=(1, 2))
-        Ds += rec[:, :, :, :L].sum(axis=(2, 3))
+        Ds += rec[:, :, :, :L].astype(np.float64).sum(axis=(2, 3))
         P.append(rec[:, :, :, 2 * L + 1:].sum(axis=1))    # sum Q^2, sum Q^4 per k and pair
         tr = plan.measure_triples(0, 0, nk * S, flags=tfim.TFIM_MEASURE_REUSE_LAYOUT)
-        tr = tr.reshape(nk, S, -1, 2 * L).sum(axis=2)
-        T[:, m] = tr.sum(axis=1)
-        Ts += tr
-        Th[int(2 * m >= n_meas)] += tr
+        tr = tr.reshape(nk, S, -1, 2 * L)
+        T[:, m] = tr.sum(axis=(1, 2))
+        trf = tr.astype(np.float64).sum(axis=2)
+        Tf[:, m] = trf.sum(axis=1)
+        Ts += trf
+        Th[int(2 * m >= n_meas)] += trf
     plan.close()
+    assert np.allclose(T.astype(np.float64), Tf, rtol=1e-12, atol=0.0), "int64 sums of the triple records wrapped"
     q = np.stack(P, axis=1)  # [k][meas][pair][2]
     pr = np.zeros((nk, q.shape[1] * q.shape[2], 2 * L + 3), dtype=np.int64)
     pr[..., 2 * L + 1:] = q.reshape(nk, -1, 2)

@@ -453,8 +453,8 @@ def main():
                     help="first run a plain device copy of this many GB (calibrates HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; --gpus must be 1 "
-              "(sample words shard across GPUs by word_offset, see DESIGN.md)", file=sys.stderr)
+        print("bench.py: runs on one GPU; --gpus must be 1 (sample words would shard across "
+              "GPUs by word_offset, which is not built)", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -179,7 +179,12 @@ def test_triples_workspace_and_limits():
     p = _plan([Shape(24, 2520, 1, 4, ladder(0.2, 0.3, 2))])
     assert p.triples_workspace_bytes(0, 1) > 0
     p.close()
+    # the paper's 6 replicas: 20 triples of records, 6 replicas of G planes
+    p = _plan([Shape(24, 2048, 1, 6, ladder(0.265, 0.292, 60))])
+    assert p.triples_workspace_bytes(0, 1) == 256 * ((20 * 48 * 8 + 255) // 256) + 6 * 2 * 576 * 576
+    p.close()
     for sh in (Shape(8, 64, 1, 2, ladder(0.2, 0.3, 2)),      # two replicas
+               Shape(8, 64, 1, 7, ladder(0.2, 0.3, 2)),      # seven replicas
                Shape(24, 2528, 1, 4, ladder(0.2, 0.3, 2)),   # 3 L^6 Ltau^3 >= 2^63
                Shape(24, 4096, 1, 4, ladder(0.2, 0.3, 2))):  # both bounds exceeded
         p = _plan([sh])

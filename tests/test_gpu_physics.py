@@ -18,7 +18,7 @@ import sys
 import numpy as np
 import pytest
 
-from paper_2310_07486_amd import tfim
+from paper_2310_07486_amd import fss, tfim
 from paper_2310_07486_amd.workloads import Shape, ladder
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
@@ -99,34 +99,22 @@ def _xi3_boot(Ts, L, rng, n_boot, Ts2=None):
 
 def _quotients(runs, w, deg=3):
     """The quotient method (Methods, "The critical point and critical
-    exponents") for L = 8, 12 with sample weights w[L]: k* where the two
-    sizes' xi^(3)/L cross, and at k* the effective exponents
-    x/nu = log(A_8 / A_12) / log(8 / 12) of A = d(xi^(3)/L)/dk (1/nu),
-    A = chi^(2) and A = chi^(3) (gamma^(r)/nu), all from cubic fits in k of
-    each size's curve.  chi^(r) = Tr[M^r] / L^2 with M the tau-averaged
+    exponents") for L = 8, 12 with sample weights w[L], through the package's
+    fss.quotient_method: k* where the two sizes' xi^(3)/L cross, and at k*
+    the effective exponents x/nu = log(A_8 / A_12) / log(8 / 12) of
+    A = d(xi^(3)/L)/dk (1/nu), A = chi^(2) and A = chi^(3) (gamma^(r)/nu),
+    from cubic fits in k.  chi^(r) = Tr[M^r] / L^2 with M the tau-averaged
     equal-time correlation: the record sums over L^2, the other factors
     (Ltau, replica pairs or triples, measurements, samples) are the same for
     both sizes and cancel in the quotients.  None unless the fitted curves
     cross exactly once in the k range."""
-    cur = {}
+    curves = {}
     for L in (8, 12):
         k, Ts, Ds = runs[L][0], runs[L][4].astype(np.float64), runs[L][6].astype(np.float64)
-        x = _xi3_over_L(np.einsum("s,ksd->kd", w[L], Ts[:, :, :L] + Ts[:, :, L:]), L)
-        c2 = np.einsum("s,ks->k", w[L], Ds) / L ** 2
-        c3 = np.einsum("s,ks->k", w[L], Ts[:, :, :L].sum(axis=2)) / L ** 2
-        cur[L] = (k, np.polyfit(k, x, deg), np.polyfit(k, np.log(c2), deg), np.polyfit(k, np.log(c3), deg))
-    kk = np.linspace(0.265, 0.305, 4001)
-    d = np.polyval(cur[12][1], kk) - np.polyval(cur[8][1], kk)
-    idx = np.nonzero(np.sign(d[:-1]) != np.sign(d[1:]))[0]
-    if len(idx) != 1:
-        return None
-    ks = float(kk[idx[0]])
-    q = np.log(8 / 12)
-    return {"k*": ks,
-            "1/nu": float(np.log(np.polyval(np.polyder(cur[8][1]), ks) /
-                                 np.polyval(np.polyder(cur[12][1]), ks)) / q),
-            "gamma2/nu": float((np.polyval(cur[8][2], ks) - np.polyval(cur[12][2], ks)) / q),
-            "gamma3/nu": float((np.polyval(cur[8][3], ks) - np.polyval(cur[12][3], ks)) / q)}
+        curves[L] = (k, fss.xi_over_L(np.einsum("s,ksd->kd", w[L], Ts[:, :, :L] + Ts[:, :, L:]), L),
+                     np.einsum("s,ks->k", w[L], Ds) / L ** 2,
+                     np.einsum("s,ks->k", w[L], Ts[:, :, :L].sum(axis=2)) / L ** 2)
+    return fss.quotient_method(curves, 8, 12, 0.265, 0.305, deg)
 
 
 def _crossings(c8, c12, lo, hi):

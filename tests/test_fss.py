@@ -61,3 +61,33 @@ def test_bootstrap_weights_resample_each_size():
     res, sd = fss.bootstrap(fn, {8: 5, 12: 7}, 20, seed=3)
     assert len(res) == 20 and all(r["n8"] == 5 and r["n12"] == 7 for r in res)
     assert sd["n8"] == 0.0 and any((s[8] != 1).any() for s in seen)
+
+
+def _row(tmp_path, L, Lt, nm, k, S=6, R=6):
+    """A saved row whose records give exactly the scaling curves above, with
+    its own Ltau and measurement count (the analysis must normalise both)."""
+    P, NT = R * (R - 1) // 2, R * (R - 1) * (R - 2) // 6
+    _, y, c2, c3 = _curves(L, k)
+    ratio = 1.0 + (2.0 * np.sin(np.pi / L) * L * y) ** 2   # chi / F for xi / L = y
+    a = 2.0 / ratio                                           # profile 1 + a cos(2 pi d / L)
+    prof = 1.0 + a[:, None] * np.cos(2 * np.pi * np.arange(L) / L)[None, :]
+    f = c3 * 3 * NT * nm * Lt ** 3 * L ** 2 / L               # sum_d of the x buckets = f L
+    Ts = np.repeat((f[:, None] * prof)[:, None, :], S, axis=1)
+    Ts = np.concatenate([Ts, Ts], axis=2)                     # the same in the y direction
+    Ds = np.repeat((c2 * P * nm * Lt ** 2 * L ** 2)[:, None], S, axis=1)
+    path = tmp_path / f"row{L}.npz"
+    np.savez(path, k=k, Ts=Ts, Th=np.stack([Ts / 2, Ts / 2]), Ds=Ds, L=L, Ltau=Lt, n_meas=nm, R=R)
+    return str(path)
+
+
+def test_runner_analysis_normalises_rows_and_recovers_exponents(tmp_path):
+    from paper_2310_07486_amd import fss_run
+    a = _row(tmp_path, 8, 512, 80, np.linspace(0.265, 0.305, 16))
+    b = _row(tmp_path, 16, 2048, 40, np.linspace(0.265, 0.295986, 48))
+    res = fss_run.analyse([a, b], n_boot=4)
+    central, sd, n = res[(8, 16)]
+    assert central["k*"] == pytest.approx(KC, abs=1e-9)
+    assert central["1/nu"] == pytest.approx(INV_NU, abs=1e-7)
+    assert central["gamma2/nu"] == pytest.approx(G2, abs=1e-7)
+    assert central["gamma3/nu"] == pytest.approx(G3, abs=1e-7)
+    assert n == 4  # identical samples: every resampling crosses once

@@ -37,8 +37,17 @@
  *
  * Errors: every call returns a tfim_status and never throws.  Argument
  * errors return before anything is enqueued and leave the state unchanged.
- * A device error poisons the plan: later calls return TFIM_ESTATE.
- * tfim_last_error_detail() describes the last failure of this thread.
+ * A device error poisons the plan for the rest of its life: every later call
+ * that uses it (tfim_bind included) returns TFIM_ESTATE; a saved state is
+ * resumed on a new plan with tfim_set_state.  tfim_last_error_detail()
+ * describes the last failure of this thread.
+ *
+ * Failure injection (for tests of the error path; nothing reaches the GPU):
+ * when the environment variable TFIM_FAIL_AFTER = n >= 1 is set at
+ * tfim_plan_create, the n-th call of that plan that would enqueue device work
+ * (init, sweep, pt_swap, set_state and the measurement calls) enqueues
+ * nothing and fails as a device error does: it returns TFIM_EDEVICE and
+ * poisons the plan.
  *
  * Concurrency: calls that enqueue work (init, sweep, pt_swap) are
  * asynchronous on the bound stream; calls that return data to the host
@@ -72,9 +81,10 @@ typedef int32_t tfim_status;
  * ladder k[0] < k[1] < ... < k[n_k-1] through tempering. */
 typedef struct {
     uint32_t L;           /* even, 2..24 (one thread per spatial column) */
-    uint32_t Ltau;        /* multiple of 8, 8..65536 (else TFIM_EUNSUPPORTED) */
-    uint32_t n_words;     /* >= 1; samples = 64*n_words */
-    uint32_t word_offset; /* global index of word 0 (word_offset + n_words <= 2^20) */
+    uint32_t Ltau;        /* even, 4..65536; multispin form: a multiple of 8
+                             (else TFIM_EUNSUPPORTED) */
+    uint32_t n_words;     /* >= 1; samples = 64*n_words (plain form: samples) */
+    uint32_t word_offset; /* global index of word 0 (the words used end below 2^20) */
     uint32_t n_replicas;  /* 1..64 */
     uint32_t n_k;         /* 1..255 */
     const double *k;      /* n_k couplings, > 0, strictly increasing; copied */
@@ -86,6 +96,22 @@ typedef struct {
 
 typedef struct tfim_plan tfim_plan;
 
+/* Representation of a plan's spins (Methods, "The Trotter-Suzuki formula":
+ * classical spins S = +-1; "Simulation details": multispin coding).
+ * TFIM_FORM_MULTISPIN: 64 disorder samples per uint64 word, as above.
+ * TFIM_FORM_PLAIN_I8: one signed byte (+1 / -1) per spin and coupling, one
+ *   sample per configuration; tfim_shape.n_words then counts SAMPLES, and
+ *   sample s draws every random number of word word_offset + s/64, lane
+ *   s % 64, so its trajectory is exactly that lane's in a multispin run.
+ *   Canonical layouts: spins int8 [r][w][s][tau][y][x], couplings int8
+ *   [s][d][y][x]; k labels and energies as above.  Ltau needs only be even.
+ *   Runs the per-shape schedule; tfim_measure (records in the plain
+ *   per-sample mode, buckets, energies) and tfim_measure_range (mode 1);
+ *   batched/concurrent schedules, the autotuner, three-replica and two-time
+ *   records and the debug dump return TFIM_EUNSUPPORTED. */
+#define TFIM_FORM_MULTISPIN 0u
+#define TFIM_FORM_PLAIN_I8 1u
+
 /* Device arena layout, in bytes (offsets are 256-byte aligned). */
 typedef struct {
     size_t total;     /* size of the arena to pass to tfim_bind */
@@ -96,11 +122,12 @@ typedef struct {
     size_t measure;   /* measurement records */
 } tfim_sizes;
 
-/* Create a plan for n_shapes shapes sampled together with one seed.
- * TFIM_EINVAL: odd or out-of-range L/Ltau, n_words = 0, bad ladder,
- * repeated stream_id, unknown bc_tau. */
+/* Create a plan for n_shapes shapes sampled together with one seed, in the
+ * given form (TFIM_FORM_MULTISPIN or TFIM_FORM_PLAIN_I8).
+ * TFIM_EINVAL: unknown form, odd or out-of-range L/Ltau, n_words = 0, bad
+ * ladder, repeated stream_id, unknown bc_tau. */
 tfim_status tfim_plan_create(const tfim_shape *shapes, uint32_t n_shapes, uint64_t seed,
-                             tfim_plan **plan_out);
+                             uint32_t form, tfim_plan **plan_out);
 void tfim_plan_destroy(tfim_plan *plan);
 
 /* Sizes of the device arena (host-only). */
@@ -113,23 +140,27 @@ tfim_status tfim_bind(tfim_plan *plan, void *device_arena, size_t arena_bytes,
 
 /* Instance (Methods, "Model and simulations": J = +-1 with probability 1/2).
  * J_host == NULL: draw the couplings on the device from the seed;
- * otherwise copy n_words*2*L*L canonical words from the host. */
-tfim_status tfim_init_couplings(tfim_plan *plan, uint32_t shape, const uint64_t *J_host);
+ * otherwise copy the canonical host array: n_words*2*L*L uint64 words
+ * (multispin) or samples*2*L*L int8 values +-1 (plain; anything else is
+ * TFIM_EINVAL). */
+tfim_status tfim_init_couplings(tfim_plan *plan, uint32_t shape, const void *J_host);
 
 /* Initial state: hot start (i.i.d. spins) when S_host == NULL, otherwise a
- * canonical host array of n_replicas*n_k*n_words*L*L*Ltau words.  Resets
- * k labels to the identity, recounts energies and sets t = m = 0 for the
- * whole plan.  Couplings must be initialised first (else TFIM_ESTATE). */
-tfim_status tfim_init_spins(tfim_plan *plan, uint32_t shape, const uint64_t *S_host);
+ * canonical host array of n_replicas*n_k*n_words*L*L*Ltau uint64 words
+ * (multispin) or n_replicas*n_k*samples*L*L*Ltau int8 values +-1 (plain).
+ * Resets k labels to the identity, recounts energies and sets t = m = 0 for
+ * the whole plan.  Couplings must be initialised first (else TFIM_ESTATE). */
+tfim_status tfim_init_spins(tfim_plan *plan, uint32_t shape, const void *S_host);
 
 /* n sweeps of every shape (Methods, "Simulation details"; Table I): a
  * checkerboard Metropolis sweep (colour 0 then colour 1), the energy
  * recount, and a tempering step after sweep t when pt_every > 0 and
- * (t+1) % pt_every == 0.  Asynchronous.  TFIM_EOVERFLOW if t would pass
- * 2^32 - 1. */
+ * (t+1) % pt_every == 0.  Asynchronous.  TFIM_EOVERFLOW, before anything is
+ * enqueued, if t + n would pass 2^32 - 1. */
 tfim_status tfim_sweep(tfim_plan *plan, uint64_t n);
 
-/* One explicit tempering step of every shape (uses and advances m). */
+/* One explicit tempering step of every shape (uses and advances m;
+ * TFIM_EOVERFLOW if m would pass 2^32 - 1). */
 tfim_status tfim_pt_swap(tfim_plan *plan);
 
 /* Measurement (Methods, "One-time observables"), synchronous.
@@ -277,9 +308,10 @@ tfim_status tfim_get_thresholds(const tfim_plan *plan, uint32_t shape, uint32_t 
                                 uint32_t *dmax, uint32_t *Tpt, size_t tpt_capacity,
                                 size_t *n_tpt);
 
-/* Copy state back in canonical layouts (synchronous). */
-tfim_status tfim_export_spins(tfim_plan *plan, uint32_t shape, uint64_t *S_host);
-tfim_status tfim_export_couplings(tfim_plan *plan, uint32_t shape, uint64_t *J_host);
+/* Copy state back in the form's canonical layouts (synchronous): uint64
+ * words (multispin) or int8 +-1 (plain). */
+tfim_status tfim_export_spins(tfim_plan *plan, uint32_t shape, void *S_host);
+tfim_status tfim_export_couplings(tfim_plan *plan, uint32_t shape, void *J_host);
 tfim_status tfim_get_state(tfim_plan *plan, uint32_t shape, uint8_t *kidx_host,
                            uint32_t *U_host);
 /* Sweep counter t and tempering counter m of a shape (they key its random
@@ -289,7 +321,7 @@ tfim_status tfim_get_counters(const tfim_plan *plan, uint32_t shape, uint64_t *t
 /* Restore a saved state: spins (canonical) and k labels of one shape, and
  * that shape's counters t, m; energies and lane masks are recomputed.  Resuming from
  * a saved state continues bit-for-bit. */
-tfim_status tfim_set_state(tfim_plan *plan, uint32_t shape, const uint64_t *S_host,
+tfim_status tfim_set_state(tfim_plan *plan, uint32_t shape, const void *S_host,
                            const uint8_t *kidx_host, uint64_t t, uint64_t m);
 
 /* Launch schedules of tfim_sweep (both give bit-identical spins, labels,

@@ -55,7 +55,10 @@ struct tfim_plan {
     char* arena = nullptr;
     hipStream_t stream = nullptr;
     bool bound = false;
-    bool poisoned = false;
+    bool poisoned = false;   // sticky: set by a device error, never cleared
+    uint32_t form = TFIM_FORM_MULTISPIN;
+    // failure injection (TFIM_FAIL_AFTER): the n-th enqueueing call fails
+    int64_t fail_after = 0;
     std::vector<uint64_t> t, m;  // host mirrors per shape
     uint32_t schedule = TFIM_SCHED_PER_SHAPE;
     int variant = 3;  // helper waves where L = 24, else the streaming kernel
@@ -142,6 +145,18 @@ tfim_status usable(tfim_plan* pl) {
     if (!pl->bound) return fail(TFIM_ESTATE, "plan not bound to a device arena");
     return TFIM_OK;
 }
+
+// Failure injection: counts the calls that enqueue device work; the
+// fail_after-th one enqueues nothing and fails as a device error does
+// (TFIM_EDEVICE, plan poisoned).  Off when fail_after is 0.
+tfim_status injected(tfim_plan* pl) {
+    if (pl->fail_after <= 0) return TFIM_OK;
+    if (--pl->fail_after > 0) return TFIM_OK;
+    pl->poisoned = true;
+    return fail(TFIM_EDEVICE, "injected device failure (TFIM_FAIL_AFTER)");
+}
+
+bool plain(const tfim_plan* pl) { return pl->form == TFIM_FORM_PLAIN_I8; }
 
 // Metropolis thresholds Tu[i][u] = floor(2^32 exp(-k_i (12 - 4u))) and the
 // swap tables, FP64 with the C library exp, x 2^32 exact, floor, clamp.
@@ -230,7 +245,8 @@ void build_buckets(ShapeHost& h) {
     if (h.btab.empty()) h.btab.push_back(0);
 }
 
-tfim_status validate(const tfim_shape* s, uint32_t n) {
+tfim_status validate(const tfim_shape* s, uint32_t n, uint32_t form) {
+    if (form != TFIM_FORM_MULTISPIN && form != TFIM_FORM_PLAIN_I8) return fail(TFIM_EINVAL, "unknown form");
     if (!s || n == 0 || n > 64) return fail(TFIM_EINVAL, "need 1..64 shapes");
     for (uint32_t i = 0; i < n; ++i) {
         const tfim_shape& a = s[i];
@@ -243,8 +259,10 @@ tfim_status validate(const tfim_shape* s, uint32_t n) {
             snprintf(buf, sizeof buf, "shape %u: Ltau=%u must be even in [4,65536]", i, a.Ltau);
             return fail(TFIM_EINVAL, buf);
         }
-        if (a.n_words == 0 || (uint64_t)a.word_offset + a.n_words > (1u << 20))
-            return fail(TFIM_EINVAL, "n_words must be >= 1 and word_offset+n_words <= 2^20");
+        // PLAIN_I8: n_words counts samples, sample s using word word_offset + s/64
+        const uint64_t words = form == TFIM_FORM_PLAIN_I8 ? ((uint64_t)a.n_words + 63) / 64 : a.n_words;
+        if (a.n_words == 0 || (uint64_t)a.word_offset + words > (1u << 20))
+            return fail(TFIM_EINVAL, "n_words must be >= 1 and the words used must end below 2^20");
         if (a.n_replicas == 0 || a.n_replicas > 64) return fail(TFIM_EINVAL, "n_replicas in 1..64");
         if (a.n_k == 0 || a.n_k > 255 || !a.k) return fail(TFIM_EINVAL, "n_k in 1..255 with k != NULL");
         if ((uint64_t)a.n_replicas * a.n_k >= (1u << 30)) return fail(TFIM_EINVAL, "too many walkers");
@@ -257,7 +275,7 @@ tfim_status validate(const tfim_shape* s, uint32_t n) {
             if (s[q].stream_id == a.stream_id) return fail(TFIM_EINVAL, "stream_id repeated in plan");
         if (a.bc_tau != TFIM_BC_PERIODIC && a.bc_tau != TFIM_BC_ANTIPERIODIC)
             return fail(TFIM_EINVAL, "unknown bc_tau");
-        if (a.Ltau % 8 != 0)
+        if (a.Ltau % 8 != 0 && form == TFIM_FORM_MULTISPIN)
             return fail(TFIM_EUNSUPPORTED, "the GPU sweep walks tau in chunks of 8: Ltau % 8 must be 0");
         // L^2 <= 1024 threads per workgroup
     }
@@ -283,13 +301,16 @@ const char* tfim_strerror(tfim_status st) {
 const char* tfim_last_error_detail(void) { return g_detail.c_str(); }
 
 tfim_status tfim_plan_create(const tfim_shape* shapes, uint32_t n_shapes, uint64_t seed,
-                             tfim_plan** out) {
+                             uint32_t form, tfim_plan** out) {
     if (!out) return fail(TFIM_EINVAL, "null output pointer");
     *out = nullptr;
-    tfim_status st = validate(shapes, n_shapes);
+    tfim_status st = validate(shapes, n_shapes, form);
     if (st != TFIM_OK) return st;
     tfim_plan* pl = new tfim_plan();
     pl->seed = seed;
+    pl->form = form;
+    const bool pf = form == TFIM_FORM_PLAIN_I8;
+    if (const char* fa = std::getenv("TFIM_FAIL_AFTER")) pl->fail_after = std::max(0ll, std::atoll(fa));
     size_t off = 0;
     size_t tot_S = 0, tot_J = 0, tot_lab = 0, tot_tab = 0, tot_meas = 0;
     for (uint32_t i = 0; i < n_shapes; ++i) {
@@ -301,19 +322,25 @@ tfim_status tfim_plan_create(const tfim_shape* shapes, uint32_t n_shapes, uint64
         build_tables(h);
         build_buckets(h);
         const size_t L2 = (size_t)h.s.L * h.s.L, nk = h.s.n_k, W = h.s.n_words,
-                     R = h.s.n_replicas, Lt = h.s.Ltau, S = 64 * W;
-        h.nS = R * nk * W * Lt * L2 * 8;
-        h.nJ = W * 2 * L2 * 8;
-        h.nLab = R * S * nk;
-        h.nMask = R * W * nk * (nk + 1) * 8;
-        h.nRec = h.P ? nk * S * h.P * (2 * h.s.L + 3) * 8 : 0;
-        h.nBuck = nk * 2 * h.s.L * 8;
+                     R = h.s.n_replicas, Lt = h.s.Ltau, S = pf ? W : 64 * W;
         h.nc = (int)((Lt + 63) / 64);
         h.nx = (int)((L2 + 63) / 64);
-        // bit layouts for every measurement, the one-replica two-time records included
-        h.nPt = nk * S * R * (size_t)h.nc * 64 * h.nx * 8;
-        h.nPx = nk * S * R * (size_t)h.nx * Lt * 8;
-        h.nDump = h.P ? (2 * L2 * L2 + Lt * Lt) * 4 : 0;
+        h.nLab = R * S * nk;
+        h.nRec = h.P ? nk * S * h.P * (2 * h.s.L + 3) * 8 : 0;
+        h.nBuck = nk * 2 * h.s.L * 8;
+        if (pf) {
+            // one byte per spin and coupling; no lane masks or bit layouts
+            h.nS = R * nk * S * Lt * L2;
+            h.nJ = S * 2 * L2;
+        } else {
+            h.nS = R * nk * W * Lt * L2 * 8;
+            h.nJ = W * 2 * L2 * 8;
+            h.nMask = R * W * nk * (nk + 1) * 8;
+            // bit layouts for every measurement, the one-replica two-time records included
+            h.nPt = nk * S * R * (size_t)h.nc * 64 * h.nx * 8;
+            h.nPx = nk * S * R * (size_t)h.nx * Lt * 8;
+            h.nDump = h.P ? (2 * L2 * L2 + Lt * Lt) * 4 : 0;
+        }
         h.oS = off; off = align256(off + h.nS); tot_S += h.nS;
         h.oJ = off; off = align256(off + h.nJ); tot_J += h.nJ;
         h.oK = off; off = align256(off + h.nLab);
@@ -395,10 +422,10 @@ tfim_status tfim_bind(tfim_plan* pl, void* arena, size_t bytes, void* stream) {
     if (!pl || !arena) return fail(TFIM_EINVAL, "null plan or arena");
     if (bytes < pl->sizes.total) return fail(TFIM_EINVAL, "arena smaller than tfim_sizes.total");
     if (((uintptr_t)arena & 255) != 0) return fail(TFIM_EINVAL, "arena must be 256-byte aligned");
+    if (pl->poisoned) return fail(TFIM_ESTATE, "plan poisoned by an earlier device error");
     pl->arena = (char*)arena;
     pl->stream = (hipStream_t)stream;
     pl->bound = true;
-    pl->poisoned = false;
     drop_graphs(pl);
     pl->batch_threads = pl->batch_bpc = pl->batch_blocks = 0;
     pl->tables_up = false;
@@ -451,15 +478,28 @@ static tfim_status reset_counters(tfim_plan* pl) {
     return check_hip(pl, e, "reset counters");
 }
 
-tfim_status tfim_init_couplings(tfim_plan* pl, uint32_t shape, const uint64_t* J_host) {
+// Plain-form host arrays must hold +1 / -1 bytes only.
+static bool plus_minus_one(const void* p, size_t n) {
+    const int8_t* b = (const int8_t*)p;
+    for (size_t i = 0; i < n; ++i)
+        if (b[i] != 1 && b[i] != -1) return false;
+    return true;
+}
+
+tfim_status tfim_init_couplings(tfim_plan* pl, uint32_t shape, const void* J_host) {
     tfim_status st = shape_ok(pl, shape);
     if (st != TFIM_OK) return st;
     ShapeHost& h = pl->shapes[shape];
+    if (J_host && plain(pl) && !plus_minus_one(J_host, h.nJ))
+        return fail(TFIM_EINVAL, "plain-form couplings must be +1 or -1");
+    if ((st = injected(pl)) != TFIM_OK) return st;
     const tfim::ShapeDev d = dev_of(pl, shape);
     hipError_t e;
     if (J_host) {
         e = hipMemcpyAsync(d.J, J_host, h.nJ, hipMemcpyHostToDevice, pl->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(pl->stream);
+    } else if (plain(pl)) {
+        e = tfim::plain_init_couplings(d, pl->seed, pl->stream);
     } else {
         e = tfim::launch_init_couplings(d, pl->seed, pl->stream);
     }
@@ -473,21 +513,27 @@ tfim_status tfim_init_couplings(tfim_plan* pl, uint32_t shape, const uint64_t* J
 
 static hipError_t refresh_derived(tfim_plan* pl, uint32_t shape) {
     const tfim::ShapeDev d = dev_of(pl, shape);
+    if (plain(pl)) return tfim::plain_energy(d, pl->stream);
     hipError_t e = tfim::launch_energy(d, pl->stream);
     if (e == hipSuccess) e = tfim::launch_mask_rebuild(d, pl->stream);
     return e;
 }
 
-tfim_status tfim_init_spins(tfim_plan* pl, uint32_t shape, const uint64_t* S_host) {
+tfim_status tfim_init_spins(tfim_plan* pl, uint32_t shape, const void* S_host) {
     tfim_status st = shape_ok(pl, shape);
     if (st != TFIM_OK) return st;
     ShapeHost& h = pl->shapes[shape];
     if (!h.J_ready) return fail(TFIM_ESTATE, "couplings of this shape are not initialised");
+    if (S_host && plain(pl) && !plus_minus_one(S_host, h.nS))
+        return fail(TFIM_EINVAL, "plain-form spins must be +1 or -1");
+    if ((st = injected(pl)) != TFIM_OK) return st;
     const tfim::ShapeDev d = dev_of(pl, shape);
     hipError_t e;
     if (S_host) {
         e = hipMemcpyAsync(d.S, S_host, h.nS, hipMemcpyHostToDevice, pl->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(pl->stream);
+    } else if (plain(pl)) {
+        e = tfim::plain_init_spins(d, pl->seed, pl->stream);
     } else {
         e = tfim::launch_init_spins(d, pl->seed, pl->stream);
     }
@@ -534,10 +580,17 @@ static hipError_t timing_end(tfim_plan* pl, std::pair<hipEvent_t, hipEvent_t>& e
 static hipError_t timed_sweep(tfim_plan* pl, int i, bool energy) {
     std::pair<hipEvent_t, hipEvent_t> ev;
     hipError_t e = timing_begin(pl, ev);
-    if (e == hipSuccess)
+    if (e == hipSuccess && plain(pl))
+        e = tfim::plain_sweep(dev_of(pl, i), pl->seed, counters_of(pl, i), pl->stream);
+    else if (e == hipSuccess)
         e = tfim::launch_sweep(dev_of(pl, i), pl->seed, counters_of(pl, i), pl->variant, energy,
                                pl->stream);
     return timing_end(pl, ev, 1, e);
+}
+
+static hipError_t temper(tfim_plan* pl, int i) {
+    if (plain(pl)) return tfim::plain_temper(dev_of(pl, i), pl->seed, counters_of(pl, i), pl->stream);
+    return tfim::launch_temper(dev_of(pl, i), pl->seed, counters_of(pl, i), pl->stream);
 }
 
 // Enqueue one sweep of every shape (plus due tempering) with the per-shape
@@ -554,7 +607,7 @@ static hipError_t enqueue_sweep(tfim_plan* pl, bool last) {
     for (int i = 0; i < ns && e == hipSuccess; ++i) {
         const uint32_t pe = pl->shapes[i].s.pt_every;
         const bool due = pe > 0 && ((pl->t[i] + 1) % pe) == 0;
-        if (due) e = tfim::launch_temper(dev_of(pl, i), pl->seed, counters_of(pl, i), pl->stream);
+        if (due) e = temper(pl, i);
         if (e == hipSuccess) e = tfim::launch_advance(counters_of(pl, i), 1u, due ? 1u : 0u, pl->stream);
     }
     return e;
@@ -787,7 +840,8 @@ static tfim_status sweep_impl(tfim_plan* pl, uint64_t n) {
     if ((st = all_ready(pl)) != TFIM_OK) return st;
     if (n == 0) return TFIM_OK;
     for (size_t i = 0; i < pl->shapes.size(); ++i)
-        if (pl->t[i] + n > 0xFFFFFFFFull) return fail(TFIM_EOVERFLOW, "sweep counter would pass 2^32-1");
+        if (n > 0xFFFFFFFFull - pl->t[i]) return fail(TFIM_EOVERFLOW, "sweep counter would pass 2^32-1");
+    if ((st = injected(pl)) != TFIM_OK) return st;
     // host mirrors of the counters: tempering after sweeps t+1 .. t+n that
     // are multiples of pt_every
     auto advance = [pl](uint64_t k) {
@@ -816,10 +870,12 @@ tfim_status tfim_pt_swap(tfim_plan* pl) {
     tfim_status st = usable(pl);
     if (st != TFIM_OK) return st;
     if ((st = all_ready(pl)) != TFIM_OK) return st;
+    for (size_t i = 0; i < pl->shapes.size(); ++i)
+        if (pl->m[i] >= 0xFFFFFFFFull) return fail(TFIM_EOVERFLOW, "tempering counter overflow");
+    if ((st = injected(pl)) != TFIM_OK) return st;
     hipError_t e = hipSuccess;
     for (size_t i = 0; i < pl->shapes.size() && e == hipSuccess; ++i) {
-        if (pl->m[i] + 1 > 0xFFFFFFFFull) return fail(TFIM_EOVERFLOW, "tempering counter overflow");
-        e = tfim::launch_temper(dev_of(pl, (int)i), pl->seed, counters_of(pl, (int)i), pl->stream);
+        e = temper(pl, (int)i);
         if (e == hipSuccess) e = tfim::launch_advance(counters_of(pl, (int)i), 0u, 1u, pl->stream);
         pl->m[i] += 1;
     }
@@ -838,7 +894,7 @@ static tfim_status copy_back(tfim_plan* pl, void* dst, const void* src, size_t n
     return check_hip(pl, e, what);
 }
 
-tfim_status tfim_export_spins(tfim_plan* pl, uint32_t shape, uint64_t* S_host) {
+tfim_status tfim_export_spins(tfim_plan* pl, uint32_t shape, void* S_host) {
     tfim_status st = shape_ok(pl, shape);
     if (st != TFIM_OK) return st;
     if (!S_host) return fail(TFIM_EINVAL, "null host pointer");
@@ -846,7 +902,7 @@ tfim_status tfim_export_spins(tfim_plan* pl, uint32_t shape, uint64_t* S_host) {
     return copy_back(pl, S_host, pl->arena + h.oS, h.nS, "export spins");
 }
 
-tfim_status tfim_export_couplings(tfim_plan* pl, uint32_t shape, uint64_t* J_host) {
+tfim_status tfim_export_couplings(tfim_plan* pl, uint32_t shape, void* J_host) {
     tfim_status st = shape_ok(pl, shape);
     if (st != TFIM_OK) return st;
     if (!J_host) return fail(TFIM_EINVAL, "null host pointer");
@@ -871,13 +927,14 @@ tfim_status tfim_get_counters(const tfim_plan* pl, uint32_t shape, uint64_t* t, 
     return TFIM_OK;
 }
 
-tfim_status tfim_set_state(tfim_plan* pl, uint32_t shape, const uint64_t* S_host,
+tfim_status tfim_set_state(tfim_plan* pl, uint32_t shape, const void* S_host,
                            const uint8_t* kidx_host, uint64_t t, uint64_t m) {
     tfim_status st = shape_ok(pl, shape);
     if (st != TFIM_OK) return st;
     ShapeHost& h = pl->shapes[shape];
     if (!h.J_ready) return fail(TFIM_ESTATE, "couplings of this shape are not initialised");
     if (!S_host || !kidx_host) return fail(TFIM_EINVAL, "null host pointer");
+    if (plain(pl) && !plus_minus_one(S_host, h.nS)) return fail(TFIM_EINVAL, "plain-form spins must be +1 or -1");
     if (t > 0xFFFFFFFFull || m > 0xFFFFFFFFull) return fail(TFIM_EOVERFLOW, "counter beyond 2^32-1");
     const size_t nk = h.s.n_k;
     std::vector<uint8_t> winv(h.nLab);
@@ -890,6 +947,7 @@ tfim_status tfim_set_state(tfim_plan* pl, uint32_t shape, const uint64_t* S_host
             winv[g * nk + i] = (uint8_t)w;
         }
     }
+    if ((st = injected(pl)) != TFIM_OK) return st;
     const tfim::ShapeDev d = dev_of(pl, shape);
     hipError_t e = hipMemcpyAsync(d.S, S_host, h.nS, hipMemcpyHostToDevice, pl->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(d.kidx, kidx_host, h.nLab, hipMemcpyHostToDevice, pl->stream);
@@ -1103,6 +1161,8 @@ tfim_status tfim_set_schedule(tfim_plan* pl, uint32_t schedule) {
     if (schedule != TFIM_SCHED_PER_SHAPE && schedule != TFIM_SCHED_BATCHED &&
         schedule != TFIM_SCHED_CONCURRENT)
         return fail(TFIM_EINVAL, "unknown schedule");
+    if (schedule != TFIM_SCHED_PER_SHAPE && plain(pl))
+        return fail(TFIM_EUNSUPPORTED, "the plain form runs the per-shape schedule only");
     if (schedule == TFIM_SCHED_BATCHED) {
         tfim_status st = usable(pl);
         if (st != TFIM_OK) return st;
@@ -1120,6 +1180,7 @@ tfim_status tfim_set_schedule(tfim_plan* pl, uint32_t schedule) {
 tfim_status tfim_set_batch(tfim_plan* pl, uint32_t threads, uint32_t blocks_per_cu) {
     tfim_status st = usable(pl);
     if (st != TFIM_OK) return st;
+    if (plain(pl)) return fail(TFIM_EUNSUPPORTED, "the plain form runs the per-shape schedule only");
     return batch_setup(pl, threads, blocks_per_cu);
 }
 
@@ -1224,6 +1285,7 @@ tfim_status tfim_autotune(tfim_plan* pl, uint32_t sweeps_per_trial, const char* 
     if ((st = all_ready(pl)) != TFIM_OK) return st;
     if (sweeps_per_trial == 0) return fail(TFIM_EINVAL, "sweeps_per_trial must be >= 1");
     if (sweeps_done) *sweeps_done = 0;
+    if (plain(pl)) return fail(TFIM_EUNSUPPORTED, "the plain form has one launch configuration");
     const std::string key = tune_key(pl);
     Choice c;
     if (cache_path && cache_lookup(cache_path, key, &c)) {
@@ -1322,15 +1384,29 @@ tfim_status tfim_get_tuning(const tfim_plan* pl, tfim_tuning* out) {
     return TFIM_OK;
 }
 
+static uint64_t samples_of(const tfim_plan* pl, const ShapeHost& h) {
+    return plain(pl) ? (uint64_t)h.s.n_words : 64ull * h.s.n_words;
+}
+
 static tfim_status measure_core(tfim_plan* pl, uint32_t shape, uint32_t mode, uint32_t cfg0,
                                 uint32_t ncfg, uint32_t flags) {
     ShapeHost& h = pl->shapes[shape];
     if (!h.S_ready) return fail(TFIM_ESTATE, "spins of this shape are not initialised");
     const tfim::ShapeDev d = dev_of(pl, shape);
-    if (!tfim::measure_ok(d)) return fail(TFIM_EUNSUPPORTED, "measurement needs 2..6 replicas and L <= 32");
-    const uint64_t ncfg_all = (uint64_t)h.s.n_k * 64 * h.s.n_words;
-    if ((uint64_t)cfg0 + ncfg > ncfg_all) return fail(TFIM_EINVAL, "configuration range out of bounds");
+    const uint64_t ncfg_all = (uint64_t)h.s.n_k * samples_of(pl, h);
     if (mode > 1) return fail(TFIM_EINVAL, "unknown measurement mode");
+    if (plain(pl)) {
+        if (!tfim::plain_measure_ok(d)) return fail(TFIM_EUNSUPPORTED, "measurement needs 2..6 replicas");
+        if (mode != 1) return fail(TFIM_EUNSUPPORTED, "the plain form measures in the plain per-sample mode (1)");
+        if ((uint64_t)cfg0 + ncfg > ncfg_all) return fail(TFIM_EINVAL, "configuration range out of bounds");
+        tfim_status st = injected(pl);
+        if (st != TFIM_OK) return st;
+        return check_hip(pl, tfim::plain_measure(d, (int)cfg0, (int)ncfg, pl->stream), "measure");
+    }
+    if (!tfim::measure_ok(d)) return fail(TFIM_EUNSUPPORTED, "measurement needs 2..6 replicas and L <= 32");
+    if ((uint64_t)cfg0 + ncfg > ncfg_all) return fail(TFIM_EINVAL, "configuration range out of bounds");
+    tfim_status st = injected(pl);
+    if (st != TFIM_OK) return st;
     const size_t rl = (size_t)(2 * h.s.L + 3) * h.P * 8;
     hipError_t e = hipMemsetAsync(pl->arena + h.oRec + (size_t)cfg0 * rl, 0, (size_t)ncfg * rl, pl->stream);
     if (e == hipSuccess && !(flags & TFIM_MEASURE_REUSE_LAYOUT)) e = tfim::launch_transpose(d, pl->stream);
@@ -1343,7 +1419,7 @@ tfim_status tfim_measure(tfim_plan* pl, uint32_t shape, uint32_t what, void* out
     if (st != TFIM_OK) return st;
     ShapeHost& h = pl->shapes[shape];
     if (!out) return fail(TFIM_EINVAL, "null host pointer");
-    const size_t S = 64 * (size_t)h.s.n_words, nk = h.s.n_k, R = h.s.n_replicas;
+    const size_t S = samples_of(pl, h), nk = h.s.n_k, R = h.s.n_replicas;
     if (what == TFIM_MEASURE_ENERGY) {
         if (bytes < R * S * nk * 4) return fail(TFIM_EINVAL, "output buffer too small");
         std::vector<uint8_t> winv(h.nLab);
@@ -1359,9 +1435,11 @@ tfim_status tfim_measure(tfim_plan* pl, uint32_t shape, uint32_t what, void* out
         return fail(TFIM_EINVAL, "unknown measurement");
     const size_t need = what == TFIM_MEASURE_RECORDS ? h.nRec : h.nBuck;
     if (bytes < need) return fail(TFIM_EINVAL, "output buffer too small");
-    if ((st = measure_core(pl, shape, pl->measure_mode, 0, (uint32_t)(nk * S), 0)) != TFIM_OK) return st;
+    const uint32_t mode = plain(pl) ? 1u : pl->measure_mode;
+    if ((st = measure_core(pl, shape, mode, 0, (uint32_t)(nk * S), 0)) != TFIM_OK) return st;
     if (what == TFIM_MEASURE_BUCKETS) {
-        const hipError_t e = tfim::launch_buckets(dev_of(pl, (int)shape), pl->stream);
+        const tfim::ShapeDev d = dev_of(pl, (int)shape);
+        const hipError_t e = plain(pl) ? tfim::plain_buckets(d, pl->stream) : tfim::launch_buckets(d, pl->stream);
         if ((st = check_hip(pl, e, "buckets")) != TFIM_OK) return st;
         return copy_back(pl, out, pl->arena + h.oBuck, h.nBuck, "copy buckets");
     }
@@ -1384,6 +1462,7 @@ tfim_status tfim_triples_workspace(const tfim_plan* pl, uint32_t shape, uint32_t
                                    size_t* bytes) {
     if (!pl || !bytes) return fail(TFIM_EINVAL, "null argument");
     if (shape >= pl->shapes.size()) return fail(TFIM_EINVAL, "shape index out of range");
+    if (plain(pl)) return fail(TFIM_EUNSUPPORTED, "three-replica records need the multispin form");
     const tfim::ShapeDev d = dev_of(pl, shape);
     if (const char* why = tfim::triples_unsupported(d)) return fail(TFIM_EUNSUPPORTED, why);
     const tfim::TripleLayout lay = tfim::triple_layout(d, (int)ncfg);
@@ -1397,6 +1476,7 @@ tfim_status tfim_measure_triples(tfim_plan* pl, uint32_t shape, uint32_t cfg0, u
     tfim_status st = shape_ok(pl, shape);
     if (st != TFIM_OK) return st;
     ShapeHost& h = pl->shapes[shape];
+    if (plain(pl)) return fail(TFIM_EUNSUPPORTED, "three-replica records need the multispin form");
     if (!h.S_ready) return fail(TFIM_ESTATE, "spins of this shape are not initialised");
     const tfim::ShapeDev d = dev_of(pl, shape);
     if (const char* why = tfim::triples_unsupported(d)) return fail(TFIM_EUNSUPPORTED, why);
@@ -1409,6 +1489,7 @@ tfim_status tfim_measure_triples(tfim_plan* pl, uint32_t shape, uint32_t cfg0, u
     const size_t rec_used = (size_t)ncfg * (R * (R - 1) * (R - 2) / 6) * 2 * h.s.L * 8;
     if (out && out_bytes < rec_used) return fail(TFIM_EINVAL, "output buffer too small");
     if (ncfg == 0) return TFIM_OK;
+    if ((st = injected(pl)) != TFIM_OK) return st;
     hipError_t e = hipSuccess;
     if (!(flags & TFIM_MEASURE_REUSE_LAYOUT)) e = tfim::launch_transpose(d, pl->stream);
     if (e == hipSuccess) e = tfim::launch_triples(d, (int)cfg0, (int)ncfg, ws, pl->stream);
@@ -1423,6 +1504,7 @@ tfim_status tfim_measure_time(tfim_plan* pl, uint32_t shape, uint32_t cfg0, uint
     tfim_status st = shape_ok(pl, shape);
     if (st != TFIM_OK) return st;
     ShapeHost& h = pl->shapes[shape];
+    if (plain(pl)) return fail(TFIM_EUNSUPPORTED, "two-time records need the multispin form");
     if (!h.S_ready) return fail(TFIM_ESTATE, "spins of this shape are not initialised");
     const tfim::ShapeDev d = dev_of(pl, shape);
     if (const char* why = tfim::timecorr_unsupported(d)) return fail(TFIM_EUNSUPPORTED, why);
@@ -1433,6 +1515,7 @@ tfim_status tfim_measure_time(tfim_plan* pl, uint32_t shape, uint32_t cfg0, uint
     if (ws_bytes < need) return fail(TFIM_EINVAL, "workspace too small");
     if (out && out_bytes < need) return fail(TFIM_EINVAL, "output buffer too small");
     if (ncfg == 0) return TFIM_OK;
+    if ((st = injected(pl)) != TFIM_OK) return st;
     hipError_t e = hipSuccess;
     if (!(flags & TFIM_MEASURE_REUSE_LAYOUT)) e = tfim::launch_transpose(d, pl->stream);
     if (e == hipSuccess) e = tfim::launch_timecorr(d, (int)cfg0, (int)ncfg, (int64_t*)ws, pl->stream);
@@ -1453,6 +1536,7 @@ tfim_status tfim_dump_gram(tfim_plan* pl, uint32_t shape, uint32_t i, uint32_t s
     tfim_status st = shape_ok(pl, shape);
     if (st != TFIM_OK) return st;
     ShapeHost& h = pl->shapes[shape];
+    if (plain(pl)) return fail(TFIM_EUNSUPPORTED, "the debug dump needs the multispin form");
     if (!h.S_ready) return fail(TFIM_ESTATE, "spins of this shape are not initialised");
     const size_t S = 64 * (size_t)h.s.n_words;
     if (i >= h.s.n_k || s >= S || a >= h.s.n_replicas || b >= h.s.n_replicas)

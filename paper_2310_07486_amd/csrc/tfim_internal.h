@@ -213,4 +213,16 @@ hipError_t tm_top(int L, double k, const int8_t* Jx, const int8_t* Jy, int odd, 
                   int max_iter, void* ws, double* lambda, int* iters, hipStream_t st);
 int sweep_variants();
 const char* sweep_variant_name(int v);
+// Plain form (one int8 per spin, one sample per configuration; ShapeDev.W
+// holds the number of samples, S and J point at int8 arrays).
+hipError_t plain_init_couplings(const ShapeDev& sh, uint64_t seed, hipStream_t st);
+hipError_t plain_init_spins(const ShapeDev& sh, uint64_t seed, hipStream_t st);
+hipError_t plain_energy(const ShapeDev& sh, hipStream_t st);
+// colour 0, colour 1 and the energy recount of one sweep
+hipError_t plain_sweep(const ShapeDev& sh, uint64_t seed, const Counters* ctr, hipStream_t st);
+hipError_t plain_temper(const ShapeDev& sh, uint64_t seed, const Counters* ctr, hipStream_t st);
+bool plain_measure_ok(const ShapeDev& sh);
+// pair records of configurations cfg0 .. cfg0+ncfg-1 (zeroed first)
+hipError_t plain_measure(const ShapeDev& sh, int cfg0, int ncfg, hipStream_t st);
+hipError_t plain_buckets(const ShapeDev& sh, hipStream_t st);
 }  // namespace tfim

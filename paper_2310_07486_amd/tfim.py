@@ -30,6 +30,8 @@ TFIM_MEASURE_ENERGY = 3
 TFIM_SCHED_BATCHED = 0
 TFIM_SCHED_PER_SHAPE = 1
 TFIM_SCHED_CONCURRENT = 2
+TFIM_FORM_MULTISPIN = 0
+TFIM_FORM_PLAIN_I8 = 1
 
 # Every symbol include/tfim.h declares.
 SYMBOLS = [
@@ -93,7 +95,7 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         P, U32, U64, SZ = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t
         sig = {
-            "tfim_plan_create": [P, U32, U64, P],
+            "tfim_plan_create": [P, U32, U64, U32, P],
             "tfim_plan_destroy": [P],
             "tfim_plan_sizes": [P, P],
             "tfim_bind": [P, P, SZ, P],
@@ -223,12 +225,15 @@ class Plan:
     """A plan over one or more shapes; owns a torch device arena.
 
     shapes: sequence of objects with L, Ltau, n_words, n_replicas, k,
-    pt_every, stream_id, word_offset (see workloads.Shape)."""
+    pt_every, stream_id, word_offset (see workloads.Shape).
+    form: TFIM_FORM_MULTISPIN (64 samples per word) or TFIM_FORM_PLAIN_I8
+    (one int8 per spin; n_words then counts samples)."""
 
     def __init__(self, shapes: Sequence, seed: int, *, device: str = "cuda", stream=None,
-                 bind: bool = True):
+                 bind: bool = True, form: int = TFIM_FORM_MULTISPIN):
         self.shapes = list(shapes)
         self.seed = int(seed)
+        self.form = int(form)
         self._k = [np.ascontiguousarray(np.asarray(s.k, dtype=np.float64)) for s in self.shapes]
         arr = (tfim_shape * len(self.shapes))()
         for i, s in enumerate(self.shapes):
@@ -239,7 +244,7 @@ class Plan:
                                 getattr(s, "stream_id", i))
         self._arr = arr
         h = ctypes.c_void_p()
-        _check(lib().tfim_plan_create(arr, len(self.shapes), self.seed, ctypes.byref(h)),
+        _check(lib().tfim_plan_create(arr, len(self.shapes), self.seed, self.form, ctypes.byref(h)),
                "tfim_plan_create")
         self._h = h
         sz = tfim_sizes()
@@ -282,14 +287,27 @@ class Plan:
         s = self.shapes[shape]
         return s.L, s.Ltau, s.n_words, s.n_replicas, len(self._k[shape])
 
+    @property
+    def plain(self) -> bool:
+        return self.form == TFIM_FORM_PLAIN_I8
+
+    def samples(self, shape: int = 0) -> int:
+        """Disorder samples of a shape (64 per word, or n_words in the plain form)."""
+        W = self.shapes[shape].n_words
+        return W if self.plain else 64 * W
+
     # -- ABI calls -------------------------------------------------------------
+    def _host(self, a):
+        return np.ascontiguousarray(a, dtype=np.int8 if self.plain else np.uint64)
+
     def init_couplings(self, shape: int = 0, J: Optional[np.ndarray] = None):
-        p = None if J is None else _ptr(np.ascontiguousarray(J, dtype=np.uint64))
-        _check(lib().tfim_init_couplings(self._h, shape, p), "tfim_init_couplings")
+        J = None if J is None else self._host(J)
+        _check(lib().tfim_init_couplings(self._h, shape, None if J is None else _ptr(J)),
+               "tfim_init_couplings")
 
     def init_spins(self, shape: int = 0, S: Optional[np.ndarray] = None):
-        p = None if S is None else _ptr(np.ascontiguousarray(S, dtype=np.uint64))
-        _check(lib().tfim_init_spins(self._h, shape, p), "tfim_init_spins")
+        S = None if S is None else self._host(S)
+        _check(lib().tfim_init_spins(self._h, shape, None if S is None else _ptr(S)), "tfim_init_spins")
 
     def init(self):
         for i in range(len(self.shapes)):
@@ -298,6 +316,8 @@ class Plan:
             self.init_spins(i)
 
     def sweep(self, n: int = 1):
+        if int(n) < 0:
+            raise ValueError("number of sweeps must be >= 0")
         _check(lib().tfim_sweep(self._h, int(n)), "tfim_sweep")
 
     def pt_swap(self):
@@ -339,21 +359,24 @@ class Plan:
         return {n: getattr(t, n) for n, _ in tfim_tuning._fields_}
 
     def export_spins(self, shape: int = 0) -> np.ndarray:
+        """Multispin: uint64 [r][w][j][tau][xy]; plain: int8 [r][w][s][tau][xy]."""
         L, Lt, W, R, nk = self._dims(shape)
-        S = np.zeros((R, nk, W, Lt, L * L), dtype=np.uint64)
+        S = np.zeros((R, nk, W, Lt, L * L), dtype=np.int8 if self.plain else np.uint64)
         _check(lib().tfim_export_spins(self._h, shape, _ptr(S)), "tfim_export_spins")
         return S
 
     def export_couplings(self, shape: int = 0) -> np.ndarray:
+        """Multispin: uint64 [j][d][xy]; plain: int8 [s][d][xy]."""
         L, Lt, W, R, nk = self._dims(shape)
-        J = np.zeros((W, 2, L * L), dtype=np.uint64)
+        J = np.zeros((W, 2, L * L), dtype=np.int8 if self.plain else np.uint64)
         _check(lib().tfim_export_couplings(self._h, shape, _ptr(J)), "tfim_export_couplings")
         return J
 
     def get_state(self, shape: int = 0):
         L, Lt, W, R, nk = self._dims(shape)
-        kidx = np.zeros((R, 64 * W, nk), dtype=np.uint8)
-        U = np.zeros((R, 64 * W, nk), dtype=np.uint32)
+        S = self.samples(shape)
+        kidx = np.zeros((R, S, nk), dtype=np.uint8)
+        U = np.zeros((R, S, nk), dtype=np.uint32)
         _check(lib().tfim_get_state(self._h, shape, _ptr(kidx), _ptr(U)), "tfim_get_state")
         return kidx, U
 
@@ -365,7 +388,7 @@ class Plan:
         return t.value, m.value
 
     def set_state(self, shape: int, S: np.ndarray, kidx: np.ndarray, t: int, m: int):
-        _check(lib().tfim_set_state(self._h, shape, _ptr(np.ascontiguousarray(S, dtype=np.uint64)),
+        _check(lib().tfim_set_state(self._h, shape, _ptr(self._host(S)),
                                     _ptr(np.ascontiguousarray(kidx, dtype=np.uint8)), t, m),
                "tfim_set_state")
 
@@ -384,12 +407,13 @@ class Plan:
     def measure(self, shape: int = 0, what: int = TFIM_MEASURE_RECORDS) -> np.ndarray:
         L, Lt, W, R, nk = self._dims(shape)
         P = R * (R - 1) // 2
+        S = self.samples(shape)
         if what == TFIM_MEASURE_RECORDS:
-            out = np.zeros((nk, 64 * W, P, 2 * L + 3), dtype=np.int64)
+            out = np.zeros((nk, S, P, 2 * L + 3), dtype=np.int64)
         elif what == TFIM_MEASURE_BUCKETS:
             out = np.zeros((nk, 2, L), dtype=np.int64)
         elif what == TFIM_MEASURE_ENERGY:
-            out = np.zeros((R, 64 * W, nk), dtype=np.uint32)
+            out = np.zeros((R, S, nk), dtype=np.uint32)
         else:
             raise ValueError("unknown measurement")
         _check(lib().tfim_measure(self._h, shape, what, _ptr(out), out.nbytes), "tfim_measure")
@@ -475,9 +499,9 @@ class Plan:
         return Ga, Gb, Q
 
 
-def plan_shapes_only(shapes: Sequence, seed: int) -> Plan:
+def plan_shapes_only(shapes: Sequence, seed: int, form: int = TFIM_FORM_MULTISPIN) -> Plan:
     """A plan without a device arena (host-only calls: sizes, thresholds)."""
-    return Plan(shapes, seed, bind=False)
+    return Plan(shapes, seed, bind=False, form=form)
 
 
 def unpack_lane(words: np.ndarray, b: int) -> np.ndarray:

@@ -59,10 +59,12 @@ class Workload:
 
 
 def c1_plain() -> Workload:
-    """One disorder sample, L=8, Ltau=32, k=0.29, two replicas, 2000 sweeps
-    (run as lane 0 of one multispin word)."""
+    """One disorder sample, L=8, Ltau=32, k=0.29, two replicas, no tempering,
+    2000 sweeps, in the plain one-byte-per-spin form (n_words counts samples
+    there); the same shape in the multispin form runs it as lane 0 of one
+    word."""
     return Workload("plain-L8-Lt32-k0.29", [Shape(8, 32, 1, 2, [0.29], pt_every=0)],
-                    SEED_BASE + 1, sweeps=2000)
+                    SEED_BASE + 1, sweeps=2000, extra={"form": "plain_i8"})
 
 
 def c2_multispin() -> Workload:

@@ -208,3 +208,28 @@ def test_paper_schedule_rows_and_the_L24_arena():
     assert p.sizes["spins"] == 6 * 60 * 20 * 24 ** 2 * 2048 * 8  # 67.95 GB
     assert p.sizes["total"] < 250e9
     p.close()
+
+
+def test_plain_form_sizes_and_validation():
+    """The plain form (one int8 per spin; n_words counts samples) sizes its
+    spins at one byte each and accepts any even Ltau; an unknown form is
+    refused."""
+    s = Shape(8, 30, 5, 2, [0.2, 0.3], pt_every=1)
+    with pytest.raises(tfim.TfimError) as e:
+        _plan([s])
+    assert e.value.status == tfim.TFIM_EUNSUPPORTED  # multispin needs Ltau % 8 == 0
+    p = tfim.plan_shapes_only([s], 1, form=tfim.TFIM_FORM_PLAIN_I8)
+    assert p.sizes["spins"] == 2 * 2 * 5 * 64 * 30
+    assert p.sizes["couplings"] == 5 * 2 * 64
+    assert p.samples(0) == 5
+    p.close()
+    with pytest.raises(tfim.TfimError) as e:
+        tfim.plan_shapes_only([s], 1, form=7)
+    assert e.value.status == tfim.TFIM_EINVAL
+    # the words a plain shape draws from must end below 2^20
+    big = Shape(8, 32, 65, 2, [0.2], word_offset=(1 << 20) - 1)
+    with pytest.raises(tfim.TfimError) as e:
+        tfim.plan_shapes_only([big], 1, form=tfim.TFIM_FORM_PLAIN_I8)
+    assert e.value.status == tfim.TFIM_EINVAL
+    big.n_words = 64
+    tfim.plan_shapes_only([big], 1, form=tfim.TFIM_FORM_PLAIN_I8).close()

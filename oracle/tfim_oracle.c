@@ -155,13 +155,13 @@ int64_t oracle_action(int L, int Ltau, int bc, const int8_t *S, const int8_t *Jx
     int64_t E = 0;
     for (int tau = 0; tau < Ltau; ++tau) {
         const int8_t *P = S + (size_t)tau * L2;
-        const int8_t *Pn = S + (size_t)((tau + 1) % Ltau) * L2;
+        const int8_t *Pn = S + (size_t)(tau + 1 == Ltau ? 0 : tau + 1) * L2;
         const int64_t ct = (bc && tau == Ltau - 1) ? -1 : 1;
         for (int y = 0; y < L; ++y)
             for (int x = 0; x < L; ++x) {
                 int xy = x + L * y;
-                int xp = ((x + 1) % L) + L * y;
-                int yp = x + L * ((y + 1) % L);
+                int xp = (x + 1 == L ? 0 : x + 1) + L * y;
+                int yp = x + L * (y + 1 == L ? 0 : y + 1);
                 E -= (int64_t)Jx[xy] * P[xy] * P[xp];
                 E -= (int64_t)Jy[xy] * P[xy] * P[yp];
                 E -= ct * P[xy] * Pn[xy];
@@ -245,17 +245,17 @@ void oracle_energy(const oracle_shape *sh, int32_t n_samples, const int8_t *S,
             }
 }
 
-/* Energy change of flipping site (xy, tau): dE = 2 S h, with h the local
+/* Energy change of flipping site (x, y, tau): dE = 2 S h, with h the local
  * field of the four spatial and two temporal neighbours (the neighbour
  * across the tau wrap with the sign -1 when bc = 1). */
-int oracle_local_dE(int L, int Ltau, int bc, const int8_t *cfg, const int8_t *jx,
-                    const int8_t *jy, int xy, int tau)
+static int site_dE(int L, int Ltau, int bc, const int8_t *cfg, const int8_t *jx,
+                   const int8_t *jy, int x, int y, int tau)
 {
     const int L2 = L * L;
-    int x = xy % L, y = xy / L;
-    int xm = ((x + L - 1) % L) + L * y, xp = ((x + 1) % L) + L * y;
-    int ym = x + L * ((y + L - 1) % L), yp = x + L * ((y + 1) % L);
-    int tm = (tau + Ltau - 1) % Ltau, tp = (tau + 1) % Ltau;
+    int xy = x + L * y;
+    int xm = (x == 0 ? L - 1 : x - 1) + L * y, xp = (x + 1 == L ? 0 : x + 1) + L * y;
+    int ym = x + L * (y == 0 ? L - 1 : y - 1), yp = x + L * (y + 1 == L ? 0 : y + 1);
+    int tm = tau == 0 ? Ltau - 1 : tau - 1, tp = tau + 1 == Ltau ? 0 : tau + 1;
     const int8_t *P = cfg + (size_t)tau * L2;
     const int cm = (bc && tau == 0) ? -1 : 1, cp = (bc && tau == Ltau - 1) ? -1 : 1;
     int h = jx[xy] * P[xp] + jx[xm] * P[xm] + jy[xy] * P[yp] + jy[ym] * P[ym] +
@@ -263,10 +263,18 @@ int oracle_local_dE(int L, int Ltau, int bc, const int8_t *cfg, const int8_t *jx
     return 2 * P[xy] * h;
 }
 
+int oracle_local_dE(int L, int Ltau, int bc, const int8_t *cfg, const int8_t *jx,
+                    const int8_t *jy, int xy, int tau)
+{
+    return site_dE(L, Ltau, bc, cfg, jx, jy, xy % L, xy / L, tau);
+}
+
 /* One Metropolis half-sweep over the sites of colour c = (x+y+tau) mod 2
  * for every (replica, walker, sample): flip iff dE <= 0 or
  * R < T[k-index][dE/4 - 1].  Sites of one colour only have neighbours of
- * the other colour, so the visiting order is irrelevant. */
+ * the other colour, so the visiting order is irrelevant.  The uniforms
+ * depend on the sample only through its word, so they are drawn once per
+ * word into a table R[tau][xy] and then read by each sample of the word. */
 static void half_sweep(const oracle_shape *sh, int32_t n_samples,
                        const int32_t *samples, int c, uint32_t t, int8_t *S,
                        const int8_t *Jx, const int8_t *Jy, const uint8_t *kidx,
@@ -274,33 +282,41 @@ static void half_sweep(const oracle_shape *sh, int32_t n_samples,
 {
     const int L = sh->L, Lt = sh->Ltau, L2 = L * L, N = L2 * Lt;
     const int nk = sh->n_k;
-#pragma omp parallel for collapse(2) schedule(dynamic)
-    for (int r = 0; r < sh->n_replicas; ++r)
-        for (int w = 0; w < nk; ++w) {
-            for (int tau = 0; tau < Lt; ++tau)
-                for (int xy = 0; xy < L2; ++xy) {
-                    if (((xy % L + xy / L + tau) & 1) != c) continue;
-                    uint32_t R = 0, jR = 0xFFFFFFFFu;
-                    for (int si = 0; si < n_samples; ++si) {
-                        uint32_t j = sh->word_offset + (uint32_t)samples[si] / 64u;
-                        if (j != jR) {
-                            R = oracle_metro_uniform(sh, t, r, w, c, xy, tau, j);
-                            jR = j;
-                        }
-                        int8_t *cfg = S + ((size_t)(r * nk + w) * n_samples + si) * N;
-                        int dE = oracle_local_dE(L, Lt, sh->bc_tau, cfg, Jx + (size_t)si * L2,
-                                                 Jy + (size_t)si * L2, xy, tau);
-                        int accept;
-                        if (dE <= 0) {
-                            accept = 1;
-                        } else {
-                            int i = kidx[((size_t)r * n_samples + si) * nk + w];
-                            accept = R < T[i * 3 + (dE / 4 - 1)];
-                        }
-                        if (accept) cfg[(size_t)tau * L2 + xy] = (int8_t)(-cfg[(size_t)tau * L2 + xy]);
+#pragma omp parallel
+    {
+        uint32_t *Rtab = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)N);
+#pragma omp for collapse(2) schedule(dynamic)
+        for (int r = 0; r < sh->n_replicas; ++r)
+            for (int w = 0; w < nk; ++w) {
+                uint32_t jR = 0xFFFFFFFFu;
+                for (int si = 0; si < n_samples; ++si) {
+                    uint32_t j = sh->word_offset + (uint32_t)samples[si] / 64u;
+                    if (j != jR) {
+                        for (int tau = 0; tau < Lt; ++tau)
+                            for (int y = 0; y < L; ++y)
+                                for (int x = 0; x < L; ++x)
+                                    if (((x + y + tau) & 1) == c)
+                                        Rtab[(size_t)tau * L2 + x + L * y] =
+                                            oracle_metro_uniform(sh, t, r, w, c, x + L * y, tau, j);
+                        jR = j;
                     }
+                    int8_t *cfg = S + ((size_t)(r * nk + w) * n_samples + si) * N;
+                    const int8_t *jx = Jx + (size_t)si * L2, *jy = Jy + (size_t)si * L2;
+                    const int i = kidx[((size_t)r * n_samples + si) * nk + w];
+                    for (int tau = 0; tau < Lt; ++tau)
+                        for (int y = 0; y < L; ++y)
+                            for (int x = ((c + y + tau) & 1); x < L; x += 2) {
+                                int dE = site_dE(L, Lt, sh->bc_tau, cfg, jx, jy, x, y, tau);
+                                size_t lin = (size_t)tau * L2 + x + L * y;
+                                /* the table index is only used when dE > 0 */
+                                int q = dE > 0 ? dE / 4 - 1 : 0;
+                                int accept = (dE <= 0) | (Rtab[lin] < T[i * 3 + q]);
+                                cfg[lin] = (int8_t)(accept ? -cfg[lin] : cfg[lin]);
+                            }
                 }
-        }
+            }
+        free(Rtab);
+    }
 }
 
 /* One parallel-tempering step: pairs (i, i+1) with i = m mod 2, m mod 2 + 2,

@@ -425,17 +425,24 @@ hipError_t launch_triple_groups(int L, int ncfg, int nb, const int8_t* gw, int64
 
 size_t store_lds(int RR) { return (size_t)2 * RR * 64 * kPitch + (size_t)2 * RR * 64 * 4 + 2 * 64 * 4; }
 
+// The records are sums of atomic adds: cleared first by a kernel (no memset
+// node, so the launch sequence may be captured in a graph).
+__global__ void k_zero_records(int64_t* __restrict__ rec, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        rec[i] = 0;
+}
+
 template <int RR>
 hipError_t launch_triples_rr(const ShapeDev& sh, int cfg0, int ncfg, const TripleLayout& lay,
-                             void* ws, hipStream_t st) {
+                             int64_t* rec, int8_t* gw, hipStream_t st) {
     int dev = 0, ncu = 256;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    char* w = (char*)ws;
-    int64_t* rec = (int64_t*)w;
-    int8_t* gw = (int8_t*)(w + lay.rec_bytes);
-    hipError_t e = hipMemsetAsync(rec, 0, lay.rec_bytes, st);
-    if (e != hipSuccess) return e;
+    hipError_t e;
+    const size_t nrec = (size_t)ncfg * (RR * (RR - 1) * (RR - 2) / 6) * 2 * sh.L;
+    hipLaunchKernelGGL(k_zero_records, dim3((unsigned)std::min<size_t>((nrec + 255) / 256, 1024)), dim3(256), 0,
+                       st, rec, nrec);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     const int ntp = lay.nt * (lay.nt + 1) / 2;
     const long long items = (long long)ncfg * ntp;
     const int g1 = (int)std::min<long long>(items, 16LL * ncu);
@@ -474,14 +481,14 @@ const char* triples_unsupported(const ShapeDev& sh) {
     return nullptr;
 }
 
-hipError_t launch_triples(const ShapeDev& sh, int cfg0, int ncfg, void* ws, hipStream_t st) {
+hipError_t launch_triples(const ShapeDev& sh, int cfg0, int ncfg, int64_t* rec, int8_t* gw, hipStream_t st) {
     if (ncfg <= 0) return hipSuccess;
     const TripleLayout lay = triple_layout(sh, ncfg);
     switch (sh.R) {
-        case 3: return launch_triples_rr<3>(sh, cfg0, ncfg, lay, ws, st);
-        case 4: return launch_triples_rr<4>(sh, cfg0, ncfg, lay, ws, st);
-        case 5: return launch_triples_rr<5>(sh, cfg0, ncfg, lay, ws, st);
-        case 6: return launch_triples_rr<6>(sh, cfg0, ncfg, lay, ws, st);
+        case 3: return launch_triples_rr<3>(sh, cfg0, ncfg, lay, rec, gw, st);
+        case 4: return launch_triples_rr<4>(sh, cfg0, ncfg, lay, rec, gw, st);
+        case 5: return launch_triples_rr<5>(sh, cfg0, ncfg, lay, rec, gw, st);
+        case 6: return launch_triples_rr<6>(sh, cfg0, ncfg, lay, rec, gw, st);
         default: return hipErrorInvalidValue;
     }
 }

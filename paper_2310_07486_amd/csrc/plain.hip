@@ -175,6 +175,18 @@ __global__ void k_plain_temper(ShapeDev sh, uint32_t key0, uint32_t key1, const 
     }
 }
 
+// Identity k labels: walker w of every (r, s) at k-index w.  The plain
+// label arrays hold R * ns * nk entries (ns samples, not 64 per word).
+__global__ void k_plain_labels(ShapeDev sh) {
+    const size_t total = (size_t)sh.R * sh.W * sh.nk;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const uint8_t v = (uint8_t)(i % sh.nk);
+        sh.kidx[i] = v;
+        sh.winv[i] = v;
+    }
+}
+
 __global__ void k_plain_zero(int64_t* p, size_t n) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         p[i] = 0;
@@ -289,6 +301,12 @@ hipError_t plain_init_spins(const ShapeDev& sh, uint64_t seed, hipStream_t st) {
     const size_t total = (size_t)sh.R * sh.nk * sh.W * sh.L2 * sh.Lt;
     hipLaunchKernelGGL(k_plain_init_spins, dim3(grid_of(total)), dim3(256), 0, st, sh, (uint32_t)seed,
                        (uint32_t)(seed >> 32));
+    return hipGetLastError();
+}
+
+hipError_t plain_labels_identity(const ShapeDev& sh, hipStream_t st) {
+    const size_t total = (size_t)sh.R * sh.W * sh.nk;
+    hipLaunchKernelGGL(k_plain_labels, dim3(grid_of(total)), dim3(256), 0, st, sh);
     return hipGetLastError();
 }
 

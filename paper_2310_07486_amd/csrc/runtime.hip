@@ -54,6 +54,7 @@ struct tfim_plan {
     size_t oCounters = 0;
     char* arena = nullptr;
     hipStream_t stream = nullptr;
+    int device = 0;           // current device at tfim_bind
     bool bound = false;
     bool poisoned = false;   // sticky: set by a device error, never cleared
     uint32_t form = TFIM_FORM_MULTISPIN;
@@ -432,6 +433,7 @@ tfim_status tfim_bind(tfim_plan* pl, void* arena, size_t bytes, void* stream) {
     pl->schedule = TFIM_SCHED_PER_SHAPE;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
+    pl->device = dev;
     if (e == hipSuccess) e = hipDeviceGetAttribute(&pl->n_cu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess && !pl->cap_stream) e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking);
     if (e == hipSuccess)
@@ -537,7 +539,8 @@ tfim_status tfim_init_spins(tfim_plan* pl, uint32_t shape, const void* S_host) {
     } else {
         e = tfim::launch_init_spins(d, pl->seed, pl->stream);
     }
-    if (e == hipSuccess) e = tfim::launch_labels_identity(d, pl->stream);
+    if (e == hipSuccess)
+        e = plain(pl) ? tfim::plain_labels_identity(d, pl->stream) : tfim::launch_labels_identity(d, pl->stream);
     if (e == hipSuccess) e = refresh_derived(pl, shape);
     st = check_hip(pl, e, "init spins");
     if (st != TFIM_OK) return st;
@@ -1492,7 +1495,8 @@ tfim_status tfim_measure_triples(tfim_plan* pl, uint32_t shape, uint32_t cfg0, u
     if ((st = injected(pl)) != TFIM_OK) return st;
     hipError_t e = hipSuccess;
     if (!(flags & TFIM_MEASURE_REUSE_LAYOUT)) e = tfim::launch_transpose(d, pl->stream);
-    if (e == hipSuccess) e = tfim::launch_triples(d, (int)cfg0, (int)ncfg, ws, pl->stream);
+    if (e == hipSuccess)
+        e = tfim::launch_triples(d, (int)cfg0, (int)ncfg, (int64_t*)ws, (int8_t*)ws + lay.rec_bytes, pl->stream);
     if ((st = check_hip(pl, e, "triples")) != TFIM_OK) return st;
     if (!out) return TFIM_OK;
     return copy_back(pl, out, (const char*)ws, rec_used, "copy triple records");

@@ -195,7 +195,10 @@ struct TripleLayout {
 };
 TripleLayout triple_layout(const ShapeDev& sh, int ncfg);
 const char* triples_unsupported(const ShapeDev& sh);  // nullptr if supported
-hipError_t launch_triples(const ShapeDev& sh, int cfg0, int ncfg, void* ws, hipStream_t st);
+// rec: int64 records [ncfg][triples][2][L] (cleared first); gw: the digit
+// planes, g_bytes of scratch
+hipError_t launch_triples(const ShapeDev& sh, int cfg0, int ncfg, int64_t* rec, int8_t* gw, hipStream_t st);
+
 // Two-time records (c, q2 along the periodic diagonals of H = S^T S, summed
 // over replicas) of configurations cfg0 .. cfg0+ncfg-1: int64 [ncfg][2][Lt].
 const char* timecorr_unsupported(const ShapeDev& sh);  // nullptr if supported
@@ -217,6 +220,7 @@ const char* sweep_variant_name(int v);
 // holds the number of samples, S and J point at int8 arrays).
 hipError_t plain_init_couplings(const ShapeDev& sh, uint64_t seed, hipStream_t st);
 hipError_t plain_init_spins(const ShapeDev& sh, uint64_t seed, hipStream_t st);
+hipError_t plain_labels_identity(const ShapeDev& sh, hipStream_t st);
 hipError_t plain_energy(const ShapeDev& sh, hipStream_t st);
 // colour 0, colour 1 and the energy recount of one sweep
 hipError_t plain_sweep(const ShapeDev& sh, uint64_t seed, const Counters* ctr, hipStream_t st);

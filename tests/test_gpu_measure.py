@@ -95,10 +95,13 @@ def test_full_shape_sampled_configs_and_identities():
     assert np.array_equal(Dx.sum(axis=-1), Q2) and np.array_equal(Dy.sum(axis=-1), Q2)
     assert np.all(np.abs(trQ) <= N) and np.all(Q4 >= Q2) and np.all(Q2 > 0)
     assert np.all((trQ - N) % 2 == 0)  # sum of N products of +-1
-    # sampled configurations against the oracle: samples 0 and 999, k-indices 0 and 31
-    lanes = [0, 999]
-    want = _oracle_records(sh, w.seed, lanes, 2, k_indices=[0, 31])  # [2][2][P][2L+3]
-    for ii, i in enumerate([0, 31]):
+    # 64 sampled configurations against the oracle: 16 samples spread over the
+    # 16 words and both ends of each word, at four k-indices
+    lanes = [0, 63, 64, 130, 200, 255, 333, 448, 511, 600, 700, 767, 800, 999, 1000, 1023]
+    ks = [0, 10, 21, 31]
+    _say(f"measure at full shape: oracle records of {len(lanes) * len(ks)} configurations")
+    want = _oracle_records(sh, w.seed, lanes, 2, k_indices=ks)  # [4][16][P][2L+3]
+    for ii, i in enumerate(ks):
         for si, s in enumerate(lanes):
             assert np.array_equal(rec[i, s], want[ii, si]), (i, s)
     # the plain per-sample form agrees on one configuration

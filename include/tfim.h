@@ -235,6 +235,24 @@ tfim_status tfim_measure_triples(tfim_plan *plan, uint32_t shape, uint32_t cfg0,
                                  uint32_t flags, void *workspace, size_t workspace_bytes,
                                  int64_t *out, size_t out_bytes);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * records of tfim_measure_triples with no workspace argument.  The int8 G/2
+ * digit planes live in a device array that the library holds on every GPU
+ * it runs on until the process ends (64 MiB; about 2 R (64 ceil(L/8)^2)^2
+ * bytes per configuration, so at L = 24 at most 16 configurations with six
+ * replicas or 24 with four per call: more is TFIM_EINVAL, with the limit in
+ * the detail).  rec_dev: caller-owned device memory (8-byte aligned) of at
+ * least ncfg * n_triples * 2L int64, written with the records of
+ * configurations cfg0 .. cfg0+ncfg-1 (layout as tfim_measure_triples).
+ * flags as for tfim_measure_range.  Enqueues on the plan's stream and
+ * returns (asynchronous); allocates nothing and records no memset.  Every
+ * call on one GPU shares that GPU's array and leaves it holding its planes:
+ * calls that overlap on one GPU (several streams or host threads) race. */
+tfim_status tfim_measure_triples_noalloc(tfim_plan *plan, uint32_t shape, uint32_t cfg0,
+                                         uint32_t ncfg, uint32_t flags, int64_t *rec_dev,
+                                         size_t rec_bytes);
+
 /* Two-time records (Methods, "Two-times observables"): for configuration
  * cfg = i*samples + s, with the time Gram H^r = S^rT S^r of each replica
  * (Ltau x Ltau, H_t1t2 = sum_x S_x,t1 S_x,t2),

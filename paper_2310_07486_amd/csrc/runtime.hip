@@ -1502,6 +1502,42 @@ tfim_status tfim_measure_triples(tfim_plan* pl, uint32_t shape, uint32_t cfg0, u
     return copy_back(pl, out, (const char*)ws, rec_used, "copy triple records");
 }
 
+tfim_status tfim_measure_triples_noalloc(tfim_plan* pl, uint32_t shape, uint32_t cfg0, uint32_t ncfg,
+                                         uint32_t flags, int64_t* rec_dev, size_t rec_bytes) {
+    tfim_status st = shape_ok(pl, shape);
+    if (st != TFIM_OK) return st;
+    ShapeHost& h = pl->shapes[shape];
+    if (plain(pl)) return fail(TFIM_EUNSUPPORTED, "three-replica records need the multispin form");
+    if (!h.S_ready) return fail(TFIM_ESTATE, "spins of this shape are not initialised");
+    const tfim::ShapeDev d = dev_of(pl, shape);
+    if (const char* why = tfim::triples_unsupported(d)) return fail(TFIM_EUNSUPPORTED, why);
+    const uint64_t ncfg_all = (uint64_t)h.s.n_k * 64 * h.s.n_words;
+    if ((uint64_t)cfg0 + ncfg > ncfg_all) return fail(TFIM_EINVAL, "configuration range out of bounds");
+    const uint32_t R = h.s.n_replicas;
+    const size_t rec_used = (size_t)ncfg * (R * (R - 1) * (R - 2) / 6) * 2 * h.s.L * 8;
+    if (!rec_dev || ((uintptr_t)rec_dev & 7)) return fail(TFIM_EINVAL, "records need an 8-byte aligned device buffer");
+    if (rec_bytes < rec_used) return fail(TFIM_EINVAL, "record buffer too small");
+    void* scr = nullptr;
+    size_t scr_bytes = 0;
+    if ((st = check_hip(pl, tfim::static_scratch(pl->device, &scr, &scr_bytes), "static scratch")) != TFIM_OK)
+        return st;
+    const tfim::TripleLayout lay = tfim::triple_layout(d, (int)ncfg);
+    if (lay.g_bytes > scr_bytes) {
+        char buf[200];
+        snprintf(buf, sizeof buf,
+                 "%u configurations need %zu bytes of digit planes; the library's scratch holds %zu "
+                 "(at most %zu configurations of this shape per call)",
+                 ncfg, lay.g_bytes, scr_bytes, scr_bytes / (lay.g_bytes / std::max<uint32_t>(ncfg, 1)));
+        return fail(TFIM_EINVAL, buf);
+    }
+    if (ncfg == 0) return TFIM_OK;
+    if ((st = injected(pl)) != TFIM_OK) return st;
+    hipError_t e = hipSuccess;
+    if (!(flags & TFIM_MEASURE_REUSE_LAYOUT)) e = tfim::launch_transpose(d, pl->stream);
+    if (e == hipSuccess) e = tfim::launch_triples(d, (int)cfg0, (int)ncfg, rec_dev, (int8_t*)scr, pl->stream);
+    return check_hip(pl, e, "triples (library scratch)");
+}
+
 tfim_status tfim_measure_time(tfim_plan* pl, uint32_t shape, uint32_t cfg0, uint32_t ncfg,
                               uint32_t flags, void* ws, size_t ws_bytes, int64_t* out,
                               size_t out_bytes) {

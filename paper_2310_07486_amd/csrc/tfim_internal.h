@@ -198,7 +198,9 @@ const char* triples_unsupported(const ShapeDev& sh);  // nullptr if supported
 // rec: int64 records [ncfg][triples][2][L] (cleared first); gw: the digit
 // planes, g_bytes of scratch
 hipError_t launch_triples(const ShapeDev& sh, int cfg0, int ncfg, int64_t* rec, int8_t* gw, hipStream_t st);
-
+// Library-held device scratch of the entry points that allocate nothing:
+// its device address on `device` (looked up once per device) and its size.
+hipError_t static_scratch(int device, void** ptr, size_t* bytes);
 // Two-time records (c, q2 along the periodic diagonals of H = S^T S, summed
 // over replicas) of configurations cfg0 .. cfg0+ncfg-1: int64 [ncfg][2][Lt].
 const char* timecorr_unsupported(const ShapeDev& sh);  // nullptr if supported

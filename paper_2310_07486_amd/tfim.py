@@ -44,6 +44,7 @@ SYMBOLS = [
     "tfim_measure_range", "tfim_set_measure_mode", "tfim_set_batch",
     "tfim_triples_workspace", "tfim_measure_triples", "tfim_xi3", "tfim_binder",
     "tfim_measure_time", "tfim_tm_workspace", "tfim_tm_apply", "tfim_tm_top",
+    "tfim_measure_triples_noalloc",
 ]
 TFIM_MEASURE_REUSE_LAYOUT = 1
 
@@ -127,6 +128,7 @@ def lib():
             "tfim_xi3": [P, U32, U32, U32, U32, P],
             "tfim_binder": [P, U32, U32, U32, U32, P],
             "tfim_measure_time": [P, U32, U32, U32, U32, P, SZ, P, SZ],
+            "tfim_measure_triples_noalloc": [P, U32, U32, U32, U32, P, SZ],
             "tfim_tm_workspace": [U32, P],
             "tfim_tm_apply": [U32, ctypes.c_double, P, P, P, P, P],
             "tfim_tm_top": [U32, ctypes.c_double, P, P, U32, U32, ctypes.c_double, U32, P, SZ, P, P, P],
@@ -463,6 +465,17 @@ class Plan:
                                           ctypes.c_void_p(ws.data_ptr()), ws.numel(), _ptr(out),
                                           out.nbytes), "tfim_measure_triples")
         return out
+
+    def measure_triples_noalloc(self, shape: int, cfg0: int, ncfg: int, rec, flags: int = 0):
+        """Three-replica records of configurations cfg0 .. cfg0+ncfg-1 into
+        rec, a caller-owned torch int64 device tensor of at least
+        ncfg * triples * 2L elements; the library allocates nothing (its own
+        device scratch holds the digit planes).  Asynchronous on the plan's
+        stream."""
+        _check(lib().tfim_measure_triples_noalloc(self._h, shape, cfg0, ncfg, flags,
+                                                  ctypes.c_void_p(rec.data_ptr()),
+                                                  rec.numel() * rec.element_size()),
+               "tfim_measure_triples_noalloc")
 
     def measure_time(self, shape: int, cfg0: int, ncfg: int, flags: int = 0, copy: bool = True):
         """Two-time records [ncfg][2][Ltau] (c and q2 summed over replicas) of

@@ -50,27 +50,78 @@ def measured_traffic(workload_name: str, kernel: str):
     return t["per_launch"]
 
 
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _omp_threads(n):
+    """Set the OpenMP thread count of the loaded oracle (libgomp)."""
+    import ctypes
+    ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+
+
 def cpu_baseline(workload, seconds: float):
-    """The oracle (plain C, one byte per spin, OpenMP) on a bounded sample of
-    the same workload: one disorder sample, all replicas and walkers."""
+    """The oracle as it stands (plain C, one byte per spin, OpenMP over
+    replica-walker units; numpy float64 BLAS for the measurement) on bounded
+    samples of the same workload, on every host thread and on one:
+    - the chain: one disorder sample, all replicas and walkers;
+    - the measurement: the pair records (Gram G, overlaps Q and their
+      reductions) of 64 configurations of the large shape (two samples at
+      every k-index), as integer ops per ns."""
     import oracle
+    from oracle import measure as om
     sh = workload.shapes[0]
-    ch = oracle.Chain(sh.L, sh.Ltau, sh.k, sh.n_replicas, workload.seed, [0],
-                      pt_every=sh.pt_every)
-    per_sweep = sh.L * sh.L * sh.Ltau * sh.n_replicas * len(sh.k)
-    t0 = time.perf_counter()
-    ch.run(1)
-    t1 = time.perf_counter() - t0
-    n = max(1, min(200, int(seconds / max(t1, 1e-3))))
-    t0 = time.perf_counter()
-    ch.run(n)
-    dt = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    per_sweep = sh.L * sh.L * sh.Ltau * sh.n_replicas * len(sh.k)
+
+    def chain_rate(n_threads, budget):
+        _omp_threads(n_threads)
+        ch = oracle.Chain(sh.L, sh.Ltau, sh.k, sh.n_replicas, workload.seed, [0],
+                          pt_every=sh.pt_every)
+        t0 = time.perf_counter()
+        ch.run(1)
+        t1 = time.perf_counter() - t0
+        n = max(1, min(200, int(budget / max(t1, 1e-3))))
+        t0 = time.perf_counter()
+        ch.run(n)
+        dt = time.perf_counter() - t0
+        return per_sweep * n / (dt * 1e9), n, dt
+
+    v_all, n_all, dt_all = chain_rate(threads, seconds)
+    log(f"bench: cpu baseline: oracle chain {v_all:.3f} spin-updates/ns on {threads} threads")
+    v_one, n_one, dt_one = chain_rate(1, seconds / 2)
+    log(f"bench: cpu baseline: oracle chain {v_one:.3f} spin-updates/ns on 1 thread")
+    # measurement: 2 samples x 32 k-indices = 64 configurations (hot start)
+    _omp_threads(threads)
+    ch = oracle.Chain(sh.L, sh.Ltau, sh.k, sh.n_replicas, workload.seed, [0, 1], pt_every=sh.pt_every)
+    _, g_ops, q_ops = measure_ops(sh)
+    t0 = time.perf_counter()
+    rec = om.measure_chain(ch)
+    dt_m = time.perf_counter() - t0
+    ncfg = rec.shape[0] * rec.shape[1]
+    gram_rate = (g_ops + q_ops) * ncfg / (dt_m * 1e9)
+    log(f"bench: cpu baseline: oracle pair records of {ncfg} configurations in {dt_m:.1f} s, "
+        f"{gram_rate:.1f} int-ops/ns")
     return {
-        "value": per_sweep * n / (dt * 1e9), "unit": "spin-updates/ns", "cores": threads,
+        "value": round(v_all, 4), "unit": "spin-updates/ns", "cores": threads,
         "kind": "oracle",
         "sample": f"1 of 1024 samples x {sh.n_replicas} replicas x {len(sh.k)} k, "
-                  f"{n} sweeps ({per_sweep * n:.3g} updates, {dt:.1f} s)",
+                  f"{n_all} sweeps ({per_sweep * n_all:.3g} updates, {dt_all:.1f} s)",
+        "one_core": {"value": round(v_one, 4), "unit": "spin-updates/ns", "cores": 1,
+                     "sample": f"the same sample, {n_one} sweeps ({dt_one:.1f} s)"},
+        "host": {"nproc": os.cpu_count(), "cpu_model": _cpu_model(), "omp_threads": threads},
+        "measurement": {"value": round(gram_rate, 2), "unit": "int-ops/ns", "cores": threads,
+                        "kind": "oracle (numpy float64 BLAS on +-1 entries, int64 reductions)",
+                        "sample": f"pair records of {ncfg} configurations of 576 x 2048 spins "
+                                  f"(2 samples x {len(sh.k)} k, {sh.n_replicas} replicas), "
+                                  f"{dt_m:.1f} s",
+                        "ops_per_configuration": g_ops + q_ops},
     }
 
 
@@ -105,13 +156,16 @@ def measure_leg(plan, sh, torch, args):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1)
 
-    # layouts (bit transposition) once, timed on its own
-    t_tr = timed(lambda: plan.measure_range(0, 0, 0, 1, copy=False))
-    log("bench: measure: transposition + 1 configuration %.2f ms" % t_tr)
+    # layouts (bit transposition) once, timed on their own (a range of no
+    # configurations lays out the bits and measures nothing)
+    t_tr = timed(lambda: plan.measure_range(0, 0, 0, 0, copy=False))
+    log("bench: measure: transposition %.2f ms" % t_tr)
     t_all = timed(lambda: plan.measure_range(0, 0, 0, ncfg, flags=tfim.TFIM_MEASURE_REUSE_LAYOUT,
                                              copy=False))
     tops = per_cfg * ncfg / (t_all * 1e-3) / 1e12
-    log("bench: measure: batched MFMA, %d configurations: %.1f ms, %.1f TOP/s" % (ncfg, t_all, tops))
+    tops_tr = per_cfg * ncfg / ((t_all + t_tr) * 1e-3) / 1e12
+    log("bench: measure: batched MFMA, %d configurations: %.1f ms, %.1f TOP/s (%.1f with the "
+        "transposition)" % (ncfg, t_all, tops, tops_tr))
     n_un = min(args.unbatched_cfgs, ncfg)
 
     def unbatched():
@@ -134,7 +188,9 @@ def measure_leg(plan, sh, torch, args):
         "ops_per_configuration": per_cfg, "gram_ops": g_ops * ncfg, "overlap_ops": q_ops * ncfg,
         "transpose_ms": round(t_tr, 3),
         "batched_mfma": {"ms": round(t_all, 3), "int8_tops": round(tops, 2),
-                          "frac_of_int8_peak": round(tops / 5000.0, 4)},
+                          "frac_of_int8_peak": round(tops / 5000.0, 4),
+                          "int8_tops_with_transpose": round(tops_tr, 2),
+                          "frac_with_transpose": round(tops_tr / 5000.0, 4)},
         "per_configuration_mfma": {"configurations": n_un, "ms_per_cfg": round(t_un / n_un, 4),
                                     "int8_tops": round(tops_un, 2)},
         "plain_per_sample": {"configurations": n_pl, "ms_per_cfg": round(t_pl / n_pl, 4),
@@ -297,6 +353,52 @@ def transfer_leg(torch, args):
     }
 
 
+def c1_leg(torch, args):
+    """One disorder sample in the plain one-byte-per-spin form (L=8, Ltau=32,
+    two replicas, k=0.29, no tempering, 2000 sweeps): the energy per spin
+    e(t) = (2U - 3N)/N of each replica and the overlap q(t) = trQ/N after
+    every sweep, and the time of the sweeps alone."""
+    from paper_2310_07486_amd import tfim
+    from paper_2310_07486_amd.workloads import c1_plain
+    w = c1_plain()
+    sh = w.shapes[0]
+    N = sh.L * sh.L * sh.Ltau
+    plan = tfim.Plan([sh], w.seed, form=tfim.TFIM_FORM_PLAIN_I8)
+    plan.init()
+    e, q = [], []
+    for _ in range(w.sweeps):
+        plan.sweep(1)
+        U = plan.measure(0, tfim.TFIM_MEASURE_ENERGY)[:, 0, 0].astype(np.int64)
+        rec = plan.measure(0, tfim.TFIM_MEASURE_RECORDS)[0, 0, 0]
+        e.append(((2 * U - 3 * N) / N).tolist())
+        q.append(float(rec[2 * sh.L]) / N)
+    e = np.array(e)
+    q = np.array(q)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    plan.sweep(w.sweeps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    plan.close()
+    half = w.sweeps // 2
+    log(f"bench: C1 plain form: {w.sweeps} sweeps, e = {e[half:].mean(axis=0)}, "
+        f"<q^2> = {np.mean(q[half:] ** 2):.4f}, {ms:.1f} ms for {w.sweeps} sweeps")
+    return {
+        "workload": w.name, "form": "plain_i8", "sweeps": w.sweeps,
+        "e_mean_second_half": [round(float(v), 5) for v in e[half:].mean(axis=0)],
+        "q_mean_second_half": round(float(q[half:].mean()), 5),
+        "q2_mean_second_half": round(float(np.mean(q[half:] ** 2)), 5),
+        "e_every_100": [[round(float(v), 5) for v in e[t]] for t in range(99, w.sweeps, 100)],
+        "q_every_100": [round(float(q[t]), 5) for t in range(99, w.sweeps, 100)],
+        "ms_for_sweeps": round(ms, 3),
+        "spin_updates_per_ns": round(N * sh.n_replicas * w.sweeps / (ms * 1e6), 5),
+    }
+
+
 def paper_leg(torch, args):
     """The paper's production row for L = 24 (Table I: Ltau = 2048, 60 k
     uniformly over [0.265, 0.292]) on its schedule (6 replicas, a tempering
@@ -446,8 +548,9 @@ def main():
     ap.add_argument("--no-paper", action="store_true", help="skip the paper-schedule L=24 leg")
     ap.add_argument("--triples-chunk", type=int, default=4096)
     ap.add_argument("--unbatched-cfgs", type=int, default=64)
-    ap.add_argument("--plain-cfgs", type=int, default=1)
+    ap.add_argument("--plain-cfgs", type=int, default=64)
     ap.add_argument("--no-batched", action="store_true", help="skip the five-size batched leg")
+    ap.add_argument("--no-c1", action="store_true", help="skip the one-sample plain-form leg")
     ap.add_argument("--c4-steps", type=int, default=10)
     ap.add_argument("--copy-gb", type=float, default=0.0,
                     help="first run a plain device copy of this many GB (calibrates HBM counters)")
@@ -561,6 +664,8 @@ def main():
         result["paper_schedule"] = paper_leg(torch, args)
     if not args.no_batched:
         result["batched"] = batched_leg(torch, args)
+    if not args.no_c1:
+        result["c1_plain"] = c1_leg(torch, args)
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

@@ -23,7 +23,31 @@ import numpy as np
 from . import fss
 
 
-def run(L: int, n_words: int, n_eq: int, n_meas: int, gap: int, seed: int, out: str) -> None:
+# device memory for the three-replica workspace of one chunk of
+# configurations (about 4 MB per configuration at L = 24 with 6 replicas)
+TRIPLE_BUDGET = 8 << 30
+
+
+def triple_sums(plan, sh, budget: int = TRIPLE_BUDGET) -> np.ndarray:
+    """Per-(k, sample) three-replica records summed over the triples, as
+    float64 [nk][S][2L], measured in chunks of configurations whose workspace
+    fits `budget` bytes.  The bit layouts must be current (a pair
+    measurement of this state came first)."""
+    from . import tfim
+    nk, S, L = len(sh.k), plan.samples(0), sh.L
+    ncfg = nk * S
+    per = max(1, plan.triples_workspace_bytes(0, 1))
+    chunk = max(1, min(ncfg, budget // per))
+    out = np.zeros((ncfg, 2 * L))
+    for c0 in range(0, ncfg, chunk):
+        n = min(chunk, ncfg - c0)
+        tr = plan.measure_triples(0, c0, n, flags=tfim.TFIM_MEASURE_REUSE_LAYOUT)
+        out[c0:c0 + n] = tr.astype(np.float64).sum(axis=1)
+    return out.reshape(nk, S, 2 * L)
+
+
+def run(L: int, n_words: int, n_eq: int, n_meas: int, gap: int, seed: int, out: str,
+        budget: int = TRIPLE_BUDGET) -> None:
     from . import tfim
     from .workloads import table_i
     sh = table_i(L, n_words)
@@ -31,10 +55,13 @@ def run(L: int, n_words: int, n_eq: int, n_meas: int, gap: int, seed: int, out: 
     t0 = time.time()
     plan = tfim.Plan([sh], seed)
     plan.init()
-    for e in range(n_eq // 10000):
-        plan.sweep(10000)
+    done = 0
+    while done < n_eq:
+        n = min(10000, n_eq - done)
+        plan.sweep(n)
         plan.sync()
-        print(f"fss_run: L={L} {10000 * (e + 1)} equilibration sweeps, {time.time() - t0:.0f} s", flush=True)
+        done += n
+        print(f"fss_run: L={L} {done} equilibration sweeps, {time.time() - t0:.0f} s", flush=True)
     Ts = np.zeros((nk, S, 2 * L))
     Th = np.zeros((2, nk, S, 2 * L))
     Ds = np.zeros((nk, S))
@@ -44,13 +71,12 @@ def run(L: int, n_words: int, n_eq: int, n_meas: int, gap: int, seed: int, out: 
         plan.sweep(gap)
         rec = plan.measure(0, tfim.TFIM_MEASURE_RECORDS)  # [k][s][pair][2L+3]
         Ds += rec[:, :, :, :L].astype(np.float64).sum(axis=(2, 3))
-        tr = plan.measure_triples(0, 0, nk * S, flags=tfim.TFIM_MEASURE_REUSE_LAYOUT)
-        tr = tr.reshape(nk, S, -1, 2 * L).astype(np.float64).sum(axis=2)
+        tr = triple_sums(plan, sh, budget)
         Ts += tr
         Th[int(2 * m >= n_meas)] += tr
     plan.close()
     np.savez(out, k=np.asarray(sh.k), Ts=Ts, Th=Th, Ds=Ds, L=L, Ltau=sh.Ltau, n_meas=n_meas,
-             R=sh.n_replicas)
+             R=sh.n_replicas, seed=seed, n_eq=n_eq, gap=gap, n_words=n_words)
     print(f"fss_run: L={L} saved {out} after {time.time() - t0:.0f} s", flush=True)
 
 
@@ -66,11 +92,22 @@ def _curves(row, w):
     return row["k"], x, c2, c3
 
 
+# pairs whose bootstrap finds one crossing in fewer resamplings than this are
+# nearly parallel there: their errors are conditioned on a crossing existing
+RELIABLE_FRACTION = 0.9
+
+
 def analyse(paths, n_boot: int = 200, seed: int = 2310):
     rows = {}
     for p in paths:
         row = dict(np.load(p))
-        rows[int(row["L"])] = row
+        L = int(row["L"])
+        if L in rows:
+            raise ValueError(f"two rows for L = {L} ({p} and an earlier file)")
+        rows[L] = row
+        meta = ", ".join(f"{k} {int(row[k])}" for k in ("seed", "n_eq", "gap", "n_words", "n_meas")
+                         if k in row)
+        print(f"L={L}: {p}: {meta}")
     results = {}
     for La, Lb in itertools.combinations(sorted(rows), 2):
         lo = 0.265
@@ -86,8 +123,12 @@ def analyse(paths, n_boot: int = 200, seed: int = 2310):
         if central is None:
             print(f"({La}, {Lb}): no single crossing")
             continue
+        frac = len(res) / n_boot
+        flag = "" if frac >= RELIABLE_FRACTION else (
+            f"; UNRELIABLE: only {100 * frac:.0f}% of resamplings cross once, so the errors are "
+            f"conditioned on a crossing and too small")
         print(f"({La}, {Lb}): " + ", ".join(f"{q} = {central[q]:.4f} +- {sd.get(q, float('nan')):.4f}"
-                                             for q in central) + f" ({len(res)} of {n_boot} resamplings)")
+                                             for q in central) + f" ({len(res)} of {n_boot} resamplings{flag})")
     for L, row in sorted(rows.items()):
         Th = row["Th"]
         w = np.ones(Th.shape[2])

@@ -91,3 +91,13 @@ def test_runner_analysis_normalises_rows_and_recovers_exponents(tmp_path):
     assert central["gamma2/nu"] == pytest.approx(G2, abs=1e-7)
     assert central["gamma3/nu"] == pytest.approx(G3, abs=1e-7)
     assert n == 4  # identical samples: every resampling crosses once
+
+
+def test_runner_analysis_refuses_two_rows_of_one_size(tmp_path):
+    from paper_2310_07486_amd import fss_run
+    a = _row(tmp_path, 8, 512, 80, np.linspace(0.265, 0.305, 16))
+    b = str(tmp_path / "again.npz")
+    import shutil
+    shutil.copy(a, b)
+    with pytest.raises(ValueError):
+        fss_run.analyse([a, b], n_boot=2)

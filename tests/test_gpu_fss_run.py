@@ -26,3 +26,23 @@ def test_runner_saves_rows_and_analyses_the_pair(tmp_path, capsys):
     assert central is not None and n >= 15
     assert 0.28 <= central["k*"] <= 0.30 and 0.0 < sd["k*"] < 0.02
     assert 0.0 < central["gamma2/nu"] < central["gamma3/nu"]
+
+
+def test_triple_sums_in_chunks_equal_one_call():
+    """The runner measures three-replica records in chunks of configurations
+    (the workspace of a full Table I row does not fit one GPU at once); the
+    chunked sums equal the sums of one call over every configuration."""
+    from paper_2310_07486_amd import tfim
+    from paper_2310_07486_amd.workloads import table_i
+    sh = table_i(8, n_words=1)
+    plan = tfim.Plan([sh], 77)
+    plan.init()
+    plan.sweep(40)
+    plan.measure(0, tfim.TFIM_MEASURE_RECORDS)  # lays out the bits
+    nk, S, L = len(sh.k), plan.samples(0), sh.L
+    whole = plan.measure_triples(0, 0, nk * S, flags=tfim.TFIM_MEASURE_REUSE_LAYOUT)
+    want = whole.reshape(nk, S, -1, 2 * L).astype(np.float64).sum(axis=2)
+    per = plan.triples_workspace_bytes(0, 1)
+    got = fss_run.triple_sums(plan, sh, budget=per * 100 + 5)  # chunks of 100, a ragged last one
+    assert np.array_equal(got, want)
+    plan.close()

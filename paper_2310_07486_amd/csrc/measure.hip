@@ -25,9 +25,11 @@
 // 2. k_gram_mfma: one workgroup per configuration at a time, 64x64 tiles of
 //    G (upper triangle of tile pairs), all replicas at once, bucket sums in
 //    LDS, flushed once per configuration.
-// 3. k_overlap_mfma: 64x64 tiles of every Q^ab, all pairs at once for up to
-//    4 replicas (5 or 6: one launch per group of 5 pairs); per-lane int64
-//    sums flushed once per configuration.
+// 3. k_overlap_mfma: every wave alone (no LDS, no barrier) on 64x64 tiles of
+//    up to 3 pairs at once (more: one launch per group of 3), operands
+//    unpacked in registers, the rank-one corrections folded into one more
+//    K step so the accumulator is Q; per-lane int64 sums flushed once per
+//    configuration by each of the wave teams that share it.
 // The plain per-sample form (k_*_plain) computes one matrix element per
 // thread with an int32 multiply-accumulate loop over unpacked spins, one
 // launch per configuration: the reference point for the batched form.
@@ -123,8 +125,21 @@ __device__ __forceinline__ v4i lds_v4(const uint8_t* base) { return *(const v4i*
 
 // ---------------------------------------------------------------------------
 // G tiles and the D buckets.
+//
+// The tile pairs (X, Y), X <= Y, of the upper triangle cover every element:
+// an element (x, y) of an off-diagonal pair stands for (y, x) too, with the
+// displacements negated.  Its products go to U, those of diagonal pairs to
+// F, and the flush folds D[d] = F[d] + U[d] + U[-d mod L].
+//
+// BLK (L a multiple of 8): tile X holds the 8 x 8 block of sites
+// (bx, by) = (X mod L/8, X div L/8), row r the site (8bx + r mod 8,
+// 8by + r div 8).  The 16 elements of a lane then take 4 values of x1 - y1
+// (one per q mod 4) and 4 of x2 - y2 (one per q div 4), so each lane sums
+// them in registers and adds 8 bucket values per pair and block, not 32.
+// Otherwise tile X holds the sites 64X .. 64X + 63 and every element adds
+// its own two.
 // ---------------------------------------------------------------------------
-template <int RR>
+template <int RR, bool BLK>
 __global__ void __launch_bounds__(256) k_gram_mfma(ShapeDev sh, int cfg0, int ncfg) {
     constexpr int PP = RR * (RR - 1) / 2;
     extern __shared__ __align__(16) uint8_t smem[];
@@ -132,13 +147,20 @@ __global__ void __launch_bounds__(256) k_gram_mfma(ShapeDev sh, int cfg0, int nc
     uint8_t* Bl = smem + RR * 64 * kRowPitch;             // [RR][64][kRowPitch]
     int* nA = (int*)(Bl + RR * 64 * kRowPitch);           // [RR][64]
     int* nB = nA + RR * 64;                               // [RR][64]
-    unsigned long long* Dblk = (unsigned long long*)(nB + RR * 64);  // [PP][2][L]
+    unsigned long long* Fb = (unsigned long long*)(nB + RR * 64);  // [PP][2][L]
+    unsigned long long* Ub = Fb + PP * 2 * sh.L;                   // [PP][2][L]
     const int L = sh.L, L2 = sh.L2, Lt = sh.Lt;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int wx = wv & 1, wy = wv >> 1;
+    const int wx = wv & 1, wy = wv >> 1, h = lane >> 5;
     const int ntile = sh.nx;
     const int ntp = ntile * (ntile + 1) / 2;
-    for (int e = tid; e < PP * 2 * L; e += 256) Dblk[e] = 0;
+    const int nbl = L >> 3;
+    // site of row r of tile X
+    auto site = [&](int X, int r) {
+        if constexpr (BLK) return (8 * (X / nbl) + (r >> 3)) * L + 8 * (X % nbl) + (r & 7);
+        return 64 * X + r;
+    };
+    for (int e = tid; e < 2 * PP * 2 * L; e += 256) Fb[e] = 0;  // F and U
     for (int cfg = cfg0 + blockIdx.x; cfg < cfg0 + ncfg; cfg += gridDim.x) {
         for (int tp = 0; tp < ntp; ++tp) {
             // tile pair (X, Y), X <= Y, in row-major order of the upper triangle
@@ -148,6 +170,7 @@ __global__ void __launch_bounds__(256) k_gram_mfma(ShapeDev sh, int cfg0, int nc
             const bool diag = X == Y;
             const uint8_t* Bsrc = diag ? Al : Bl;
             const int* nBsrc = diag ? nA : nB;
+            unsigned long long* Db = diag ? Fb : Ub;
             v16i acc[RR];
 #pragma unroll
             for (int r = 0; r < RR; ++r)
@@ -160,9 +183,8 @@ __global__ void __launch_bounds__(256) k_gram_mfma(ShapeDev sh, int cfg0, int nc
                 const uint64_t vm = low_bits(Lt - 64 * c);
                 for (int e = tid; e < (diag ? 1 : 2) * RR * 64; e += 256) {
                     const int side = e / (RR * 64), rr = (e / 64) % RR, row = e & 63;
-                    const int xy0 = 64 * (side ? Y : X);
                     const size_t m = (size_t)cfg * RR + rr;
-                    const uint64_t v = sh.Pt[(m * sh.nc + c) * sh.nxp + xy0 + row] & vm;
+                    const uint64_t v = sh.Pt[(m * sh.nc + c) * sh.nxp + site(side ? Y : X, row)] & vm;
                     (side ? nB : nA)[rr * 64 + row] += __popcll(v);
                     unpack64(v, (side ? Bl : Al) + (rr * 64 + row) * kRowPitch);
                 }
@@ -180,221 +202,343 @@ __global__ void __launch_bounds__(256) k_gram_mfma(ShapeDev sh, int cfg0, int nc
             }
             __syncthreads();  // popcounts complete
             const int col = 32 * wy + (lane & 31);
-            const int y = 64 * Y + col;
-#pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int row = 32 * wx + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
-                const int x = 64 * X + row;
-                if (x >= L2 || y >= L2) continue;
-                long long G[RR];
+            // G^r of this lane's element q (|G| <= Ltau <= 2^16)
+            auto gram = [&](int q, int (&G)[RR]) {
+                const int row = 32 * wx + 8 * (q >> 2) + 4 * h + (q & 3);
 #pragma unroll
                 for (int r = 0; r < RR; ++r)
-                    G[r] = (long long)Lt - 2ll * (nA[r * 64 + row] + nBsrc[r * 64 + col]) +
-                           4ll * acc[r][q];
-                const int x1 = x % L, x2 = x / L, y1 = y % L, y2 = y / L;
-                const int dx = (x1 - y1 + L) % L, dy = (x2 - y2 + L) % L;
+                    G[r] = Lt - 2 * (nA[r * 64 + row] + nBsrc[r * 64 + col]) + 4 * acc[r][q];
+            };
+            if constexpr (BLK) {
+                // x1 - y1 by q mod 4 and x2 - y2 by q div 4, all sites valid
+                const int y1 = 8 * (Y % nbl) + (col & 7), y2 = 8 * (Y / nbl) + (col >> 3);
+                const int x1 = 8 * (X % nbl) + 4 * h, x2 = 8 * (X / nbl) + 4 * wx;
+                int Gq[RR][16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    int G[RR];
+                    gram(q, G);
+#pragma unroll
+                    for (int r = 0; r < RR; ++r) Gq[r][q] = G[r];
+                }
                 int p = 0;
 #pragma unroll
                 for (int a = 0; a < RR; ++a)
 #pragma unroll
                     for (int b = a + 1; b < RR; ++b, ++p) {
-                        const unsigned long long h = (unsigned long long)(G[a] * G[b]);
-                        atomicAdd(&Dblk[(p * 2 + 0) * L + dx], h);
-                        atomicAdd(&Dblk[(p * 2 + 1) * L + dy], h);
-                        if (!diag) {  // the mirror element (y, x)
-                            atomicAdd(&Dblk[(p * 2 + 0) * L + (L - dx) % L], h);
-                            atomicAdd(&Dblk[(p * 2 + 1) * L + (L - dy) % L], h);
+                        long long sx[4] = {0, 0, 0, 0}, sy[4] = {0, 0, 0, 0};
+#pragma unroll
+                        for (int q = 0; q < 16; ++q) {
+                            const long long hv = (long long)Gq[a][q] * Gq[b][q];
+                            sx[q & 3] += hv;
+                            sy[q >> 2] += hv;
+                        }
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            atomicAdd(&Db[(p * 2 + 0) * L + (x1 + j - y1 + L) % L], (unsigned long long)sx[j]);
+                            atomicAdd(&Db[(p * 2 + 1) * L + (x2 + j - y2 + L) % L], (unsigned long long)sy[j]);
                         }
                     }
+            } else {
+                const int y = 64 * Y + col;
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int x = 64 * X + 32 * wx + 8 * (q >> 2) + 4 * h + (q & 3);
+                    if (x >= L2 || y >= L2) continue;
+                    int G[RR];
+                    gram(q, G);
+                    const int dx = (x % L - y % L + L) % L, dy = (x / L - y / L + L) % L;
+                    int p = 0;
+#pragma unroll
+                    for (int a = 0; a < RR; ++a)
+#pragma unroll
+                        for (int b = a + 1; b < RR; ++b, ++p) {
+                            const unsigned long long hv = (unsigned long long)((long long)G[a] * G[b]);
+                            atomicAdd(&Db[(p * 2 + 0) * L + dx], hv);
+                            atomicAdd(&Db[(p * 2 + 1) * L + dy], hv);
+                        }
+                }
             }
         }
         __syncthreads();
+        // D[d] = F[d] + U[d] + U[-d]; sum Q^2 = sum_xy G^a_xy G^b_xy =
+        // sum_d D_x[d] (one workgroup holds all of this configuration's
+        // buckets)
         const int rl = 2 * L + 3;
         for (int e = tid; e < PP * 2 * L; e += 256) {
-            const int p = e / (2 * L), d = e % (2 * L);
-            atomicAdd((unsigned long long*)&sh.rec[((size_t)cfg * PP + p) * rl + d], Dblk[e]);
-            Dblk[e] = 0;
+            const int d = e % L;
+            Fb[e] += Ub[e] + Ub[e - d + (L - d) % L];
         }
+        __syncthreads();
+        if (tid < PP) {
+            unsigned long long q2 = 0;
+            for (int d = 0; d < L; ++d) q2 += Fb[(tid * 2 + 0) * L + d];
+            sh.rec[((size_t)cfg * PP + tid) * rl + 2 * L + 1] = (int64_t)q2;
+        }
+        for (int e = tid; e < PP * 2 * L; e += 256) {
+            const int p = e / (2 * L), d = e % (2 * L);
+            sh.rec[((size_t)cfg * PP + p) * rl + d] = (int64_t)Fb[e];
+        }
+        __syncthreads();
+        for (int e = tid; e < 2 * PP * 2 * L; e += 256) Fb[e] = 0;
     }
 }
 
 // ---------------------------------------------------------------------------
-// Q tiles: trQ, sum Q^2, sum Q^4 for the pairs P0 .. P0 + NP - 1 (pairs a < b
-// in lexicographic order).  Up to 4 replicas one launch takes every pair;
-// with 5 or 6 one launch per group of 5 pairs keeps the accumulators of a
-// tile (16 per pair and lane) within the register budget.
+// Q tiles: trQ and sum Q^4 for the pairs P0 .. P0 + NP - 1 (pairs a < b in
+// lexicographic order; sum Q^2 comes from the Gram buckets).
+//
+// Every wave works alone, with no LDS and no barrier: a 64 x 64 tile
+// (tau in 64T + [0, 64), tau' in 64T2 + [0, 64)) of each of its pairs as
+// 2 x 2 blocks of 32 x 32, the accumulators (64 registers per pair, three
+// pairs per launch) in the AGPRs, one wave per SIMD.  The operands come straight from each lane's
+// packed row words: in K step ks of chunk g, lane (i, h) of a block feeds
+// row i with bits 8j + 4h + m (j, m < 4) of the 32-bit half ks of its word,
+// one byte each, in the same order on both sides.  Row-side bytes are 4 B
+// (0 or 4), column-side bytes B, so the K steps sum 4 B^aT B^b; one more K
+// step adds X_tau + Y_tau' with X = h2 - 2 m^a_tau and
+// Y = (L^2 - h2) - 2 m^b_tau' (h2 = floor(L^2 / 2)), held as sixteen int8
+// pieces on one side against ones on the other.  The accumulator is then
+// Q itself: the epilogue squares it twice and adds.
+//
+// Waves form teams of wc.  Team t takes configurations t, t + nteams, ...;
+// its member j the tiles j, j + wc, ... of each, and it flushes its sums
+// once per configuration.  Workgroup b runs on XCD b mod nxcd, so a team
+// no larger than an XCD's share of waves reads its rows from one L2.
 // ---------------------------------------------------------------------------
 template <int RR, int P0, int NP>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
-k_overlap_mfma(ShapeDev sh, int cfg0, int ncfg) {
-    extern __shared__ __align__(16) uint8_t smem[];
-    uint8_t* Al = smem;
-    uint8_t* Bl = smem + RR * 64 * kRowPitch;
-    int* mA = (int*)(Bl + RR * 64 * kRowPitch);
-    int* mB = mA + RR * 64;
-    unsigned long long* red = (unsigned long long*)(mB + RR * 64);  // [NP][2]: trQ, sum Q^4
-    const int L2 = sh.L2, Lt = sh.Lt;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int wx = wv & 1, wy = wv >> 1;
-    const int ntt = (Lt + 63) / 64;
-    constexpr int kRows = 2 * RR * 64;        // operand rows of one K chunk (A and B)
-    constexpr int kPer = (kRows + 255) / 256;  // rows per thread
-    for (int e = tid; e < NP * 2; e += 256) red[e] = 0;
-    for (int cfg = cfg0 + blockIdx.x; cfg < cfg0 + ncfg; cfg += gridDim.x) {
-        unsigned long long s4u[NP];
-        long long tr[NP];
+struct PairSides {
+    int na = 0, nb = 0;
+    int ra[RR] = {}, rb[RR] = {};  // replica of each row-side / column-side slot
+    int pa[NP] = {}, pb[NP] = {};  // slots of pair P0 + p
+    constexpr PairSides() {
+        int sa[RR] = {}, sb[RR] = {};
+        for (int r = 0; r < RR; ++r) sa[r] = sb[r] = -1;
+        int p = 0;
+        for (int a = 0; a < RR; ++a)
+            for (int b = a + 1; b < RR; ++b, ++p) {
+                if (p < P0 || p >= P0 + NP) continue;
+                if (sa[a] < 0) { sa[a] = na; ra[na++] = a; }
+                if (sb[b] < 0) { sb[b] = nb; rb[nb++] = b; }
+                pa[p - P0] = sa[a];
+                pb[p - P0] = sb[b];
+            }
+    }
+};
+
+// K-step operand of one lane from the 32-bit word half x pre-shifted by 4h:
+// byte j of dword m = bit 8j + m of x, times 4 on the row side.
+template <bool kRow>
+__device__ __forceinline__ v4i bits_operand(uint32_t x) {
+    v4i o;
+    if constexpr (kRow) {
+        const uint32_t x4 = x << 2;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) o[m] = (int)((x4 >> m) & 0x04040404u);
+    } else {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) o[m] = (int)((x >> m) & 0x01010101u);
+    }
+    return o;
+}
+
+// Sixteen int8 bytes summing to v, |v| <= 1792: fifteen of floor(v / 16) and
+// one of floor(v / 16) + (v mod 16).
+__device__ __forceinline__ v4i pieces16(int v) {
+    const int q = v >> 4, r = v & 15;
+    const uint32_t rep = (uint32_t)(q & 0xFF) * 0x01010101u;
+    v4i o;
+    o[0] = (int)((rep & 0xFFFFFF00u) | (uint32_t)((q + r) & 0xFF));
+    o[1] = o[2] = o[3] = (int)rep;
+    return o;
+}
+
+constexpr int kTeamWaves = 4;  // waves per workgroup of the overlap kernel
+
+template <int RR, int P0, int NP>
+__global__ void __launch_bounds__(64 * kTeamWaves) __attribute__((amdgpu_waves_per_eu(1, 1)))
+k_overlap_mfma(ShapeDev sh, int cfg0, int ncfg, int wc, int nxcd) {
+    constexpr PairSides<RR, P0, NP> ps{};
+    constexpr int NA = ps.na, NB = ps.nb;
+    constexpr int PP = RR * (RR - 1) / 2;
+    const int lane = threadIdx.x & 63, i = lane & 31, h = lane >> 5, sh4 = 4 * h;
+    const int G = gridDim.x * kTeamWaves, gx = G / nxcd;
+    const int xcd = blockIdx.x % nxcd;
+    const int s = (blockIdx.x / nxcd) * kTeamWaves + (threadIdx.x >> 6);
+    int team, member;
+    if (wc <= gx) {
+        team = xcd * (gx / wc) + s / wc;
+        member = s % wc;
+    } else {
+        const int k = wc / gx;
+        team = xcd / k;
+        member = (xcd % k) * gx + s;
+    }
+    const int nteams = G / wc;
+    const int L2 = sh.L2, Lt = sh.Lt, nx = sh.nx, ntt = (Lt + 63) / 64, ntiles = ntt * ntt;
+    const int h2 = L2 >> 1;
+    const int rl = 2 * sh.L + 3;
+    if (member >= ntiles) return;
+    for (int cfg = cfg0 + team; cfg < cfg0 + ncfg; cfg += nteams) {
+        unsigned long long s4[NP];
+        int tr[NP];
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
-            s4u[p] = 0;
+            s4[p] = 0;
             tr[p] = 0;
         }
-        for (int tt = 0; tt < ntt * ntt; ++tt) {
-            const int T = tt / ntt, T2 = tt % ntt;
-            const bool diag = T == T2;
-            const uint8_t* Bsrc = diag ? Al : Bl;
-            const int* mBsrc = diag ? mA : mB;
-            const int nrows = (diag ? 1 : 2) * RR * 64;
-            // operand rows of K chunk g: side (A: tile T, B: tile T2), replica, tau
-            auto fetch = [&](int g, uint64_t (&v)[kPer]) {
-                const uint64_t vm = low_bits(L2 - 64 * g);
+        const uint64_t* const px = sh.Px + (size_t)cfg * RR * nx * Lt;
+        for (int t = member; t < ntiles; t += wc) {
+            const int T = t / ntt, T2 = t - T * ntt;
+            // this lane's rows: tau = 64T + 32u + i (row side), 64T2 + 32v + i
+            // (column side), clamped into [0, Lt): a row past Lt only feeds
+            // elements of its own row or column, which the epilogue skips, and
+            // loads without a branch let the wait counts stay exact
+            const int ta0 = 64 * T + i, tb0 = 64 * T2 + i;
+            const int rowa[2] = {min(ta0, Lt - 1), min(ta0 + 32, Lt - 1)};
+            const int rowb[2] = {min(tb0, Lt - 1), min(tb0 + 32, Lt - 1)};
+            auto fetch = [&](int g, uint64_t (&wa)[2][NA], uint64_t (&wb)[2][NB]) {
 #pragma unroll
-                for (int k = 0; k < kPer; ++k) {
-                    const int e = tid + 256 * k;
-                    v[k] = 0;
-                    if (e < nrows) {
-                        const int side = e / (RR * 64), rr = (e / 64) % RR, row = e & 63;
-                        const int tau = 64 * (side ? T2 : T) + row;
-                        const size_t m = (size_t)cfg * RR + rr;
-                        v[k] = tau < Lt ? (sh.Px[(m * sh.nx + g) * Lt + tau] & vm) : 0ull;
-                    }
+                for (int u = 0; u < 2; ++u) {
+#pragma unroll
+                    for (int a = 0; a < NA; ++a) wa[u][a] = px[((size_t)ps.ra[a] * nx + g) * Lt + rowa[u]];
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) wb[u][b] = px[((size_t)ps.rb[b] * nx + g) * Lt + rowb[u]];
                 }
             };
-            v16i acc[NP];
+            v16i acc[NP][2][2];
 #pragma unroll
             for (int p = 0; p < NP; ++p)
 #pragma unroll
-                for (int q = 0; q < 16; ++q) acc[p][q] = 0;
-            uint64_t vn[kPer];
-            fetch(0, vn);
-            __syncthreads();  // previous tile's epilogue has read mA, mB
-            for (int e = tid; e < 2 * RR * 64; e += 256) mA[e] = 0;
-            for (int g = 0; g < sh.nx; ++g) {
-                __syncthreads();
+                for (int u = 0; u < 2; ++u)
 #pragma unroll
-                for (int k = 0; k < kPer; ++k) {
-                    const int e = tid + 256 * k;
-                    if (e < nrows) {
-                        const int side = e / (RR * 64), rr = (e / 64) % RR, row = e & 63;
-                        (side ? mB : mA)[rr * 64 + row] += __popcll(vn[k]);
-                        unpack64(vn[k], (side ? Bl : Al) + (rr * 64 + row) * kRowPitch);
-                    }
+                    for (int v = 0; v < 2; ++v)
+#pragma unroll
+                        for (int q = 0; q < 16; ++q) acc[p][u][v][q] = 0;
+            int ma[2][NA], mb[2][NB];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+#pragma unroll
+                for (int a = 0; a < NA; ++a) ma[u][a] = 0;
+#pragma unroll
+                for (int b = 0; b < NB; ++b) mb[u][b] = 0;
+            }
+            auto chunk = [&](const uint64_t (&wa)[2][NA], const uint64_t (&wb)[2][NB]) {
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+#pragma unroll
+                    for (int a = 0; a < NA; ++a) ma[u][a] += __popcll(wa[u][a]);
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) mb[u][b] += __popcll(wb[u][b]);
                 }
-                __syncthreads();
-                if (g + 1 < sh.nx) fetch(g + 1, vn);  // in flight during the MFMAs
 #pragma unroll
                 for (int ks = 0; ks < 2; ++ks) {
-                    const int ko = 32 * ks + 16 * (lane >> 5);
-                    v4i a[RR - 1], b[RR - 1];
+                    v4i A[2][NA], B[2][NB];
 #pragma unroll
-                    for (int r = 0; r < RR - 1; ++r) {
-                        a[r] = lds_v4(Al + (r * 64 + 32 * wx + (lane & 31)) * kRowPitch + ko);
-                        b[r] = lds_v4(Bsrc + ((r + 1) * 64 + 32 * wy + (lane & 31)) * kRowPitch + ko);
+                    for (int u = 0; u < 2; ++u) {
+#pragma unroll
+                        for (int a = 0; a < NA; ++a)
+                            A[u][a] = bits_operand<true>((uint32_t)(wa[u][a] >> (32 * ks)) >> sh4);
+#pragma unroll
+                        for (int b = 0; b < NB; ++b)
+                            B[u][b] = bits_operand<false>((uint32_t)(wb[u][b] >> (32 * ks)) >> sh4);
                     }
-                    int p = 0;
 #pragma unroll
-                    for (int ra = 0; ra < RR; ++ra)
+                    for (int p = 0; p < NP; ++p)
 #pragma unroll
-                        for (int rb = ra + 1; rb < RR; ++rb, ++p)
-                            if (p >= P0 && p < P0 + NP)
-                                acc[p - P0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[ra], b[rb - 1],
-                                                                                    acc[p - P0], 0, 0, 0);
+                        for (int u = 0; u < 2; ++u)
+#pragma unroll
+                            for (int v = 0; v < 2; ++v)
+                                acc[p][u][v] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                                    A[u][ps.pa[p]], B[v][ps.pb[p]], acc[p][u][v], 0, 0, 0);
                 }
+            };
+            // two word sets in turn, the next chunk's loads in flight during
+            // this chunk's MFMAs; the loop body is one straight block (past
+            // the last chunk a fetch reloads it) so that the loads stay ahead
+            // of their uses and the wait counts are fixed
+            uint64_t w0a[2][NA], w0b[2][NB], w1a[2][NA], w1b[2][NB];
+            fetch(0, w0a, w0b);
+            for (int g = 0; g + 1 < nx; g += 2) {
+                fetch(g + 1, w1a, w1b);
+                chunk(w0a, w0b);
+                fetch(min(g + 2, nx - 1), w0a, w0b);
+                chunk(w1a, w1b);
             }
-            __syncthreads();
-            // epilogue: Q = L^2 - 2 (m_tau + m_tau') + 4 B^aT B^b; |Q| <= L^2,
-            // Q^2 < 2^19, Q^4 < 2^38
-            const int col = 32 * wy + (lane & 31);
-            const int tau2 = 64 * T2 + col;
-            int cc[RR];
+            if (nx & 1) chunk(w0a, w0b);
+            // the correction step: X on the row side's first half-wave, Y on
+            // the column side's second, ones against them
+            {
+                const v4i ones = {0x01010101, 0x01010101, 0x01010101, 0x01010101};
+                v4i A[2][NA], B[2][NB];
 #pragma unroll
-            for (int rb = 0; rb < RR; ++rb) cc[rb] = -2 * mBsrc[rb * 64 + col];
-            if (!diag && 64 * (T + 1) <= Lt && 64 * (T2 + 1) <= Lt) {
-                // interior off-diagonal tile: no bounds, no trace; Q^4 summed
-                // unsigned, one 32x32->64 multiply-add per element and pair
+                for (int u = 0; u < 2; ++u) {
 #pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    const int row = 32 * wx + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
-                    int cr[RR];
+                    for (int a = 0; a < NA; ++a) A[u][a] = h ? ones : pieces16(h2 - 2 * ma[u][a]);
 #pragma unroll
-                    for (int ra = 0; ra < RR; ++ra) cr[ra] = L2 - 2 * mA[ra * 64 + row];
-                    int p = 0;
-#pragma unroll
-                    for (int ra = 0; ra < RR; ++ra)
-#pragma unroll
-                        for (int rb = ra + 1; rb < RR; ++rb, ++p) {
-                            if (p < P0 || p >= P0 + NP) continue;
-                            const int qv = cr[ra] + cc[rb] + 4 * acc[p - P0][q];
-                            const uint32_t q2 = (uint32_t)(qv * qv);
-                            s4u[p - P0] += (unsigned long long)q2 * q2;
-                        }
+                    for (int b = 0; b < NB; ++b) B[u][b] = h ? pieces16(L2 - h2 - 2 * mb[u][b]) : ones;
                 }
+#pragma unroll
+                for (int p = 0; p < NP; ++p)
+#pragma unroll
+                    for (int u = 0; u < 2; ++u)
+#pragma unroll
+                        for (int v = 0; v < 2; ++v)
+                            acc[p][u][v] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                                A[u][ps.pa[p]], B[v][ps.pb[p]], acc[p][u][v], 0, 0, 0);
+            }
+            // epilogue: |Q| <= L^2, Q^2 < 2^20, Q^4 < 2^40
+            if (64 * (T + 1) <= Lt && 64 * (T2 + 1) <= Lt && T != T2) {
+#pragma unroll
+                for (int p = 0; p < NP; ++p)
+#pragma unroll
+                    for (int u = 0; u < 2; ++u)
+#pragma unroll
+                        for (int v = 0; v < 2; ++v)
+#pragma unroll
+                            for (int q = 0; q < 16; ++q) {
+                                const int qv = acc[p][u][v][q];
+                                const uint32_t q2 = (uint32_t)__mul24(qv, qv);
+                                s4[p] += (unsigned long long)q2 * q2;
+                            }
             } else {
 #pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    const int row = 32 * wx + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
-                    const int tau = 64 * T + row;
-                    if (tau >= Lt || tau2 >= Lt) continue;
-                    int cr[RR];
+                for (int u = 0; u < 2; ++u)
 #pragma unroll
-                    for (int ra = 0; ra < RR; ++ra) cr[ra] = L2 - 2 * mA[ra * 64 + row];
-                    int p = 0;
+                    for (int v = 0; v < 2; ++v) {
+                        const int col = 64 * T2 + 32 * v + i;
 #pragma unroll
-                    for (int ra = 0; ra < RR; ++ra)
+                        for (int q = 0; q < 16; ++q) {
+                            const int row = 64 * T + 32 * u + 8 * (q >> 2) + 4 * h + (q & 3);
+                            if (row >= Lt || col >= Lt) continue;
 #pragma unroll
-                        for (int rb = ra + 1; rb < RR; ++rb, ++p) {
-                            if (p < P0 || p >= P0 + NP) continue;
-                            const int qv = cr[ra] + cc[rb] + 4 * acc[p - P0][q];
-                            const uint32_t q2 = (uint32_t)__mul24(qv, qv);
-                            s4u[p - P0] += (unsigned long long)q2 * q2;
-                            if (diag && tau == tau2) tr[p - P0] += qv;
+                            for (int p = 0; p < NP; ++p) {
+                                const int qv = acc[p][u][v][q];
+                                const uint32_t q2 = (uint32_t)__mul24(qv, qv);
+                                s4[p] += (unsigned long long)q2 * q2;
+                                if (row == col) tr[p] += qv;
+                            }
                         }
-                }
+                    }
             }
         }
-        // per-configuration flush: wave reduction, then one atomic per value
+        // per-configuration flush: wave reduction, one atomic per value
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) {
-                s4u[p] += (unsigned long long)__shfl_xor((long long)s4u[p], off, 64);
+                s4[p] += (unsigned long long)__shfl_xor((long long)s4[p], off, 64);
                 tr[p] += __shfl_xor(tr[p], off, 64);
             }
         }
         if (lane == 0) {
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
-                atomicAdd(&red[p * 2 + 0], (unsigned long long)tr[p]);
-                atomicAdd(&red[p * 2 + 1], s4u[p]);
+                unsigned long long* rp = (unsigned long long*)(sh.rec + ((size_t)cfg * PP + P0 + p) * rl);
+                atomicAdd(rp + 2 * sh.L, (unsigned long long)(long long)tr[p]);
+                atomicAdd(rp + 2 * sh.L + 2, s4[p]);
             }
         }
-        __syncthreads();
-        // sum Q^2 = sum_xy G^a_xy G^b_xy = sum_d D_x[d]: the Gram kernel's
-        // buckets of this configuration are complete (earlier launch)
-        const int rl = 2 * sh.L + 3;
-        constexpr int PP = RR * (RR - 1) / 2;
-        for (int e = tid; e < NP * 3; e += 256) {
-            const int p = e / 3, k = e % 3;
-            int64_t* rp = sh.rec + ((size_t)cfg * PP + P0 + p) * rl;
-            if (k == 1) {
-                int64_t q2 = 0;
-                for (int d = 0; d < sh.L; ++d) q2 += rp[d];
-                rp[2 * sh.L + 1] = q2;
-            } else {
-                rp[2 * sh.L + k] = (int64_t)red[p * 2 + (k == 0 ? 0 : 1)];
-            }
-        }
-        __syncthreads();
-        for (int e = tid; e < NP * 2; e += 256) red[e] = 0;
     }
 }
 
@@ -512,22 +656,18 @@ __global__ void k_buckets(ShapeDev sh) {
 
 size_t gram_lds(int RR, int L) {
     const int PP = RR * (RR - 1) / 2;
-    return (size_t)2 * RR * 64 * kRowPitch + (size_t)2 * RR * 64 * 4 + (size_t)PP * 2 * L * 8;
+    return (size_t)2 * RR * 64 * kRowPitch + (size_t)2 * RR * 64 * 4 + (size_t)2 * PP * 2 * L * 8;
 }
-size_t overlap_lds(int RR, int NP) {
-    return (size_t)2 * RR * 64 * kRowPitch + (size_t)2 * RR * 64 * 4 + (size_t)NP * 2 * 8;
-}
-
 // Pairs P0 .. PP - 1 of RR replicas in launches of at most NP pairs.
 template <int RR, int P0, int NP>
-hipError_t launch_overlap(const ShapeDev& sh, int cfg0, int ncfg, int grid, hipStream_t st) {
+hipError_t launch_overlap(const ShapeDev& sh, int cfg0, int ncfg, int grid, int wc, int nxcd, hipStream_t st) {
     constexpr int PP = RR * (RR - 1) / 2;
     constexpr int n = PP - P0 < NP ? PP - P0 : NP;
-    hipLaunchKernelGGL((k_overlap_mfma<RR, P0, n>), dim3(grid), dim3(256), overlap_lds(RR, n), st, sh, cfg0,
-                       ncfg);
+    hipLaunchKernelGGL((k_overlap_mfma<RR, P0, n>), dim3(grid), dim3(64 * kTeamWaves), 0, st, sh, cfg0, ncfg,
+                       wc, nxcd);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if constexpr (P0 + n < PP) return launch_overlap<RR, P0 + n, NP>(sh, cfg0, ncfg, grid, st);
+    if constexpr (P0 + n < PP) return launch_overlap<RR, P0 + n, NP>(sh, cfg0, ncfg, grid, wc, nxcd, st);
     return hipSuccess;
 }
 
@@ -539,16 +679,31 @@ hipError_t launch_mfma(const ShapeDev& sh, int cfg0, int ncfg, hipStream_t st) {
     const int grid = std::min(ncfg, 4 * ncu);
     static bool lds_set = false;  // 6 replicas at L = 32 take above 64 KiB
     if (!lds_set) {
-        const hipError_t e = hipFuncSetAttribute((const void*)k_gram_mfma<RR>,
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                 (int)gram_lds(RR, 32));
-        if (e != hipSuccess) return e;
+        for (const void* f : {(const void*)k_gram_mfma<RR, true>, (const void*)k_gram_mfma<RR, false>}) {
+            const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     (int)gram_lds(RR, 32));
+            if (e != hipSuccess) return e;
+        }
         lds_set = true;
     }
-    hipLaunchKernelGGL(k_gram_mfma<RR>, dim3(grid), dim3(256), gram_lds(RR, sh.L), st, sh, cfg0, ncfg);
+    if (sh.L % 8 == 0)
+        hipLaunchKernelGGL((k_gram_mfma<RR, true>), dim3(grid), dim3(256), gram_lds(RR, sh.L), st, sh, cfg0, ncfg);
+    else
+        hipLaunchKernelGGL((k_gram_mfma<RR, false>), dim3(grid), dim3(256), gram_lds(RR, sh.L), st, sh, cfg0, ncfg);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_overlap<RR, 0, (RR <= 4 ? RR * (RR - 1) / 2 : 5)>(sh, cfg0, ncfg, grid, st);
+    // overlap: one workgroup of kTeamWaves waves per CU; teams of wc waves,
+    // an XCD's share (a power-of-two fraction of it while a configuration
+    // has fewer tiles, a multiple while there are fewer configurations than
+    // teams)
+    const int nxcd = ncu % 8 == 0 ? 8 : 1;
+    const int G = kTeamWaves * ncu, gx = G / nxcd;
+    const int ntt = (sh.Lt + 63) / 64, ntiles = ntt * ntt;
+    int wc = gx;
+    while (wc % 2 == 0 && wc / 2 >= ntiles) wc /= 2;
+    auto fits = [&](int w) { return w <= gx ? gx % w == 0 : (w % gx == 0 && nxcd % (w / gx) == 0); };
+    while (wc < G && G / wc > ncfg && fits(2 * wc)) wc *= 2;
+    return launch_overlap<RR, 0, 3>(sh, cfg0, ncfg, ncu, wc, nxcd, st);
 }
 
 }  // namespace

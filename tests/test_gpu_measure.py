@@ -34,7 +34,8 @@ def _oracle_records(sh, seed, lanes, sweeps, k_indices=None):
 
 @pytest.mark.parametrize("L,Lt,R,nk", [(4, 16, 2, 3), (6, 40, 3, 2), (8, 64, 4, 3),
                                        (10, 136, 4, 2), (12, 24, 2, 4), (8, 64, 6, 2),
-                                       (10, 72, 5, 2), (24, 16, 6, 1)])
+                                       (10, 72, 5, 2), (24, 16, 6, 1), (16, 32, 4, 2),
+                                       (20, 24, 4, 1), (24, 40, 4, 1), (22, 8, 6, 1)])
 @pytest.mark.parametrize("mode", [0, 1])
 def test_records_match_oracle(L, Lt, R, nk, mode):
     sh = Shape(L, Lt, 1, R, ladder(0.2, 0.45, nk), pt_every=1)

@@ -268,7 +268,9 @@ def timecorr_leg(plan, sh, torch, args):
     L2, Lt, R = sh.L * sh.L, sh.Ltau, sh.n_replicas
     ntt = (Lt + 63) // 64
     alg = Lt * (Lt + 1) * L2 * R                                   # symmetric H, mul + add
-    exe = (ntt * (ntt + 1) // 2) * 2 * 64 * 64 * 64 * ((L2 + 63) // 64) * R
+    # executed: 64 x 64 tiles of the upper triangle, K = 64 per chunk plus the
+    # 32-wide correction step, replicas taken two at a time
+    exe = (ntt * (ntt + 1) // 2) * 2 * 64 * 64 * (64 * ((L2 + 63) // 64) + 32) * (2 * ((R + 1) // 2))
     chunk = min(args.triples_chunk, ncfg)
     stream = torch.cuda.current_stream()
     plan.measure_time(0, 0, chunk, copy=False)

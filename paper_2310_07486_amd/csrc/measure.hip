@@ -326,33 +326,6 @@ struct PairSides {
     }
 };
 
-// K-step operand of one lane from the 32-bit word half x pre-shifted by 4h:
-// byte j of dword m = bit 8j + m of x, times 4 on the row side.
-template <bool kRow>
-__device__ __forceinline__ v4i bits_operand(uint32_t x) {
-    v4i o;
-    if constexpr (kRow) {
-        const uint32_t x4 = x << 2;
-#pragma unroll
-        for (int m = 0; m < 4; ++m) o[m] = (int)((x4 >> m) & 0x04040404u);
-    } else {
-#pragma unroll
-        for (int m = 0; m < 4; ++m) o[m] = (int)((x >> m) & 0x01010101u);
-    }
-    return o;
-}
-
-// Sixteen int8 bytes summing to v, |v| <= 1792: fifteen of floor(v / 16) and
-// one of floor(v / 16) + (v mod 16).
-__device__ __forceinline__ v4i pieces16(int v) {
-    const int q = v >> 4, r = v & 15;
-    const uint32_t rep = (uint32_t)(q & 0xFF) * 0x01010101u;
-    v4i o;
-    o[0] = (int)((rep & 0xFFFFFF00u) | (uint32_t)((q + r) & 0xFF));
-    o[1] = o[2] = o[3] = (int)rep;
-    return o;
-}
-
 constexpr int kTeamWaves = 4;  // waves per workgroup of the overlap kernel
 
 template <int RR, int P0, int NP>
@@ -438,10 +411,10 @@ k_overlap_mfma(ShapeDev sh, int cfg0, int ncfg, int wc, int nxcd) {
                     for (int u = 0; u < 2; ++u) {
 #pragma unroll
                         for (int a = 0; a < NA; ++a)
-                            A[u][a] = bits_operand<true>((uint32_t)(wa[u][a] >> (32 * ks)) >> sh4);
+                            A[u][a] = mfma_bits_operand<true>((uint32_t)(wa[u][a] >> (32 * ks)) >> sh4);
 #pragma unroll
                         for (int b = 0; b < NB; ++b)
-                            B[u][b] = bits_operand<false>((uint32_t)(wb[u][b] >> (32 * ks)) >> sh4);
+                            B[u][b] = mfma_bits_operand<false>((uint32_t)(wb[u][b] >> (32 * ks)) >> sh4);
                     }
 #pragma unroll
                     for (int p = 0; p < NP; ++p)
@@ -474,9 +447,9 @@ k_overlap_mfma(ShapeDev sh, int cfg0, int ncfg, int wc, int nxcd) {
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
 #pragma unroll
-                    for (int a = 0; a < NA; ++a) A[u][a] = h ? ones : pieces16(h2 - 2 * ma[u][a]);
+                    for (int a = 0; a < NA; ++a) A[u][a] = h ? ones : mfma_pieces16(h2 - 2 * ma[u][a]);
 #pragma unroll
-                    for (int b = 0; b < NB; ++b) B[u][b] = h ? pieces16(L2 - h2 - 2 * mb[u][b]) : ones;
+                    for (int b = 0; b < NB; ++b) B[u][b] = h ? mfma_pieces16(L2 - h2 - 2 * mb[u][b]) : ones;
                 }
 #pragma unroll
                 for (int p = 0; p < NP; ++p)

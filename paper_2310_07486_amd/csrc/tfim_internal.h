@@ -131,6 +131,40 @@ __device__ __forceinline__ uint64_t wave_transpose64(uint64_t v) {
     return v;
 }
 
+// Operands of v_mfma_i32_32x32x32_i8 built in registers from bit rows.  In K
+// step ks of a 64-bit chunk word w, lane (i, h) of a block feeds row i with
+// bits 8j + 4h + m (j, m < 4) of the 32-bit half ks of w, one byte each; the
+// same order on both sides of a product permutes K alike, so the dot product
+// is the popcount of the AND of the two rows.  x is the half already shifted
+// right by 4h; byte j of dword m is bit 8j + m of x, times 4 when kTimes4.
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+template <bool kTimes4>
+__device__ __forceinline__ i32x4 mfma_bits_operand(uint32_t x) {
+    i32x4 o;
+    if constexpr (kTimes4) {
+        const uint32_t x4 = x << 2;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) o[m] = (int)((x4 >> m) & 0x04040404u);
+    } else {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) o[m] = (int)((x >> m) & 0x01010101u);
+    }
+    return o;
+}
+
+// Sixteen int8 bytes summing to v, |v| <= 1792: fifteen of floor(v / 16) and
+// one of floor(v / 16) + (v mod 16).  Against sixteen ones on the other side
+// of one K step it adds v to every element of a row (or column).
+__device__ __forceinline__ i32x4 mfma_pieces16(int v) {
+    const int q = v >> 4, r = v & 15;
+    const uint32_t rep = (uint32_t)(q & 0xFF) * 0x01010101u;
+    i32x4 o;
+    o[0] = (int)((rep & 0xFFFFFF00u) | (uint32_t)((q + r) & 0xFF));
+    o[1] = o[2] = o[3] = (int)rep;
+    return o;
+}
+
 }  // namespace tfim
 
 // Kernel launchers (defined in the .hip files, called by the runtime).

@@ -43,7 +43,6 @@ namespace {
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-constexpr int kRowPitch = 80;  // bytes per unpacked 64-element row in LDS (16-byte aligned)
 constexpr int kMaxR = 6;       // replicas handled by the MFMA kernels
 constexpr int kMaxP = kMaxR * (kMaxR - 1) / 2;
 
@@ -99,37 +98,24 @@ __global__ void __launch_bounds__(256) k_transpose(ShapeDev sh, long long items)
     }
 }
 
-// 64 bits -> 64 bytes in {0,1} (byte t = bit t), written as four 16-byte stores.
-__device__ __forceinline__ void unpack64(uint64_t v, uint8_t* dst) {
-    uint32_t out[16];
-#pragma unroll
-    for (int d = 0; d < 16; ++d) {
-        const uint32_t nib = (uint32_t)(v >> (4 * d)) & 0xFu;
-        out[d] = __umul24(nib, 0x00204081u) & 0x01010101u;
-    }
-    v4i* p = (v4i*)dst;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        v4i x;
-        x[0] = (int)out[4 * q]; x[1] = (int)out[4 * q + 1];
-        x[2] = (int)out[4 * q + 2]; x[3] = (int)out[4 * q + 3];
-        p[q] = x;
-    }
-}
-
-__device__ __forceinline__ uint64_t low_bits(int n) {
-    return n >= 64 ? ~0ull : (n <= 0 ? 0ull : ((1ull << n) - 1ull));
-}
-
-__device__ __forceinline__ v4i lds_v4(const uint8_t* base) { return *(const v4i*)base; }
-
 // ---------------------------------------------------------------------------
 // G tiles and the D buckets.
 //
-// The tile pairs (X, Y), X <= Y, of the upper triangle cover every element:
-// an element (x, y) of an off-diagonal pair stands for (y, x) too, with the
-// displacements negated.  Its products go to U, those of diagonal pairs to
-// F, and the flush folds D[d] = F[d] + U[d] + U[-d mod L].
+// One workgroup takes one configuration at a time.  It first counts the
+// down spins n^r_x of every site row (popcount along tau) into LDS; then its
+// four waves share the tile pairs (X, Y), X <= Y, of the upper triangle,
+// each wave alone (no barrier inside a configuration), one wave per SIMD:
+// the 2 x 2 blocks of 32 x 32 of every replica's G^r = S S^T, accumulators
+// in the AGPRs, K = tau in chunks of 64, the {0,1} operands built in
+// registers from each lane's bit row.  The epilogue forms
+// G = Ltau - 2 (n_x + n_y) + 4 (B B^T)_xy and the products G^a G^b.
+//
+// An element (x, y) of an off-diagonal pair stands for (y, x) too, with the
+// displacements negated; its products go to U, those of the diagonal
+// blocks of diagonal pairs to F, and the flush folds D[d] = F[d] + U[d] +
+// U[-d mod L].  In a diagonal pair the block (rows 32.., columns 0..31) is
+// the mirror of (rows 0.., columns 32..): only the latter is computed, into
+// U.
 //
 // BLK (L a multiple of 8): tile X holds the 8 x 8 block of sites
 // (bx, by) = (X mod L/8, X div L/8), row r the site (8bx + r mod 8,
@@ -139,133 +125,193 @@ __device__ __forceinline__ v4i lds_v4(const uint8_t* base) { return *(const v4i*
 // Otherwise tile X holds the sites 64X .. 64X + 63 and every element adds
 // its own two.
 // ---------------------------------------------------------------------------
-template <int RR, bool BLK>
-__global__ void __launch_bounds__(256) k_gram_mfma(ShapeDev sh, int cfg0, int ncfg) {
+constexpr int kGramWaves = 4;
+
+template <int RR, int NV, bool BLK>
+__global__ void __launch_bounds__(64 * kGramWaves) __attribute__((amdgpu_waves_per_eu(1, 1)))
+k_gram_mfma(ShapeDev sh, int cfg0, int ncfg) {
     constexpr int PP = RR * (RR - 1) / 2;
     extern __shared__ __align__(16) uint8_t smem[];
-    uint8_t* Al = smem;                                   // [RR][64][kRowPitch]
-    uint8_t* Bl = smem + RR * 64 * kRowPitch;             // [RR][64][kRowPitch]
-    int* nA = (int*)(Bl + RR * 64 * kRowPitch);           // [RR][64]
-    int* nB = nA + RR * 64;                               // [RR][64]
-    unsigned long long* Fb = (unsigned long long*)(nB + RR * 64);  // [PP][2][L]
-    unsigned long long* Ub = Fb + PP * 2 * sh.L;                   // [PP][2][L]
-    const int L = sh.L, L2 = sh.L2, Lt = sh.Lt;
+    const int L = sh.L, L2 = sh.L2, Lt = sh.Lt, nc = sh.nc, nxp = sh.nxp;
+    unsigned long long* Fb = (unsigned long long*)smem;  // [PP][2][L]
+    unsigned long long* Ub = Fb + PP * 2 * L;             // [PP][2][L]
+    int* nS = (int*)(Ub + PP * 2 * L);                    // [RR][nxp]
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int wx = wv & 1, wy = wv >> 1, h = lane >> 5;
+    const int i = lane & 31, h = lane >> 5, sh4 = 4 * h;
     const int ntile = sh.nx;
     const int ntp = ntile * (ntile + 1) / 2;
     const int nbl = L >> 3;
-    // site of row r of tile X
     auto site = [&](int X, int r) {
         if constexpr (BLK) return (8 * (X / nbl) + (r >> 3)) * L + 8 * (X % nbl) + (r & 7);
         return 64 * X + r;
     };
-    for (int e = tid; e < 2 * PP * 2 * L; e += 256) Fb[e] = 0;  // F and U
+    for (int e = tid; e < 2 * PP * 2 * L; e += 64 * kGramWaves) Fb[e] = 0;  // F and U
     for (int cfg = cfg0 + blockIdx.x; cfg < cfg0 + ncfg; cfg += gridDim.x) {
-        for (int tp = 0; tp < ntp; ++tp) {
-            // tile pair (X, Y), X <= Y, in row-major order of the upper triangle
+        const uint64_t* const pt = sh.Pt + (size_t)cfg * RR * nc * nxp;
+        for (int e = tid; e < RR * nxp; e += 64 * kGramWaves) {
+            const int r = e / nxp, xy = e - r * nxp;
+            int n = 0;
+            for (int c = 0; c < nc; ++c) n += __popcll(pt[((size_t)r * nc + c) * nxp + xy]);
+            nS[e] = n;
+        }
+        __syncthreads();
+        // work units: tile pairs, or (NV = 1) their two column halves
+        for (int unit = wv; unit < ntp * (2 / NV); unit += kGramWaves) {
+            const int tp = NV == 2 ? unit : unit >> 1;
+            const int v0 = NV == 2 ? 0 : (unit & 1);  // first column block
             int X = 0, rem = tp;
             while (rem >= ntile - X) { rem -= ntile - X; ++X; }
             const int Y = X + rem;
-            const bool diag = X == Y;
-            const uint8_t* Bsrc = diag ? Al : Bl;
-            const int* nBsrc = diag ? nA : nB;
-            unsigned long long* Db = diag ? Fb : Ub;
-            v16i acc[RR];
+            const int sa[2] = {site(X, i), site(X, 32 + i)};
+            int sb[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) sb[v] = site(Y, 32 * (v0 + v) + i);
+            v16i acc[RR][2][NV];
 #pragma unroll
             for (int r = 0; r < RR; ++r)
 #pragma unroll
-                for (int q = 0; q < 16; ++q) acc[r][q] = 0;
-            __syncthreads();  // previous tile's epilogue has read nA, nB
-            for (int e = tid; e < 2 * RR * 64; e += 256) nA[e] = 0;  // nA and nB
-            for (int c = 0; c < sh.nc; ++c) {
-                __syncthreads();
-                const uint64_t vm = low_bits(Lt - 64 * c);
-                for (int e = tid; e < (diag ? 1 : 2) * RR * 64; e += 256) {
-                    const int side = e / (RR * 64), rr = (e / 64) % RR, row = e & 63;
-                    const size_t m = (size_t)cfg * RR + rr;
-                    const uint64_t v = sh.Pt[(m * sh.nc + c) * sh.nxp + site(side ? Y : X, row)] & vm;
-                    (side ? nB : nA)[rr * 64 + row] += __popcll(v);
-                    unpack64(v, (side ? Bl : Al) + (rr * 64 + row) * kRowPitch);
-                }
-                __syncthreads();
+                for (int u = 0; u < 2; ++u)
 #pragma unroll
-                for (int ks = 0; ks < 2; ++ks) {
-                    const int ko = 32 * ks + 16 * (lane >> 5);
+                    for (int v = 0; v < NV; ++v)
+#pragma unroll
+                        for (int q = 0; q < 16; ++q) acc[r][u][v][q] = 0;
+            // the K loop; kDiag: Y = X, the column rows are row rows (no
+            // loads of their own) and, with both column blocks, the block
+            // (1, 0) is skipped
+            auto kloop = [&](auto diagC) {
+                constexpr bool kDiag = decltype(diagC)::value;
+                constexpr int NB = kDiag ? 0 : NV;  // column-side words loaded
+                auto fetch = [&](int c, uint64_t (&wa)[2][RR], uint64_t (&wb)[NV][RR]) {
 #pragma unroll
                     for (int r = 0; r < RR; ++r) {
-                        const v4i a = lds_v4(Al + (r * 64 + 32 * wx + (lane & 31)) * kRowPitch + ko);
-                        const v4i b = lds_v4(Bsrc + (r * 64 + 32 * wy + (lane & 31)) * kRowPitch + ko);
-                        acc[r] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, acc[r], 0, 0, 0);
+                        const size_t o = ((size_t)r * nc + c) * nxp;
+#pragma unroll
+                        for (int u = 0; u < 2; ++u) wa[u][r] = pt[o + sa[u]];
+#pragma unroll
+                        for (int v = 0; v < NB; ++v) wb[v][r] = pt[o + sb[v]];
                     }
-                }
-            }
-            __syncthreads();  // popcounts complete
-            const int col = 32 * wy + (lane & 31);
-            // G^r of this lane's element q (|G| <= Ltau <= 2^16)
-            auto gram = [&](int q, int (&G)[RR]) {
-                const int row = 32 * wx + 8 * (q >> 2) + 4 * h + (q & 3);
+                };
+                auto chunk = [&](const uint64_t (&wa)[2][RR], const uint64_t (&wb)[NV][RR]) {
 #pragma unroll
-                for (int r = 0; r < RR; ++r)
-                    G[r] = Lt - 2 * (nA[r * 64 + row] + nBsrc[r * 64 + col]) + 4 * acc[r][q];
+                    for (int ks = 0; ks < 2; ++ks) {
+                        i32x4 A[2][RR], B[NV][RR];
+#pragma unroll
+                        for (int r = 0; r < RR; ++r) {
+#pragma unroll
+                            for (int u = 0; u < 2; ++u)
+                                A[u][r] = mfma_bits_operand<false>((uint32_t)(wa[u][r] >> (32 * ks)) >> sh4);
+#pragma unroll
+                            for (int v = 0; v < NB; ++v)
+                                B[v][r] = mfma_bits_operand<false>((uint32_t)(wb[v][r] >> (32 * ks)) >> sh4);
+                        }
+#pragma unroll
+                        for (int r = 0; r < RR; ++r)
+#pragma unroll
+                            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                                for (int v = 0; v < NV; ++v) {
+                                    if (kDiag && NV == 2 && u == 1 && v == 0) continue;
+                                    const i32x4 b = kDiag ? A[NV == 2 ? v : v0][r] : B[v][r];
+                                    acc[r][u][v] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[u][r], b, acc[r][u][v],
+                                                                                         0, 0, 0);
+                                }
+                    }
+                };
+                // two word sets in turn, the next chunk in flight during this
+                // one; one straight loop block (a fetch past the last chunk
+                // reloads it) keeps the loads ahead and the waits exact
+                uint64_t w0a[2][RR], w0b[NV][RR], w1a[2][RR], w1b[NV][RR];
+                fetch(0, w0a, w0b);
+                for (int c = 0; c + 1 < nc; c += 2) {
+                    fetch(c + 1, w1a, w1b);
+                    chunk(w0a, w0b);
+                    fetch(min(c + 2, nc - 1), w0a, w0b);
+                    chunk(w1a, w1b);
+                }
+                if (nc & 1) chunk(w0a, w0b);
             };
-            if constexpr (BLK) {
-                // x1 - y1 by q mod 4 and x2 - y2 by q div 4, all sites valid
-                const int y1 = 8 * (Y % nbl) + (col & 7), y2 = 8 * (Y / nbl) + (col >> 3);
-                const int x1 = 8 * (X % nbl) + 4 * h, x2 = 8 * (X / nbl) + 4 * wx;
-                int Gq[RR][16];
+            const bool diag = X == Y;
+            if (diag)
+                kloop(std::true_type{});
+            else
+                kloop(std::false_type{});
+            // epilogue, block by block
 #pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    int G[RR];
-                    gram(q, G);
+            for (int u = 0; u < 2; ++u)
 #pragma unroll
-                    for (int r = 0; r < RR; ++r) Gq[r][q] = G[r];
-                }
-                int p = 0;
+                for (int v = 0; v < NV; ++v) {
+                    const int V = v0 + v;  // column block in the tile
+                    if (diag && NV == 2 && u == 1 && V == 0) continue;
+                    unsigned long long* Db = (diag && (NV == 1 || u == V)) ? Fb : Ub;
+                    const int ys = sb[v];  // this lane's column site
+                    int nb[RR];
 #pragma unroll
-                for (int a = 0; a < RR; ++a)
+                    for (int r = 0; r < RR; ++r) nb[r] = Lt - 2 * nS[r * nxp + ys];
+                    // G^r of element q (|G| <= Ltau <= 2^16)
+                    auto gram = [&](int q, int (&G)[RR]) {
+                        const int xs = site(X, 32 * u + 8 * (q >> 2) + 4 * h + (q & 3));
 #pragma unroll
-                    for (int b = a + 1; b < RR; ++b, ++p) {
-                        long long sx[4] = {0, 0, 0, 0}, sy[4] = {0, 0, 0, 0};
+                        for (int r = 0; r < RR; ++r) G[r] = nb[r] - 2 * nS[r * nxp + xs] + 4 * acc[r][u][v][q];
+                    };
+                    if constexpr (BLK) {
+                        // x1 - y1 by q mod 4 and x2 - y2 by q div 4, all sites valid
+                        const int col = 32 * V + i;
+                        const int y1 = 8 * (Y % nbl) + (col & 7), y2 = 8 * (Y / nbl) + (col >> 3);
+                        const int x1 = 8 * (X % nbl) + 4 * h, x2 = 8 * (X / nbl) + 4 * u;
+                        int Gq[RR][16];
 #pragma unroll
                         for (int q = 0; q < 16; ++q) {
-                            const long long hv = (long long)Gq[a][q] * Gq[b][q];
-                            sx[q & 3] += hv;
-                            sy[q >> 2] += hv;
-                        }
+                            int G[RR];
+                            gram(q, G);
 #pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            atomicAdd(&Db[(p * 2 + 0) * L + (x1 + j - y1 + L) % L], (unsigned long long)sx[j]);
-                            atomicAdd(&Db[(p * 2 + 1) * L + (x2 + j - y2 + L) % L], (unsigned long long)sy[j]);
+                            for (int r = 0; r < RR; ++r) Gq[r][q] = G[r];
+                        }
+                        int p = 0;
+#pragma unroll
+                        for (int a = 0; a < RR; ++a)
+#pragma unroll
+                            for (int b = a + 1; b < RR; ++b, ++p) {
+                                long long sx[4] = {0, 0, 0, 0}, sy[4] = {0, 0, 0, 0};
+#pragma unroll
+                                for (int q = 0; q < 16; ++q) {
+                                    const long long hv = (long long)Gq[a][q] * Gq[b][q];
+                                    sx[q & 3] += hv;
+                                    sy[q >> 2] += hv;
+                                }
+#pragma unroll
+                                for (int j = 0; j < 4; ++j) {
+                                    atomicAdd(&Db[(p * 2 + 0) * L + (x1 + j - y1 + L) % L], (unsigned long long)sx[j]);
+                                    atomicAdd(&Db[(p * 2 + 1) * L + (x2 + j - y2 + L) % L], (unsigned long long)sy[j]);
+                                }
+                            }
+                    } else {
+                        const int y = ys;
+#pragma unroll
+                        for (int q = 0; q < 16; ++q) {
+                            const int x = site(X, 32 * u + 8 * (q >> 2) + 4 * h + (q & 3));
+                            if (x >= L2 || y >= L2) continue;
+                            int G[RR];
+                            gram(q, G);
+                            const int dx = (x % L - y % L + L) % L, dy = (x / L - y / L + L) % L;
+                            int p = 0;
+#pragma unroll
+                            for (int a = 0; a < RR; ++a)
+#pragma unroll
+                                for (int b = a + 1; b < RR; ++b, ++p) {
+                                    const unsigned long long hv = (unsigned long long)((long long)G[a] * G[b]);
+                                    atomicAdd(&Db[(p * 2 + 0) * L + dx], hv);
+                                    atomicAdd(&Db[(p * 2 + 1) * L + dy], hv);
+                                }
                         }
                     }
-            } else {
-                const int y = 64 * Y + col;
-#pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    const int x = 64 * X + 32 * wx + 8 * (q >> 2) + 4 * h + (q & 3);
-                    if (x >= L2 || y >= L2) continue;
-                    int G[RR];
-                    gram(q, G);
-                    const int dx = (x % L - y % L + L) % L, dy = (x / L - y / L + L) % L;
-                    int p = 0;
-#pragma unroll
-                    for (int a = 0; a < RR; ++a)
-#pragma unroll
-                        for (int b = a + 1; b < RR; ++b, ++p) {
-                            const unsigned long long hv = (unsigned long long)((long long)G[a] * G[b]);
-                            atomicAdd(&Db[(p * 2 + 0) * L + dx], hv);
-                            atomicAdd(&Db[(p * 2 + 1) * L + dy], hv);
-                        }
                 }
-            }
         }
         __syncthreads();
         // D[d] = F[d] + U[d] + U[-d]; sum Q^2 = sum_xy G^a_xy G^b_xy =
         // sum_d D_x[d] (one workgroup holds all of this configuration's
         // buckets)
         const int rl = 2 * L + 3;
-        for (int e = tid; e < PP * 2 * L; e += 256) {
+        for (int e = tid; e < PP * 2 * L; e += 64 * kGramWaves) {
             const int d = e % L;
             Fb[e] += Ub[e] + Ub[e - d + (L - d) % L];
         }
@@ -275,12 +321,12 @@ __global__ void __launch_bounds__(256) k_gram_mfma(ShapeDev sh, int cfg0, int nc
             for (int d = 0; d < L; ++d) q2 += Fb[(tid * 2 + 0) * L + d];
             sh.rec[((size_t)cfg * PP + tid) * rl + 2 * L + 1] = (int64_t)q2;
         }
-        for (int e = tid; e < PP * 2 * L; e += 256) {
+        for (int e = tid; e < PP * 2 * L; e += 64 * kGramWaves) {
             const int p = e / (2 * L), d = e % (2 * L);
             sh.rec[((size_t)cfg * PP + p) * rl + d] = (int64_t)Fb[e];
         }
         __syncthreads();
-        for (int e = tid; e < 2 * PP * 2 * L; e += 256) Fb[e] = 0;
+        for (int e = tid; e < 2 * PP * 2 * L; e += 64 * kGramWaves) Fb[e] = 0;
     }
 }
 
@@ -629,7 +675,8 @@ __global__ void k_buckets(ShapeDev sh) {
 
 size_t gram_lds(int RR, int L) {
     const int PP = RR * (RR - 1) / 2;
-    return (size_t)2 * RR * 64 * kRowPitch + (size_t)2 * RR * 64 * 4 + (size_t)2 * PP * 2 * L * 8;
+    const int nxp = 64 * ((L * L + 63) / 64);
+    return (size_t)2 * PP * 2 * L * 8 + (size_t)RR * nxp * 4;
 }
 // Pairs P0 .. PP - 1 of RR replicas in launches of at most NP pairs.
 template <int RR, int P0, int NP>
@@ -649,20 +696,25 @@ hipError_t launch_mfma(const ShapeDev& sh, int cfg0, int ncfg, hipStream_t st) {
     int dev = 0, ncu = 256;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    const int grid = std::min(ncfg, 4 * ncu);
-    static bool lds_set = false;  // 6 replicas at L = 32 take above 64 KiB
+    // a wave holds every replica's G of its tile: 64 x 64 up to 4 replicas,
+    // 64 x 32 above
+    constexpr int NV = RR <= 4 ? 2 : 1;
+    static bool lds_set = false;
     if (!lds_set) {
-        for (const void* f : {(const void*)k_gram_mfma<RR, true>, (const void*)k_gram_mfma<RR, false>}) {
+        for (const void* f : {(const void*)k_gram_mfma<RR, NV, true>, (const void*)k_gram_mfma<RR, NV, false>}) {
             const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                      (int)gram_lds(RR, 32));
             if (e != hipSuccess) return e;
         }
         lds_set = true;
     }
+    const int ggrid = std::min(ncfg, ncu);
     if (sh.L % 8 == 0)
-        hipLaunchKernelGGL((k_gram_mfma<RR, true>), dim3(grid), dim3(256), gram_lds(RR, sh.L), st, sh, cfg0, ncfg);
+        hipLaunchKernelGGL((k_gram_mfma<RR, NV, true>), dim3(ggrid), dim3(64 * kGramWaves), gram_lds(RR, sh.L), st,
+                           sh, cfg0, ncfg);
     else
-        hipLaunchKernelGGL((k_gram_mfma<RR, false>), dim3(grid), dim3(256), gram_lds(RR, sh.L), st, sh, cfg0, ncfg);
+        hipLaunchKernelGGL((k_gram_mfma<RR, NV, false>), dim3(ggrid), dim3(64 * kGramWaves), gram_lds(RR, sh.L),
+                           st, sh, cfg0, ncfg);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // overlap: one workgroup of kTeamWaves waves per CU; teams of wc waves,

@@ -44,6 +44,7 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 
 constexpr int kPitch = 80;  // bytes per 64-byte staged row in LDS (16-byte aligned)
 constexpr int kMaxL = 32;
+constexpr int kStage = 4 * 64 * kPitch;  // bytes of one staged chunk of the pair-product operands
 
 // Slot rho in [0, 64) of a tile <-> offsets (d1, d2) in [0, 8)^2 within the
 // 8 x 8 site block: rho = 32 (d2 >> 2) + 8 (d2 & 3) + 4 (d1 >> 2) + (d1 & 3).
@@ -51,28 +52,6 @@ constexpr int kMaxL = 32;
 // d2 = 4 wx + g.
 __device__ __forceinline__ int slot_d1(int rho) { return 4 * ((rho >> 2) & 1) + (rho & 3); }
 __device__ __forceinline__ int slot_d2(int rho) { return 4 * (rho >> 5) + ((rho >> 3) & 3); }
-
-__device__ __forceinline__ uint64_t low_bits(int n) {
-    return n >= 64 ? ~0ull : (n <= 0 ? 0ull : ((1ull << n) - 1ull));
-}
-
-// 64 bits -> 64 bytes in {0,1} (byte t = bit t), four 16-byte stores.
-__device__ __forceinline__ void unpack64(uint64_t v, uint8_t* dst) {
-    uint32_t out[16];
-#pragma unroll
-    for (int d = 0; d < 16; ++d) {
-        const uint32_t nib = (uint32_t)(v >> (4 * d)) & 0xFu;
-        out[d] = __umul24(nib, 0x00204081u) & 0x01010101u;
-    }
-    v4i* p = (v4i*)dst;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        v4i x;
-        x[0] = (int)out[4 * q]; x[1] = (int)out[4 * q + 1];
-        x[2] = (int)out[4 * q + 2]; x[3] = (int)out[4 * q + 3];
-        p[q] = x;
-    }
-}
 
 __device__ __forceinline__ v4i lds_v4(const uint8_t* base) { return *(const v4i*)base; }
 
@@ -83,120 +62,162 @@ __device__ __forceinline__ int mod_l(int v, int L) {
 
 // ---------------------------------------------------------------------------
 // G' of every replica into the workspace, digit planes [cl][r][plane][Np][Np].
+// One workgroup per configuration: it counts the down spins of every site
+// row into LDS, then its four waves share the tile pairs (X, Y), X <= Y,
+// each wave alone, one per SIMD, every replica's G of its 64 x 64 tile (64 x
+// 32 above 4 replicas) in the AGPRs, the {0,1} operands built in registers
+// from the bit rows along tau.  A block is written where it stands (one byte
+// per element) and, transposed, where its mirror stands (G is symmetric; four
+// consecutive row slots per 32-bit store).  In a diagonal pair with both
+// column blocks the block (1, 0) is not computed: the block (0, 1) writes it.
 // ---------------------------------------------------------------------------
-template <int RR>
-__global__ void __launch_bounds__(256) k_gram_store(ShapeDev sh, int cfg0, int ncfg, int nb,
-                                                    int8_t* __restrict__ ws) {
-    extern __shared__ __align__(16) uint8_t smem[];
-    uint8_t* Al = smem;                           // [RR][64][kPitch]
-    uint8_t* Bl = smem + RR * 64 * kPitch;        // [RR][64][kPitch]
-    int* nA = (int*)(Bl + RR * 64 * kPitch);      // [RR][64] popcounts
-    int* nB = nA + RR * 64;                       // [RR][64]
-    int* xyA = nB + RR * 64;                      // [64] site of each row slot, -1 = padding
-    int* xyB = xyA + 64;                          // [64]
-    const int L = sh.L, Lt = sh.Lt;
+constexpr int kStoreWaves = 4;
+
+template <int RR, int NV>
+__global__ void __launch_bounds__(64 * kStoreWaves) __attribute__((amdgpu_waves_per_eu(1, 1)))
+k_gram_store(ShapeDev sh, int cfg0, int ncfg, int nb, int8_t* __restrict__ ws) {
+    extern __shared__ int nS[];  // [RR][nxp] popcounts along tau
+    const int L = sh.L, Lt = sh.Lt, nc = sh.nc, nxp = sh.nxp;
     const int nt = nb * nb, Np = 64 * nt;
     const size_t plane = (size_t)Np * Np;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int wx = wv & 1, wy = wv >> 1;
+    const int i = lane & 31, h5 = lane >> 5, sh4 = 4 * h5;
     const int ntp = nt * (nt + 1) / 2;
-    const long long items = (long long)ncfg * ntp;
-    for (long long item = blockIdx.x; item < items; item += gridDim.x) {
-        const int cl = (int)(item / ntp);
-        int X = 0, rem = (int)(item % ntp);
-        while (rem >= nt - X) { rem -= nt - X; ++X; }
-        const int Y = X + rem;
-        const bool diag = X == Y;
-        __syncthreads();  // the previous item's epilogue has read nA, nB, xyA, xyB
-        if (tid < 128) {
-            const int side = tid >> 6, rho = tid & 63, T = side ? Y : X;
-            const int x1 = 8 * (T % nb) + slot_d1(rho), x2 = 8 * (T / nb) + slot_d2(rho);
-            (side ? xyB : xyA)[rho] = (x1 < L && x2 < L) ? x1 + L * x2 : -1;
+    // site of slot rho of tile T, -1 on padding
+    auto site = [&](int T, int rho) {
+        const int x1 = 8 * (T % nb) + slot_d1(rho), x2 = 8 * (T / nb) + slot_d2(rho);
+        return (x1 < L && x2 < L) ? x1 + L * x2 : -1;
+    };
+    for (int cl = blockIdx.x; cl < ncfg; cl += gridDim.x) {
+        const uint64_t* const pt = sh.Pt + (size_t)(cfg0 + cl) * RR * nc * nxp;
+        __syncthreads();  // the previous configuration's epilogues have read nS
+        for (int e = tid; e < RR * nxp; e += 64 * kStoreWaves) {
+            const int r = e / nxp, xy = e - r * nxp;
+            int n = 0;
+            for (int c = 0; c < nc; ++c) n += __popcll(pt[((size_t)r * nc + c) * nxp + xy]);
+            nS[e] = n;
         }
-        for (int e = tid; e < 2 * RR * 64; e += 256) nA[e] = 0;  // nA and nB
-        const uint8_t* Bsrc = diag ? Al : Bl;
-        const int* nBs = diag ? nA : nB;
-        v16i acc[RR];
+        __syncthreads();
+        for (int unit = wv; unit < ntp * (2 / NV); unit += kStoreWaves) {
+            const int tp = NV == 2 ? unit : unit >> 1;
+            const int v0 = NV == 2 ? 0 : (unit & 1);
+            int X = 0, rem = tp;
+            while (rem >= nt - X) { rem -= nt - X; ++X; }
+            const int Y = X + rem;
+            const bool diag = X == Y;
+            const int xa[2] = {site(X, i), site(X, 32 + i)};
+            int xb[NV];
 #pragma unroll
-        for (int r = 0; r < RR; ++r)
+            for (int v = 0; v < NV; ++v) xb[v] = site(Y, 32 * (v0 + v) + i);
+            // padding rows read site 0 and are zeroed in the epilogue
+            const int sa[2] = {max(xa[0], 0), max(xa[1], 0)};
+            int sb[NV];
 #pragma unroll
-            for (int q = 0; q < 16; ++q) acc[r][q] = 0;
-        constexpr int kPer = (2 * RR * 64 + 255) / 256;  // bit rows per thread
-        const int nrows = (diag ? 1 : 2) * RR * 64;
-        uint64_t vn[kPer];
-        __syncthreads();  // xyA, xyB written
-        auto fetch = [&](int c) {
-            const uint64_t vm = low_bits(Lt - 64 * c);
+            for (int v = 0; v < NV; ++v) sb[v] = max(xb[v], 0);
+            v16i acc[RR][2][NV];
 #pragma unroll
-            for (int k = 0; k < kPer; ++k) {
-                const int e = tid + 256 * k;
-                vn[k] = 0;
-                if (e < nrows) {
-                    const int side = e / (RR * 64), rr = (e / 64) % RR, row = e & 63;
-                    const int xy = (side ? xyB : xyA)[row];
-                    const size_t m = (size_t)(cfg0 + cl) * RR + rr;
-                    if (xy >= 0) vn[k] = sh.Pt[(m * sh.nc + c) * sh.nxp + xy] & vm;
+            for (int r = 0; r < RR; ++r)
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+#pragma unroll
+                    for (int v = 0; v < NV; ++v)
+#pragma unroll
+                        for (int q = 0; q < 16; ++q) acc[r][u][v][q] = 0;
+            auto kloop = [&](auto diagC) {
+                constexpr bool kDiag = decltype(diagC)::value;
+                constexpr int NB = kDiag ? 0 : NV;
+                auto fetch = [&](int c, uint64_t (&wa)[2][RR], uint64_t (&wb)[NV][RR]) {
+#pragma unroll
+                    for (int r = 0; r < RR; ++r) {
+                        const size_t o = ((size_t)r * nc + c) * nxp;
+#pragma unroll
+                        for (int u = 0; u < 2; ++u) wa[u][r] = pt[o + sa[u]];
+#pragma unroll
+                        for (int v = 0; v < NB; ++v) wb[v][r] = pt[o + sb[v]];
+                    }
+                };
+                auto chunk = [&](const uint64_t (&wa)[2][RR], const uint64_t (&wb)[NV][RR]) {
+#pragma unroll
+                    for (int ks = 0; ks < 2; ++ks) {
+                        i32x4 A[2][RR], B[NV][RR];
+#pragma unroll
+                        for (int r = 0; r < RR; ++r) {
+#pragma unroll
+                            for (int u = 0; u < 2; ++u)
+                                A[u][r] = mfma_bits_operand<false>((uint32_t)(wa[u][r] >> (32 * ks)) >> sh4);
+#pragma unroll
+                            for (int v = 0; v < NB; ++v)
+                                B[v][r] = mfma_bits_operand<false>((uint32_t)(wb[v][r] >> (32 * ks)) >> sh4);
+                        }
+#pragma unroll
+                        for (int r = 0; r < RR; ++r)
+#pragma unroll
+                            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                                for (int v = 0; v < NV; ++v) {
+                                    if (kDiag && NV == 2 && u == 1 && v == 0) continue;
+                                    const i32x4 b = kDiag ? A[NV == 2 ? v : v0][r] : B[v][r];
+                                    acc[r][u][v] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[u][r], b, acc[r][u][v],
+                                                                                         0, 0, 0);
+                                }
+                    }
+                };
+                uint64_t w0a[2][RR], w0b[NV][RR], w1a[2][RR], w1b[NV][RR];
+                fetch(0, w0a, w0b);
+                for (int c = 0; c + 1 < nc; c += 2) {
+                    fetch(c + 1, w1a, w1b);
+                    chunk(w0a, w0b);
+                    fetch(min(c + 2, nc - 1), w0a, w0b);
+                    chunk(w1a, w1b);
                 }
-            }
-        };
-        fetch(0);
-        for (int c = 0; c < sh.nc; ++c) {
-            __syncthreads();
+                if (nc & 1) chunk(w0a, w0b);
+            };
+            if (diag)
+                kloop(std::true_type{});
+            else
+                kloop(std::false_type{});
+            // G = Ltau - 2 (n_row + n_col) + 4 (B B^T), G' = G / 2 as two
+            // digits G' = 64 h + l, zero on padding
 #pragma unroll
-            for (int k = 0; k < kPer; ++k) {
-                const int e = tid + 256 * k;
-                if (e < nrows) {
-                    const int side = e / (RR * 64), rr = (e / 64) % RR, row = e & 63;
-                    (side ? nB : nA)[rr * 64 + row] += __popcll(vn[k]);
-                    unpack64(vn[k], (side ? Bl : Al) + (rr * 64 + row) * kPitch);
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    const int V = v0 + v;
+                    if (diag && NV == 2 && u == 1 && V == 0) continue;
+                    const int col = 32 * V + i;
+                    const bool col_ok = xb[v] >= 0;
+#pragma unroll
+                    for (int r = 0; r < RR; ++r) {
+                        const size_t m = (size_t)cl * RR + r;
+                        int8_t* ph = ws + (2 * m) * plane;
+                        int8_t* pl = ph + plane;
+                        const int nb_ = Lt - 2 * nS[r * nxp + sb[v]];
+                        uint32_t hw[4] = {0u, 0u, 0u, 0u}, lw[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+                        for (int q = 0; q < 16; ++q) {
+                            const int row = 32 * u + 8 * (q >> 2) + 4 * h5 + (q & 3);
+                            const int xs = site(X, row);
+                            const int G = nb_ - 2 * nS[r * nxp + max(xs, 0)] + 4 * acc[r][u][v][q];
+                            const int gp = (col_ok && xs >= 0) ? (G >> 1) : 0;
+                            const int hd = (gp + 32) >> 6;
+                            const int ld = gp - 64 * hd;
+                            hw[q >> 2] |= ((uint32_t)hd & 0xFFu) << (8 * (q & 3));
+                            lw[q >> 2] |= ((uint32_t)ld & 0xFFu) << (8 * (q & 3));
+                            if (!diag || (NV == 2 && u != V)) {  // the block itself, one byte per element
+                                const size_t o = (size_t)(64 * X + row) * Np + 64 * Y + col;
+                                ph[o] = (int8_t)hd;
+                                pl[o] = (int8_t)ld;
+                            }
+                        }
+                        // the mirror: row 64 Y + col, four consecutive row slots
+#pragma unroll
+                        for (int g = 0; g < 4; ++g) {
+                            const size_t o = (size_t)(64 * Y + col) * Np + 64 * X + 32 * u + 8 * g + 4 * h5;
+                            *(uint32_t*)(ph + o) = hw[g];
+                            *(uint32_t*)(pl + o) = lw[g];
+                        }
+                    }
                 }
-            }
-            __syncthreads();
-            if (c + 1 < sh.nc) fetch(c + 1);
-#pragma unroll
-            for (int ks = 0; ks < 2; ++ks) {
-                const int ko = 32 * ks + 16 * (lane >> 5);
-#pragma unroll
-                for (int r = 0; r < RR; ++r) {
-                    const v4i a = lds_v4(Al + (r * 64 + 32 * wx + (lane & 31)) * kPitch + ko);
-                    const v4i b = lds_v4(Bsrc + (r * 64 + 32 * wy + (lane & 31)) * kPitch + ko);
-                    acc[r] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, acc[r], 0, 0, 0);
-                }
-            }
-        }
-        __syncthreads();  // popcounts complete
-        // element (row slot rho of tile X, column slot col of tile Y):
-        // G = Ltau - 2 (n_rho + n_col) + 4 (B B^T), zero on padding
-        const int col = 32 * wy + (lane & 31);
-        const bool col_ok = (diag ? xyA : xyB)[col] >= 0;
-#pragma unroll
-        for (int r = 0; r < RR; ++r) {
-            const size_t m = (size_t)cl * RR + r;
-            int8_t* ph = ws + (2 * m) * plane;
-            int8_t* pl = ph + plane;
-            uint32_t hw[4] = {0u, 0u, 0u, 0u}, lw[4] = {0u, 0u, 0u, 0u};
-#pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int row = 32 * wx + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
-                const int G = Lt - 2 * (nA[r * 64 + row] + nBs[r * 64 + col]) + 4 * acc[r][q];
-                const int gp = (col_ok && xyA[row] >= 0) ? (G >> 1) : 0;
-                const int h = (gp + 32) >> 6;
-                const int l = gp - 64 * h;
-                hw[q >> 2] |= ((uint32_t)h & 0xFFu) << (8 * (q & 3));
-                lw[q >> 2] |= ((uint32_t)l & 0xFFu) << (8 * (q & 3));
-                if (!diag) {  // the block (X, Y) itself, one byte per element
-                    const size_t o = (size_t)(64 * X + row) * Np + 64 * Y + col;
-                    ph[o] = (int8_t)h;
-                    pl[o] = (int8_t)l;
-                }
-            }
-            // the mirror block (Y, X): row 64 Y + col, four consecutive row slots
-#pragma unroll
-            for (int g = 0; g < 4; ++g) {
-                const size_t o = (size_t)(64 * Y + col) * Np + 64 * X + 32 * wx + 8 * g + 4 * (lane >> 5);
-                *(uint32_t*)(ph + o) = hw[g];
-                *(uint32_t*)(pl + o) = lw[g];
-            }
         }
     }
 }
@@ -296,35 +317,46 @@ struct PairStep {
                                 pf + G.plane + (size_t)(64 * G.Y + srow) * G.Np + spart,
                                 pg + (size_t)(64 * G.X + srow) * G.Np + spart,
                                 pg + G.plane + (size_t)(64 * G.X + srow) * G.Np + spart};
-        v4i vn[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) vn[k] = *(const v4i*)src[k];
         v16i hh, xx, ll;
 #pragma unroll
         for (int q = 0; q < 16; ++q) hh[q] = xx[q] = ll[q] = 0;
         const int lane = G.lane;
-        for (int kc = 0; kc < G.nt; ++kc) {
-            __syncthreads();  // the previous chunk's MFMAs have read stg
+        auto fetch = [&](int kc, v4i (&vn)[4]) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) *(v4i*)(G.stg + (k * 64 + srow) * kPitch + spart) = vn[k];
+            for (int k = 0; k < 4; ++k) vn[k] = *(const v4i*)(src[k] + 64 * kc);
+        };
+        // chunk kc through staging buffer kc & 1, the data of chunk kc + 2 in
+        // flight meanwhile: a buffer was last read two chunks earlier, before
+        // the barrier of the chunk in between; the barrier before the first
+        // chunk orders this product after the previous one's reads
+        auto stage = [&](int kc, v4i (&vn)[4]) {
+            uint8_t* const sb = G.stg + (kc & 1) * kStage;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) *(v4i*)(sb + (k * 64 + srow) * kPitch + spart) = vn[k];
             __syncthreads();
-            if (kc + 1 < G.nt) {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) vn[k] = *(const v4i*)(src[k] + 64 * (kc + 1));
-            }
+            fetch(min(kc + 2, G.nt - 1), vn);  // past the end: a reload, never used
 #pragma unroll
             for (int ks = 0; ks < 2; ++ks) {
                 const int ko = 32 * ks + 16 * G.h5;
-                const v4i ah = lds_v4(G.stg + (0 * 64 + 32 * G.wx + (lane & 31)) * kPitch + ko);
-                const v4i al = lds_v4(G.stg + (1 * 64 + 32 * G.wx + (lane & 31)) * kPitch + ko);
-                const v4i bh = lds_v4(G.stg + (2 * 64 + 32 * G.wy + (lane & 31)) * kPitch + ko);
-                const v4i bl = lds_v4(G.stg + (3 * 64 + 32 * G.wy + (lane & 31)) * kPitch + ko);
+                const v4i ah = lds_v4(sb + (0 * 64 + 32 * G.wx + (lane & 31)) * kPitch + ko);
+                const v4i al = lds_v4(sb + (1 * 64 + 32 * G.wx + (lane & 31)) * kPitch + ko);
+                const v4i bh = lds_v4(sb + (2 * 64 + 32 * G.wy + (lane & 31)) * kPitch + ko);
+                const v4i bl = lds_v4(sb + (3 * 64 + 32 * G.wy + (lane & 31)) * kPitch + ko);
                 hh = __builtin_amdgcn_mfma_i32_32x32x32_i8(ah, bh, hh, 0, 0, 0);
                 ll = __builtin_amdgcn_mfma_i32_32x32x32_i8(al, bl, ll, 0, 0, 0);
                 xx = __builtin_amdgcn_mfma_i32_32x32x32_i8(ah, bl, xx, 0, 0, 0);
                 xx = __builtin_amdgcn_mfma_i32_32x32x32_i8(al, bh, xx, 0, 0, 0);
             }
+        };
+        v4i v0[4], v1[4];
+        fetch(0, v0);
+        fetch(min(1, G.nt - 1), v1);
+        __syncthreads();
+        for (int kc = 0; kc + 1 < G.nt; kc += 2) {
+            stage(kc, v0);
+            stage(kc + 1, v1);
         }
+        if (G.nt & 1) stage(G.nt - 1, v0);
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int Pv = 4096 * hh[q] + 64 * xx[q] + ll[q];
@@ -346,7 +378,7 @@ __global__ void __launch_bounds__(256) k_triple_mfma(int L, int ncfg, int nb,
                                                      const int8_t* __restrict__ ws,
                                                      int64_t* __restrict__ rec) {
     constexpr int NT = RR * (RR - 1) * (RR - 2) / 6;
-    __shared__ __align__(16) uint8_t stg[4 * 64 * kPitch];  // f high, f low, g high, g low
+    __shared__ __align__(16) uint8_t stg[2 * kStage];  // twice: f high, f low, g high, g low
     __shared__ unsigned long long Tb[NTG * 2 * kMaxL];
     const int nt = nb * nb, Np = 64 * nt;
     const size_t plane = (size_t)Np * Np;
@@ -423,8 +455,6 @@ hipError_t launch_triple_groups(int L, int ncfg, int nb, const int8_t* gw, int64
     return hipSuccess;
 }
 
-size_t store_lds(int RR) { return (size_t)2 * RR * 64 * kPitch + (size_t)2 * RR * 64 * 4 + 2 * 64 * 4; }
-
 // The records are sums of atomic adds: cleared first by a kernel (no memset
 // node, so the launch sequence may be captured in a graph).
 __global__ void k_zero_records(int64_t* __restrict__ rec, size_t n) {
@@ -443,10 +473,10 @@ hipError_t launch_triples_rr(const ShapeDev& sh, int cfg0, int ncfg, const Tripl
     hipLaunchKernelGGL(k_zero_records, dim3((unsigned)std::min<size_t>((nrec + 255) / 256, 1024)), dim3(256), 0,
                        st, rec, nrec);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const int ntp = lay.nt * (lay.nt + 1) / 2;
-    const long long items = (long long)ncfg * ntp;
-    const int g1 = (int)std::min<long long>(items, 16LL * ncu);
-    hipLaunchKernelGGL(k_gram_store<RR>, dim3(g1), dim3(256), store_lds(RR), st, sh, cfg0, ncfg, lay.nb, gw);
+    constexpr int NV = RR <= 4 ? 2 : 1;
+    const size_t lds = (size_t)RR * sh.nxp * 4;
+    hipLaunchKernelGGL((k_gram_store<RR, NV>), dim3(std::min(ncfg, ncu)), dim3(64 * kStoreWaves), lds, st, sh, cfg0,
+                       ncfg, lay.nb, gw);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const long long ipc = (long long)lay.nt * lay.nt;
     const long long per_grp = std::max<long long>(1, (long long)((ncfg + 7) / 8) * ipc);

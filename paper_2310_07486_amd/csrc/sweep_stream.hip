@@ -406,15 +406,22 @@ __device__ __forceinline__ void sweep_teams(const ShapeDev& sh, const int cfg0, 
     if (active) X[hx] = p ? w3 : w5;  // X(0)
     __syncthreads();
 
-    // one segment; IS = sigma & 3 is a compile-time constant.  Waves outside
-    // every team (member is wave-uniform) only take part in the barrier.
+    // Waves outside every team (member is wave-uniform) take part in the
+    // same barriers and nothing else, decided once here: a test inside the
+    // segment would leave the store count unknown along the loop and force
+    // waits for every outstanding load.  Stores and LDS writes of a team
+    // without a configuration need no guard of their own: its buffer
+    // descriptor covers 0 bytes, and its LDS region is its own.
+    if (kPacked && !member) {
+        for (int k = 0; k < 4 * nq + 2 + (kE ? 1 : 0); ++k) __syncthreads();
+        return;
+    }
+    const bool lane_ok = ttid < L2;  // a column of the lattice (per lane)
+
+    // one segment; IS = sigma & 3 is a compile-time constant
     auto segment = [&](const int sigma, const auto ISc, const auto bulkC, const bool do_c0, const bool do_c1) {
         constexpr int IS = decltype(ISc)::value;
         constexpr bool kBulk = decltype(bulkC)::value;
-        if (!member) {
-            __syncthreads();
-            return;
-        }
         if constexpr (kBulk) {
             // no plane wraps before the last group: each lane loads its own
             // parity's planes, A + 6 and A + 7, a segment ahead of their use
@@ -451,16 +458,16 @@ __device__ __forceinline__ void sweep_teams(const ShapeDev& sh, const int cfg0, 
             const uint64_t* Yb = Y + ((IS + 1) & 1) * H;
             const Nb n{Yb[hxp], Yb[hxm], Yb[hyp], Yb[hym]};
             w1 = site<kE>(w1, n, jxp, jxm, jyp, jym, w2, w0, R1, tb, f0, f1, f2);
-            if (kE && active) add3v(sm, f0, f1, f2);  // padding threads count nothing
+            if (kE && lane_ok) add3v(sm, f0, f1, f2);  // padding threads count nothing
         }
         // every store instruction writes whole planes 2 sigma - 3 and 2 sigma - 2:
         // parity 0 holds colour 1 (just updated) and colour 0 (one segment
         // old) there, parity 1 colour 0 (two segments old) and colour 1
         const int P1 = 2 * sigma - 3, P2 = 2 * sigma - 2;
         const uint64_t a1 = kBulk ? 0ull : across(P1), a2 = kBulk ? 0ull : across(P2);
-        if (active && P1 >= 0) buf_store((p ? w0 : w1) ^ a1, spins, voff, wrap(P1) * plane);
-        if (active && P2 >= 0) buf_store((p ? w1 : w2) ^ a2, spins, voff, wrap(P2) * plane);
-        if (active) {
+        if (lane_ok && P1 >= 0) buf_store((p ? w0 : w1) ^ a1, spins, voff, wrap(P1) * plane);
+        if (lane_ok && P2 >= 0) buf_store((p ? w1 : w2) ^ a2, spins, voff, wrap(P2) * plane);
+        if (lane_ok) {
             Y[(IS & 1) * H + hx] = p ? w2 : w4;
             X[((IS + 1) & 1) * H + hx] = p ? w5 : pf1;
         }
@@ -480,7 +487,7 @@ __device__ __forceinline__ void sweep_teams(const ShapeDev& sh, const int cfg0, 
         segment(s0 + 1, I1{}, B1{}, true, gq > 0);
         segment(s0 + 2, I2{}, B1{}, true, true);
         segment(s0 + 3, I3{}, B1{}, true, true);
-        if (kE && member) {
+        if (kE) {
             add_deep(deep, sm);
             if ((gq % kFlushMacros) == kFlushMacros - 1) flush_deep(deep, Ublk, true);
         }
@@ -492,14 +499,12 @@ __device__ __forceinline__ void sweep_teams(const ShapeDev& sh, const int cfg0, 
     segment(sl + 1, I1{}, B0{}, true, nq > 1);
     segment(sl + 2, I2{}, B0{}, true, true);
     segment(sl + 3, I3{}, B0{}, true, true);
-    if (kE && member) add_deep(deep, sm);  // the 5-bit counters hold at most four sites
+    if (kE) add_deep(deep, sm);  // the 5-bit counters hold at most four sites
     segment(half, I0{}, B0{}, false, true);      // colour 1, step half-1
     segment(half + 1, I1{}, B0{}, false, true);  // colour 1, step half == step 0 (tau wrap)
     if (kE) {
-        if (member) {
-            add_deep(deep, sm);
-            flush_deep(deep, Ublk, true);
-        }
+        add_deep(deep, sm);
+        flush_deep(deep, Ublk, true);
         __syncthreads();
         if (live && ttid < 64) sh.U[((size_t)r * W * 64 + (size_t)j * 64 + ttid) * nk + w] = Ublk[ttid];
     }

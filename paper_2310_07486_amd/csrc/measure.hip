@@ -47,13 +47,12 @@ constexpr int kMaxR = 6;       // replicas handled by the MFMA kernels
 constexpr int kMaxP = kMaxR * (kMaxR - 1) / 2;
 
 constexpr int kTP = 65;  // padded row pitch (words) of the transpose tiles
-constexpr size_t kTransposeLds = (size_t)2 * 64 * kTP * 8 + 64 * 4;
+constexpr size_t kTransposeLds = (size_t)64 * kTP * 8 + 64 * 4;
 
 __global__ void __launch_bounds__(256) k_transpose(ShapeDev sh, long long items) {
     extern __shared__ uint64_t tlds[];
     uint64_t(*tile)[kTP] = (uint64_t(*)[kTP])tlds;
-    uint64_t(*outw)[kTP] = (uint64_t(*)[kTP])(tlds + 64 * kTP);
-    int* mrow = (int*)(tlds + 2 * 64 * kTP);
+    int* mrow = (int*)(tlds + 64 * kTP);
     const int L2 = sh.L2, Lt = sh.Lt, nk = sh.nk, W = sh.W, R = sh.R;
     const int S = 64 * W;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -69,31 +68,55 @@ __global__ void __launch_bounds__(256) k_transpose(ShapeDev sh, long long items)
             const int i = sh.kidx[((size_t)r * S + s) * nk + w];
             mrow[tid] = (i * S + s) * R + r;
         }
-        for (int e = tid; e < 4096; e += 256) {
+        // the 64 x 64 words of the tile: all 16 loads of a thread in flight
+        // at once (the loops are unrolled so that they can be)
+        uint64_t v[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int e = tid + 256 * k;
             const int t = e >> 6, u = e & 63, tau = 64 * c + t, xy = 64 * g + u;
-            tile[t][u] = (tau < Lt && xy < L2) ? sh.S[((size_t)cfg * Lt + tau) * L2 + xy] : 0ull;
+            v[k] = (tau < Lt && xy < L2) ? sh.S[((size_t)cfg * Lt + tau) * L2 + xy] : 0ull;
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int e = tid + 256 * k;
+            tile[e >> 6][e & 63] = v[k];
         }
         __syncthreads();
-        // bits along tau: column u of the tile, lanes = tau
-        for (int uu = 0; uu < 16; ++uu) {
-            const int u = wv * 16 + uu;
-            outw[lane][u] = wave_transpose64(tile[lane][u]);  // lane = sample bit b
+        // both transposes from the tile into registers, the sixteen of each
+        // wave independent chains of lane exchanges; then the tile's LDS
+        // serves as the staging buffer of each output in turn (one 33 KB
+        // buffer per workgroup)
+        uint64_t vt[16], vx[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            vt[k] = tile[lane][wv * 16 + k];  // column u: lanes = tau
+            vx[k] = tile[wv * 16 + k][lane];  // row t: lanes = xy
         }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            vt[k] = wave_transpose64(vt[k]);  // lane = sample bit b, bits along tau
+            vx[k] = wave_transpose64(vx[k]);  // lane = sample bit b, bits along xy
+        }
+        __syncthreads();  // every wave has read the tile
+#pragma unroll
+        for (int k = 0; k < 16; ++k) tile[lane][wv * 16 + k] = vt[k];
         __syncthreads();
-        for (int e = tid; e < 4096; e += 256) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int e = tid + 256 * k;
             const int b = e >> 6, u = e & 63;
-            sh.Pt[((size_t)mrow[b] * sh.nc + c) * sh.nxp + 64 * g + u] = outw[b][u];
+            sh.Pt[((size_t)mrow[b] * sh.nc + c) * sh.nxp + 64 * g + u] = tile[b][u];
         }
         __syncthreads();
-        // bits along xy: row t of the tile, lanes = xy
-        for (int tt = 0; tt < 16; ++tt) {
-            const int t = wv * 16 + tt;
-            outw[lane][t] = wave_transpose64(tile[t][lane]);
-        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) tile[lane][wv * 16 + k] = vx[k];
         __syncthreads();
-        for (int e = tid; e < 4096; e += 256) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int e = tid + 256 * k;
             const int b = e >> 6, t = e & 63, tau = 64 * c + t;
-            if (tau < Lt) sh.Px[((size_t)mrow[b] * sh.nx + g) * Lt + tau] = outw[b][t];
+            if (tau < Lt) sh.Px[((size_t)mrow[b] * sh.nx + g) * Lt + tau] = tile[b][t];
         }
     }
 }

@@ -120,3 +120,31 @@ def test_records_refuse_seven_replicas():
         plan.measure(0, tfim.TFIM_MEASURE_RECORDS)
     assert ei.value.status == tfim.TFIM_EUNSUPPORTED
     plan.close()
+
+
+@pytest.mark.parametrize("L,Lt,R,W,nk", [(8, 2048, 4, 1, 4), (16, 256, 4, 2, 3), (12, 72, 6, 1, 3),
+                                         (24, 2048, 4, 1, 2)])
+def test_records_of_any_range_equal_the_whole(L, Lt, R, W, nk):
+    """Records of sub-ranges of every size (one configuration, a few, the
+    XCD-sized and larger batches, odd offsets) equal those of one call over
+    all configurations: the overlap kernel's wave teams are sized from the
+    range (a single configuration spans the whole chip, a few split it, many
+    take one XCD each), and every size must give the same integers."""
+    sh = Shape(L, Lt, W, R, ladder(0.22, 0.36, nk), pt_every=1)
+    seed = 5150 + L + Lt
+    _say(f"measure ranges L={L} Lt={Lt} R={R} W={W} nk={nk}")
+    plan = tfim.Plan([sh], seed)
+    plan.init()
+    plan.sweep(3)
+    whole = plan.measure_range(0, 0, 0, nk * 64 * W)  # [cfg][pair][2L+3]
+    ncfg = whole.shape[0]
+    cuts = [0, 1, 3, 4, 9, 16, 17, 30, 61, 100, 163, ncfg]
+    cuts = sorted({c for c in cuts if c <= ncfg})
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        part = plan.measure_range(0, 0, a, b - a, flags=tfim.TFIM_MEASURE_REUSE_LAYOUT)
+        assert np.array_equal(part, whole[a:b]), (a, b)
+    # and the first configurations against the oracle
+    want = _oracle_records(sh, seed, [0, 1, 63], 3, k_indices=[0])  # [1][3][P][2L+3]
+    for si, s in enumerate([0, 1, 63]):
+        assert np.array_equal(whole[s], want[0, si]), s
+    plan.close()

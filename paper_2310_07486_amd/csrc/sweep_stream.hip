@@ -412,11 +412,27 @@ __device__ __forceinline__ void sweep_teams(const ShapeDev& sh, const int cfg0, 
     // waits for every outstanding load.  Stores and LDS writes of a team
     // without a configuration need no guard of their own: its buffer
     // descriptor covers 0 bytes, and its LDS region is its own.
+    // A team of one wave (64 columns or fewer) needs no barrier between
+    // segments: the LDS operations of one wave take effect in program order,
+    // so its teams run free of each other.  Uniform over the workgroup: all
+    // teams of an item are alike.
+    const bool solo = kPacked && cols == 64;
     if (kPacked && !member) {
-        for (int k = 0; k < 4 * nq + 2 + (kE ? 1 : 0); ++k) __syncthreads();
+        if (!solo)
+            for (int k = 0; k < 4 * nq + 2; ++k) __syncthreads();
+        if (kE) __syncthreads();
         return;
     }
     const bool lane_ok = ttid < L2;  // a column of the lattice (per lane)
+    auto seg_sync = [&]() {
+        if (solo) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        } else {
+            __syncthreads();
+        }
+    };
 
     // one segment; IS = sigma & 3 is a compile-time constant
     auto segment = [&](const int sigma, const auto ISc, const auto bulkC, const bool do_c0, const bool do_c1) {
@@ -471,7 +487,7 @@ __device__ __forceinline__ void sweep_teams(const ShapeDev& sh, const int cfg0, 
             Y[(IS & 1) * H + hx] = p ? w2 : w4;
             X[((IS + 1) & 1) * H + hx] = p ? w5 : pf1;
         }
-        __syncthreads();
+        seg_sync();
         w0 = w2; w1 = w3; w2 = w4; w3 = w5; w4 = pf0; w5 = pf1; pf0 = nx0; pf1 = nx1;
     };
     using I0 = std::integral_constant<int, 0>;

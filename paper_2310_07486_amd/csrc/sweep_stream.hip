@@ -700,6 +700,10 @@ __device__ __forceinline__ void helped_body(const ShapeDev& sh, const int cfg, u
                 __syncthreads();
                 return;
             } else {
+                // the previous segment's colour-1 count goes into the counters
+                // here, right after the barrier, where it fills the wait for
+                // this segment's LDS reads (zero before the first colour-1 site)
+                if (kE) add3v(sm, f0, f1, f2);
                 if constexpr (kBulk) {
                     // no plane wraps before the last group: each lane loads its
                     // own parity's planes, A + 6 and A + 7, a segment ahead
@@ -746,7 +750,6 @@ __device__ __forceinline__ void helped_body(const ShapeDev& sh, const int cfg, u
                         w1 = site_m<kE>(w1, n, jxp, jxm, jyp, jym, w2, w0, tb.M[0][*hm(IS & 1, 3)],
                                         tb.M[1][*hm(IS & 1, 4)], tb.M[2][*hm(IS & 1, 5)], f0, f1, f2);
                     }
-                    if (kE) add3v(sm, f0, f1, f2);
                 }
                 const int P1 = 2 * sigma - 3, P2 = 2 * sigma - 2;
                 const uint64_t a1 = kBulk ? 0ull : across(P1), a2 = kBulk ? 0ull : across(P2);
@@ -798,6 +801,7 @@ __device__ __forceinline__ void helped_body(const ShapeDev& sh, const int cfg, u
             segment(half, I0{}, roleC, B0{}, false, true);
             segment(half + 1, I1{}, roleC, B0{}, false, true);
             if (kE) {
+                add3v(sm, f0, f1, f2);  // the last colour-1 site
                 add_deep(deep, sm);
                 flush_deep(deep, Ublk, true);
             }

@@ -189,7 +189,9 @@ tfim_status tfim_measure(tfim_plan *plan, uint32_t shape, uint32_t what, void *h
  * TFIM_MEASURE_REUSE_LAYOUT skips the bit transposition (valid only if the
  * state did not change since the last measurement of this shape).
  * out == NULL: enqueue only (asynchronous, for timing); otherwise the call
- * synchronises and copies the records. */
+ * synchronises and copies the records.  ncfg = 0 measures nothing (the bit
+ * layout is still refreshed unless TFIM_MEASURE_REUSE_LAYOUT); a range
+ * past the last configuration is TFIM_EINVAL. */
 #define TFIM_MEASURE_REUSE_LAYOUT 1u
 tfim_status tfim_measure_range(tfim_plan *plan, uint32_t shape, uint32_t mode, uint32_t cfg0,
                                uint32_t ncfg, uint32_t flags, int64_t *out, size_t out_bytes);
@@ -228,7 +230,8 @@ tfim_status tfim_xi2(const int64_t *A, uint32_t L, uint32_t n_k, double *xi_out)
  *   device memory (256-byte aligned, at least the workspace size), used as
  *   scratch and holding the records at its start afterwards.  flags as for
  *   tfim_measure_range.  out == NULL: enqueue only (asynchronous); otherwise
- *   the call synchronises and copies the records to out. */
+ *   the call synchronises and copies the records to out.  ncfg = 0 launches
+ *   nothing and returns TFIM_OK (the range is still checked). */
 tfim_status tfim_triples_workspace(const tfim_plan *plan, uint32_t shape, uint32_t ncfg,
                                    size_t *bytes_out);
 tfim_status tfim_measure_triples(tfim_plan *plan, uint32_t shape, uint32_t cfg0, uint32_t ncfg,
@@ -248,7 +251,8 @@ tfim_status tfim_measure_triples(tfim_plan *plan, uint32_t shape, uint32_t cfg0,
  * flags as for tfim_measure_range.  Enqueues on the plan's stream and
  * returns (asynchronous); allocates nothing and records no memset.  Every
  * call on one GPU shares that GPU's array and leaves it holding its planes:
- * calls that overlap on one GPU (several streams or host threads) race. */
+ * calls that overlap on one GPU (several streams or host threads) race.
+ * ncfg = 0 launches nothing and returns TFIM_OK. */
 tfim_status tfim_measure_triples_noalloc(tfim_plan *plan, uint32_t shape, uint32_t cfg0,
                                          uint32_t ncfg, uint32_t flags, int64_t *rec_dev,
                                          size_t rec_bytes);
@@ -266,7 +270,8 @@ tfim_status tfim_measure_triples_noalloc(tfim_plan *plan, uint32_t shape, uint32
  * TFIM_EUNSUPPORTED).  ws: caller-owned device memory, 256-byte aligned, at
  * least ncfg*2*Ltau*8 bytes, holding the records afterwards.  flags as for
  * tfim_measure_range.  out == NULL: enqueue only (asynchronous); otherwise
- * the call synchronises and copies the records to out. */
+ * the call synchronises and copies the records to out.  ncfg = 0 launches
+ * nothing and returns TFIM_OK (the range is still checked). */
 tfim_status tfim_measure_time(tfim_plan *plan, uint32_t shape, uint32_t cfg0, uint32_t ncfg,
                               uint32_t flags, void *workspace, size_t workspace_bytes,
                               int64_t *out, size_t out_bytes);

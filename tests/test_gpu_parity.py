@@ -261,3 +261,21 @@ def test_paper_schedule_six_replicas_tempering_every_30_sweeps(variant):
     plan.sync()
     _compare(plan, 0, sh, seed, list(range(64)), 65)
     assert plan.counters() == (65, 2)
+
+
+@pytest.mark.parametrize("L,variant", [(24, 0), (24, 1), (24, 2), (24, 3), (8, 0), (8, 2)])
+def test_longest_tau(L, variant):
+    """The longest tau extent a shape may have (Ltau = 65536): the Philox
+    group counters, the plane offsets and the energy counters (U up to 3N =
+    1.1e8 at L = 24) at their largest."""
+    sh = Shape(L, 65536, 1, 1, ladder(0.25, 0.33, 2), pt_every=1)
+    seed = 65536 + 10 * L + variant
+    _say(f"longest tau L={L} Lt=65536 variant={variant}")
+    plan = tfim.Plan([sh], seed)
+    plan.set_variant(variant)
+    plan.init()
+    plan.sweep(2)
+    plan.sync()
+    _compare(plan, 0, sh, seed, [0, 63], 2)
+    assert plan.counters() == (2, 2)
+    plan.close()

@@ -279,3 +279,21 @@ def test_longest_tau(L, variant):
     _compare(plan, 0, sh, seed, [0, 63], 2)
     assert plan.counters() == (2, 2)
     plan.close()
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_identifier_extremes(variant):
+    """The largest identifiers a shape may carry in the random-number
+    counters: 64 replicas, the last word below 2^20, stream 255 and a seed
+    with its top bit set, with tempering every sweep."""
+    sh = Shape(8, 16, 1, 64, ladder(0.22, 0.34, 3), pt_every=1, stream_id=255,
+               word_offset=(1 << 20) - 1)
+    seed = (1 << 63) + 977 + variant
+    _say(f"identifier extremes R=64 word=2^20-1 stream=255 variant={variant}")
+    plan = tfim.Plan([sh], seed)
+    plan.set_variant(variant)
+    plan.init()
+    plan.sweep(4)
+    plan.sync()
+    _compare(plan, 0, sh, seed, [0, 29, 63], 4)
+    assert plan.counters() == (4, 4)

@@ -27,8 +27,9 @@
 //    triple {e, f, g}.  A work item is one output tile of one configuration
 //    with every replica pair unrolled, so these sums stay in registers
 //    across the pairs and reach the LDS buckets once per tile.  With 5 or 6
-//    replicas (10 or 20 triples) one launch per group of 2 triples forms the
-//    pair products that group needs.  Records are
+//    replicas (10 or 20 triples) one launch per replica pair forms that
+//    pair's product once and serves the 3 or 4 triples that contain it, one
+//    carrier each.  Records are
 //    scaled by 8 at the flush (G = 2 G').  Work items are handed out so that
 //    the workgroups with the same blockIdx.x mod 8 (one XCD under round-robin
 //    dispatch) share one configuration at a time.
@@ -266,7 +267,34 @@ constexpr bool pair_needed(int R, int P, int T0, int NTG) {
     return false;
 }
 
-// Accumulators of the triples T0 .. T0 + NTG - 1 over one output tile.
+// Accumulator slot of carrier C of pair P in one launch.  The triple-group
+// form (PM < 0) keeps the triples T0 .. T0 + NTG - 1 and forms every pair
+// product they need; the pair-major form (PM >= 0) forms only the product of
+// pair PM, once, with one slot per carrier (the triples that contain the
+// pair).  -1: not in this launch.
+constexpr int acc_slot(int R, int T0, int NTG, int PM, int P, int C) {
+    if (PM >= 0) return P == PM ? C : -1;
+    const int f = pair_f(R, P), g = pair_g(R, P);
+    const int t = triple_of(R, carrier_of(R, f, g, C), f, g);
+    return t >= T0 && t < T0 + NTG ? t - T0 : -1;
+}
+// The record triple of every slot of a launch.
+template <int RR, int T0, int NTG, int PM>
+struct SlotTriples {
+    int t[NTG] = {};
+    constexpr SlotTriples() {
+        for (int s = 0; s < NTG; ++s) {
+            if (PM < 0) {
+                t[s] = T0 + s;
+            } else {
+                const int f = pair_f(RR, PM), g = pair_g(RR, PM);
+                t[s] = triple_of(RR, carrier_of(RR, f, g, s), f, g);
+            }
+        }
+    }
+};
+
+// Accumulators of the slots of one launch over one output tile.
 template <int RR, int NTG>
 struct TriAcc {
     long long tx[NTG][4], ty[NTG][4];  // x-buckets by j, y-buckets by g4
@@ -280,33 +308,33 @@ struct TriGeom {
     uint8_t* stg;
 };
 
-template <int RR, int T0, int NTG, int C, int P>
+template <int RR, int T0, int NTG, int PM, int C, int P>
 struct CarrierStep {
     static __device__ __forceinline__ void run(TriAcc<RR, NTG>& a, int q, int Pv) {
         constexpr int f = pair_f(RR, P), g = pair_g(RR, P);
         constexpr int e = carrier_of(RR, f, g, C);
-        constexpr int t = triple_of(RR, e, f, g);
-        if constexpr (t >= T0 && t < T0 + NTG) {
+        constexpr int sl = acc_slot(RR, T0, NTG, PM, P, C);
+        if constexpr (sl >= 0) {
             const int j = q & 3, g4 = q >> 2;
             const int hb = (int)(int8_t)(a.cw[e][0][g4] >> (8 * j));
             const int lb = (int)(int8_t)(a.cw[e][1][g4] >> (8 * j));
             const long long v = (long long)(64 * hb + lb) * (long long)Pv;
-            a.tx[t - T0][j] += v;
-            a.ty[t - T0][g4] += v;
+            a.tx[sl][j] += v;
+            a.ty[sl][g4] += v;
         }
-        CarrierStep<RR, T0, NTG, C + 1, P>::run(a, q, Pv);
+        CarrierStep<RR, T0, NTG, PM, C + 1, P>::run(a, q, Pv);
     }
 };
-template <int RR, int T0, int NTG, int P>
-struct CarrierStep<RR, T0, NTG, RR - 2, P> {
+template <int RR, int T0, int NTG, int PM, int P>
+struct CarrierStep<RR, T0, NTG, PM, RR - 2, P> {
     static __device__ __forceinline__ void run(TriAcc<RR, NTG>&, int, int) {}
 };
 
-template <int RR, int T0, int NTG, int P>
+template <int RR, int T0, int NTG, int PM, int P>
 struct PairStep {
     static __device__ __forceinline__ void run(TriAcc<RR, NTG>& a, const TriGeom& G) {
-        if constexpr (pair_needed(RR, P, T0, NTG)) product(a, G);
-        PairStep<RR, T0, NTG, P + 1>::run(a, G);
+        if constexpr (PM >= 0 ? P == PM : pair_needed(RR, P, T0, NTG)) product(a, G);
+        PairStep<RR, T0, NTG, PM, P + 1>::run(a, G);
     }
     static __device__ __forceinline__ void product(TriAcc<RR, NTG>& a, const TriGeom& G) {
         constexpr int f = pair_f(RR, P), g = pair_g(RR, P);
@@ -360,24 +388,27 @@ struct PairStep {
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int Pv = 4096 * hh[q] + 64 * xx[q] + ll[q];
-            CarrierStep<RR, T0, NTG, 0, P>::run(a, q, Pv);
+            CarrierStep<RR, T0, NTG, PM, 0, P>::run(a, q, Pv);
         }
     }
 };
-template <int RR, int T0, int NTG>
-struct PairStep<RR, T0, NTG, RR * (RR - 1) / 2> {
+template <int RR, int T0, int NTG, int PM>
+struct PairStep<RR, T0, NTG, PM, RR * (RR - 1) / 2> {
     static __device__ __forceinline__ void run(TriAcc<RR, NTG>&, const TriGeom&) {}
 };
 
-// Records of the triples T0 .. T0 + NTG - 1 (lexicographic order a < b < c):
-// up to 4 replicas one launch takes every triple; with 5 or 6, one launch per
-// group of 2 keeps the int64 sums of a tile in registers, and each group
-// forms only the pair products its triples need.
-template <int RR, int T0, int NTG>
+// Records of the slots of one launch (triples in lexicographic order
+// a < b < c): up to 4 replicas one launch takes every triple and forms the 6
+// pair products; with 5 or 6, one launch per replica pair forms that pair's
+// product once and adds it, times each carrier's G, into the records of the
+// 3 or 4 triples that contain the pair (every pair product formed once, the
+// int64 sums of a tile in registers).
+template <int RR, int T0, int NTG, int PM>
 __global__ void __launch_bounds__(256) k_triple_mfma(int L, int ncfg, int nb,
                                                      const int8_t* __restrict__ ws,
                                                      int64_t* __restrict__ rec) {
     constexpr int NT = RR * (RR - 1) * (RR - 2) / 6;
+    constexpr SlotTriples<RR, T0, NTG, PM> stab{};
     __shared__ __align__(16) uint8_t stg[2 * kStage];  // twice: f high, f low, g high, g low
     __shared__ unsigned long long Tb[NTG * 2 * kMaxL];
     const int nt = nb * nb, Np = 64 * nt;
@@ -387,7 +418,16 @@ __global__ void __launch_bounds__(256) k_triple_mfma(int L, int ncfg, int nb,
     const int ipc = nt * nt;  // output tiles per configuration, all pairs each
     const int grp = blockIdx.x & 7, ngrp_blocks = (int)(gridDim.x >> 3), kk = (int)(blockIdx.x >> 3);
     const int ncg = grp < ncfg ? (ncfg - grp + 7) / 8 : 0;  // configurations grp, grp + 8, ...
-    const int rl = NT * 2 * L, nl = NTG * 2 * L, r0 = T0 * 2 * L;  // record, group slice
+    const int rl = NT * 2 * L, nl = NTG * 2 * L;  // record, the launch's slots
+    // element e of the slot buckets -> its place in a configuration's record
+    auto rec_at = [&](int e) {
+        const int sl = e / (2 * L);
+        int t = 0;
+#pragma unroll
+        for (int k = 0; k < NTG; ++k)
+            if (k == sl) t = stab.t[k];
+        return (size_t)t * 2 * L + (e - sl * 2 * L);
+    };
     for (int e = tid; e < nl; e += 256) Tb[e] = 0;
     int cur = -1;
     for (long long s = kk; s < (long long)ncg * ipc; s += ngrp_blocks) {
@@ -397,7 +437,7 @@ __global__ void __launch_bounds__(256) k_triple_mfma(int L, int ncfg, int nb,
             __syncthreads();
             if (cur >= 0)
                 for (int e = tid; e < nl; e += 256) {
-                    atomicAdd((unsigned long long*)&rec[(size_t)cur * rl + r0 + e], Tb[e] * 8ull);
+                    atomicAdd((unsigned long long*)&rec[(size_t)cur * rl + rec_at(e)], Tb[e] * 8ull);
                     Tb[e] = 0;
                 }
             __syncthreads();
@@ -421,7 +461,7 @@ __global__ void __launch_bounds__(256) k_triple_mfma(int L, int ncfg, int nb,
                                                          (size_t)(64 * X + col) * Np + 64 * Y + 32 * wx +
                                                          8 * g4 + 4 * h5);
         const TriGeom G{base, plane, Np, nt, X, Y, tid, lane, wx, wy, h5, stg};
-        PairStep<RR, T0, NTG, 0>::run(a, G);
+        PairStep<RR, T0, NTG, PM, 0>::run(a, G);
         const int x1 = 8 * (X % nb) + slot_d1(col), x2 = 8 * (X / nb) + slot_d2(col);
         const int y1b = 8 * (Y % nb) + 4 * h5, y2b = 8 * (Y / nb) + 4 * wx;
 #pragma unroll
@@ -437,21 +477,31 @@ __global__ void __launch_bounds__(256) k_triple_mfma(int L, int ncfg, int nb,
     __syncthreads();
     if (cur >= 0)
         for (int e = tid; e < nl; e += 256)
-            atomicAdd((unsigned long long*)&rec[(size_t)cur * rl + r0 + e], Tb[e] * 8ull);
+            atomicAdd((unsigned long long*)&rec[(size_t)cur * rl + rec_at(e)], Tb[e] * 8ull);
 }
 
-// Triples T0 .. NT - 1 in launches of at most 4 (2 with 5 or 6 replicas,
-// whose carrier digits take 16 more registers per replica).
+// Up to 4 replicas: the triples T0 .. NT - 1 in launches of at most 4.
 template <int RR, int T0>
 hipError_t launch_triple_groups(int L, int ncfg, int nb, const int8_t* gw, int64_t* rec, int grid,
                                 hipStream_t st) {
     constexpr int NT = RR * (RR - 1) * (RR - 2) / 6;
-    constexpr int kGroup = RR <= 4 ? 4 : 2;
-    constexpr int n = NT - T0 < kGroup ? NT - T0 : kGroup;
-    hipLaunchKernelGGL((k_triple_mfma<RR, T0, n>), dim3(grid), dim3(256), 0, st, L, ncfg, nb, gw, rec);
+    constexpr int n = NT - T0 < 4 ? NT - T0 : 4;
+    hipLaunchKernelGGL((k_triple_mfma<RR, T0, n, -1>), dim3(grid), dim3(256), 0, st, L, ncfg, nb, gw, rec);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if constexpr (T0 + n < NT) return launch_triple_groups<RR, T0 + n>(L, ncfg, nb, gw, rec, grid, st);
+    return hipSuccess;
+}
+
+// 5 or 6 replicas: one launch per replica pair P, P .. pairs - 1.
+template <int RR, int P>
+hipError_t launch_triple_pairs(int L, int ncfg, int nb, const int8_t* gw, int64_t* rec, int grid,
+                               hipStream_t st) {
+    constexpr int PP = RR * (RR - 1) / 2;
+    hipLaunchKernelGGL((k_triple_mfma<RR, 0, RR - 2, P>), dim3(grid), dim3(256), 0, st, L, ncfg, nb, gw, rec);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if constexpr (P + 1 < PP) return launch_triple_pairs<RR, P + 1>(L, ncfg, nb, gw, rec, grid, st);
     return hipSuccess;
 }
 
@@ -481,7 +531,8 @@ hipError_t launch_triples_rr(const ShapeDev& sh, int cfg0, int ncfg, const Tripl
     const long long ipc = (long long)lay.nt * lay.nt;
     const long long per_grp = std::max<long long>(1, (long long)((ncfg + 7) / 8) * ipc);
     const int g2 = 8 * (int)std::min<long long>(per_grp, (long long)(4 * ncu) / 8);
-    return launch_triple_groups<RR, 0>(sh.L, ncfg, lay.nb, (const int8_t*)gw, rec, g2, st);
+    if constexpr (RR >= 5) return launch_triple_pairs<RR, 0>(sh.L, ncfg, lay.nb, (const int8_t*)gw, rec, g2, st);
+    else return launch_triple_groups<RR, 0>(sh.L, ncfg, lay.nb, (const int8_t*)gw, rec, g2, st);
 }
 
 }  // namespace

@@ -277,9 +277,9 @@ __host__ __device__ inline int stream_cols(const ShapeDev& sh) { return ((sh.L2 
 
 // Sweep of g configurations cfg0 .. cfg0+g-1 of one shape by one block: a
 // team of `cols` threads (a multiple of 64) per configuration, all teams in
-// lockstep along tau (one barrier per segment).  Teams at or past `nlive`
-// and threads past the last team run the same barriers and touch no global
-// memory.  Segment sigma updates the colour-0 site at plane A = 2 sigma + p
+// lockstep along tau (one barrier per segment; teams of one wave need none
+// and run free).  Teams at or past `nlive` and threads past the last team
+// run the same barriers and touch no global memory.  Segment sigma updates the colour-0 site at plane A = 2 sigma + p
 // and the colour-1 site of the previous step at A - 3.
 // kPacked = false: one team filling the workgroup (g = nlive = 1,
 // cols = blockDim.x), so every wave is a live member.  kDeepLds: the energy

@@ -26,8 +26,8 @@
 //    G (upper triangle of tile pairs), all replicas at once, bucket sums in
 //    LDS, flushed once per configuration.
 // 3. k_overlap_mfma: every wave alone (no LDS, no barrier) on 64x64 tiles of
-//    up to 3 pairs at once (more: one launch per group of 3), operands
-//    unpacked in registers, the rank-one corrections folded into one more
+//    a group of 2 pairs at once that share a replica on one side (one launch
+//    per group, two waves per SIMD), operands unpacked in registers, the rank-one corrections folded into one more
 //    K step so the accumulator is Q; per-lane int64 sums flushed once per
 //    configuration by each of the wave teams that share it.
 // The plain per-sample form (k_*_plain) computes one matrix element per
@@ -354,13 +354,14 @@ k_gram_mfma(ShapeDev sh, int cfg0, int ncfg) {
 }
 
 // ---------------------------------------------------------------------------
-// Q tiles: trQ and sum Q^4 for the pairs P0 .. P0 + NP - 1 (pairs a < b in
-// lexicographic order; sum Q^2 comes from the Gram buckets).
+// Q tiles: trQ and sum Q^4 for the NP pairs of launch group GI (records of
+// pairs a < b in lexicographic order; sum Q^2 comes from the Gram buckets).
 //
 // Every wave works alone, with no LDS and no barrier: a 64 x 64 tile
 // (tau in 64T + [0, 64), tau' in 64T2 + [0, 64)) of each of its pairs as
-// 2 x 2 blocks of 32 x 32, the accumulators (64 registers per pair, three
-// pairs per launch) in the AGPRs, one wave per SIMD.  The operands come straight from each lane's
+// 2 x 2 blocks of 32 x 32, the accumulators 64 registers per pair, two pairs
+// per launch, two waves per SIMD (one wave's MFMAs run while the other
+// builds its operands).  The operands come straight from each lane's
 // packed row words: in K step ks of chunk g, lane (i, h) of a block feeds
 // row i with bits 8j + 4h + m (j, m < 4) of the 32-bit half ks of its word,
 // one byte each, in the same order on both sides.  Row-side bytes are 4 B
@@ -375,32 +376,77 @@ k_gram_mfma(ShapeDev sh, int cfg0, int ncfg) {
 // once per configuration.  Workgroup b runs on XCD b mod nxcd, so a team
 // no larger than an XCD's share of waves reads its rows from one L2.
 // ---------------------------------------------------------------------------
-template <int RR, int P0, int NP>
+// The launch groups of the replica pairs (pair p = (a, b), a < b, in
+// lexicographic order): two pairs (a, b), (a, c) with the same row-side
+// replica per group, the pairs left over two at a time, the last alone.  A
+// group then builds 3 operand sets for its 4 MFMA blocks per K step.
+template <int RR>
+struct PairGroups {
+    static constexpr int PP = RR * (RR - 1) / 2;
+    int pair[PP] = {};   // pair indices in launch order
+    int first[PP] = {};  // first position of group k in pair[]
+    int size[PP] = {};   // pairs of group k (1 or 2)
+    int n = 0;           // groups
+    constexpr PairGroups() {
+        int left[PP] = {}, nl = 0, at = 0, p = 0;
+        for (int a = 0; a < RR; ++a) {
+            const int p0 = p, cnt = RR - 1 - a;
+            p += cnt;
+            int k = 0;
+            for (; k + 1 < cnt; k += 2) {
+                first[n] = at; size[n++] = 2;
+                pair[at++] = p0 + k;
+                pair[at++] = p0 + k + 1;
+            }
+            if (k < cnt) left[nl++] = p0 + k;
+        }
+        for (int k = 0; k < nl; k += 2) {
+            first[n] = at; size[n++] = k + 1 < nl ? 2 : 1;
+            pair[at++] = left[k];
+            if (k + 1 < nl) pair[at++] = left[k + 1];
+        }
+    }
+};
+constexpr int pair_row(int R, int p) {
+    int a = 0;
+    while (p >= R - 1 - a) { p -= R - 1 - a; ++a; }
+    return a;
+}
+constexpr int pair_col(int R, int p) {
+    int a = 0;
+    while (p >= R - 1 - a) { p -= R - 1 - a; ++a; }
+    return a + 1 + p;
+}
+
+// Row-side and column-side replica slots of launch group GI (NP pairs).
+template <int RR, int GI, int NP>
 struct PairSides {
     int na = 0, nb = 0;
     int ra[RR] = {}, rb[RR] = {};  // replica of each row-side / column-side slot
-    int pa[NP] = {}, pb[NP] = {};  // slots of pair P0 + p
+    int pa[NP] = {}, pb[NP] = {};  // slots of the group's pair p
+    int pi[NP] = {};               // record index of the group's pair p
     constexpr PairSides() {
+        constexpr PairGroups<RR> grp{};
         int sa[RR] = {}, sb[RR] = {};
         for (int r = 0; r < RR; ++r) sa[r] = sb[r] = -1;
-        int p = 0;
-        for (int a = 0; a < RR; ++a)
-            for (int b = a + 1; b < RR; ++b, ++p) {
-                if (p < P0 || p >= P0 + NP) continue;
-                if (sa[a] < 0) { sa[a] = na; ra[na++] = a; }
-                if (sb[b] < 0) { sb[b] = nb; rb[nb++] = b; }
-                pa[p - P0] = sa[a];
-                pb[p - P0] = sb[b];
-            }
+        for (int k = 0; k < NP; ++k) {
+            const int p = grp.pair[grp.first[GI] + k];
+            const int a = pair_row(RR, p), b = pair_col(RR, p);
+            if (sa[a] < 0) { sa[a] = na; ra[na++] = a; }
+            if (sb[b] < 0) { sb[b] = nb; rb[nb++] = b; }
+            pa[k] = sa[a];
+            pb[k] = sb[b];
+            pi[k] = p;
+        }
     }
 };
 
 constexpr int kTeamWaves = 4;  // waves per workgroup of the overlap kernel
 
-template <int RR, int P0, int NP>
-__global__ void __launch_bounds__(64 * kTeamWaves) __attribute__((amdgpu_waves_per_eu(1, 1)))
+template <int RR, int GI, int NP>
+__global__ void __launch_bounds__(64 * kTeamWaves) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_overlap_mfma(ShapeDev sh, int cfg0, int ncfg, int wc, int nxcd) {
-    constexpr PairSides<RR, P0, NP> ps{};
+    constexpr PairSides<RR, GI, NP> ps{};
     constexpr int NA = ps.na, NB = ps.nb;
     constexpr int PP = RR * (RR - 1) / 2;
     const int lane = threadIdx.x & 63, i = lane & 31, h = lane >> 5, sh4 = 4 * h;
@@ -576,7 +622,7 @@ k_overlap_mfma(ShapeDev sh, int cfg0, int ncfg, int wc, int nxcd) {
         if (lane == 0) {
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
-                unsigned long long* rp = (unsigned long long*)(sh.rec + ((size_t)cfg * PP + P0 + p) * rl);
+                unsigned long long* rp = (unsigned long long*)(sh.rec + ((size_t)cfg * PP + ps.pi[p]) * rl);
                 atomicAdd(rp + 2 * sh.L, (unsigned long long)(long long)tr[p]);
                 atomicAdd(rp + 2 * sh.L + 2, s4[p]);
             }
@@ -701,16 +747,16 @@ size_t gram_lds(int RR, int L) {
     const int nxp = 64 * ((L * L + 63) / 64);
     return (size_t)2 * PP * 2 * L * 8 + (size_t)RR * nxp * 4;
 }
-// Pairs P0 .. PP - 1 of RR replicas in launches of at most NP pairs.
-template <int RR, int P0, int NP>
+// Launch groups GI .. of RR replicas, one launch each.
+template <int RR, int GI>
 hipError_t launch_overlap(const ShapeDev& sh, int cfg0, int ncfg, int grid, int wc, int nxcd, hipStream_t st) {
-    constexpr int PP = RR * (RR - 1) / 2;
-    constexpr int n = PP - P0 < NP ? PP - P0 : NP;
-    hipLaunchKernelGGL((k_overlap_mfma<RR, P0, n>), dim3(grid), dim3(64 * kTeamWaves), 0, st, sh, cfg0, ncfg,
+    constexpr PairGroups<RR> grp{};
+    constexpr int n = grp.size[GI];
+    hipLaunchKernelGGL((k_overlap_mfma<RR, GI, n>), dim3(grid), dim3(64 * kTeamWaves), 0, st, sh, cfg0, ncfg,
                        wc, nxcd);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if constexpr (P0 + n < PP) return launch_overlap<RR, P0 + n, NP>(sh, cfg0, ncfg, grid, wc, nxcd, st);
+    if constexpr (GI + 1 < grp.n) return launch_overlap<RR, GI + 1>(sh, cfg0, ncfg, grid, wc, nxcd, st);
     return hipSuccess;
 }
 
@@ -740,18 +786,18 @@ hipError_t launch_mfma(const ShapeDev& sh, int cfg0, int ncfg, hipStream_t st) {
                            st, sh, cfg0, ncfg);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // overlap: one workgroup of kTeamWaves waves per CU; teams of wc waves,
+    // overlap: two workgroups of kTeamWaves waves per CU; teams of wc waves,
     // an XCD's share (a power-of-two fraction of it while a configuration
     // has fewer tiles, a multiple while there are fewer configurations than
     // teams)
     const int nxcd = ncu % 8 == 0 ? 8 : 1;
-    const int G = kTeamWaves * ncu, gx = G / nxcd;
+    const int G = kTeamWaves * 2 * ncu, gx = G / nxcd;
     const int ntt = (sh.Lt + 63) / 64, ntiles = ntt * ntt;
     int wc = gx;
     while (wc % 2 == 0 && wc / 2 >= ntiles) wc /= 2;
     auto fits = [&](int w) { return w <= gx ? gx % w == 0 : (w % gx == 0 && nxcd % (w / gx) == 0); };
     while (wc < G && G / wc > ncfg && fits(2 * wc)) wc *= 2;
-    return launch_overlap<RR, 0, 3>(sh, cfg0, ncfg, ncu, wc, nxcd, st);
+    return launch_overlap<RR, 0>(sh, cfg0, ncfg, 2 * ncu, wc, nxcd, st);
 }
 
 }  // namespace

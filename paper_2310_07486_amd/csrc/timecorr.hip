@@ -148,48 +148,63 @@ __global__ void __launch_bounds__(64 * kTcWaves) __attribute__((amdgpu_waves_per
                                                                                      acc[a][u][v], 0, 0, 0);
                 }
                 // epilogue: lane l gathers, for each q, the element of column
-                // (l + r_q) mod 32, which lies on diagonal l (or l - 32)
+                // (l + r_q) mod 32, which lies on diagonal l (or l - 32).
+                // kEdge: a tile that reaches past Ltau drops those elements
+                // (compiled apart, so the other tiles test nothing per
+                // element).
+                auto epilogue = [&](auto edgeC) {
+                    constexpr bool kEdge = decltype(edgeC)::value;
 #pragma unroll
-                for (int u = 0; u < 2; ++u)
+                    for (int u = 0; u < 2; ++u)
 #pragma unroll
-                    for (int v = 0; v < 2; ++v) {
-                        const int D0 = 64 * (T2 - T) + 32 * (v - u);
-                        if (D0 + 31 < 0) continue;  // below the diagonal
-                        const int tau2 = 64 * T2 + 32 * v + i;
-                        int sP = 0, sN = 0, qP = 0, qN = 0;
+                        for (int v = 0; v < 2; ++v) {
+                            const int D0 = 64 * (T2 - T) + 32 * (v - u);
+                            if (D0 + 31 < 0) continue;  // below the diagonal
+                            const int tau2 = 64 * T2 + 32 * v + i;
+                            // all of a lane's gathered values, and those of
+                            // diagonal l - 32 (i + r_q >= 32) apart
+                            int sA = 0, sN = 0, qA = 0, qN = 0;
 #pragma unroll
-                        for (int q = 0; q < 16; ++q) {
-                            const int r = 8 * (q >> 2) + 4 * h + (q & 3);
-                            int hs = 0, hq = 0;  // |H| <= L^2: a group's sums stay below 2^21
+                            for (int q = 0; q < 16; ++q) {
+                                const int r = 8 * (q >> 2) + 4 * h + (q & 3);
+                                int hs = 0, hq = 0;  // |H| <= L^2: a group's sums stay below 2^21
 #pragma unroll
-                            for (int a = 0; a < kG; ++a) {
-                                if (a >= ng) continue;
-                                const int Hv = acc[a][u][v][q];
-                                hs += Hv;
-                                hq += __mul24(Hv, Hv);
+                                for (int a = 0; a < kG; ++a) {
+                                    if (a >= ng) continue;
+                                    const int Hv = acc[a][u][v][q];
+                                    hs += Hv;
+                                    hq += __mul24(Hv, Hv);
+                                }
+                                if constexpr (kEdge) {
+                                    const bool out = 64 * T + 32 * u + r >= Lt || tau2 >= Lt;
+                                    hs = out ? 0 : hs;
+                                    hq = out ? 0 : hq;
+                                }
+                                const int src = ((lane & 32) | ((lane + r) & 31)) << 2;
+                                const int gs = __builtin_amdgcn_ds_bpermute(src, hs);
+                                const int gq = __builtin_amdgcn_ds_bpermute(src, hq);
+                                const bool neg = i + r >= 32;
+                                sA += gs;
+                                qA += gq;
+                                sN += neg ? gs : 0;
+                                qN += neg ? gq : 0;
                             }
-                            if (edge && (64 * T + 32 * u + r >= Lt || tau2 >= Lt)) hs = hq = 0;
-                            const int src = ((lane & 32) | ((lane + r) & 31)) << 2;
-                            const int gs = __builtin_amdgcn_ds_bpermute(src, hs);
-                            const int gq = __builtin_amdgcn_ds_bpermute(src, hq);
-                            if (i + r < 32) {
-                                sP += gs;
-                                qP += gq;
-                            } else {
-                                sN += gs;
-                                qN += gq;
+                            const int sP = sA - sN, qP = qA - qN;
+                            const int dP = D0 + i, dN = D0 + i - 32;
+                            if (dP >= 0 && dP < Lt) {
+                                atomicAdd(&Cb[dP], (unsigned long long)(long long)sP);
+                                atomicAdd(&Cb[Lt + dP], (unsigned long long)qP);
+                            }
+                            if (dN >= 0 && dN < Lt) {
+                                atomicAdd(&Cb[dN], (unsigned long long)(long long)sN);
+                                atomicAdd(&Cb[Lt + dN], (unsigned long long)qN);
                             }
                         }
-                        const int dP = D0 + i, dN = D0 + i - 32;
-                        if (dP >= 0 && dP < Lt) {
-                            atomicAdd(&Cb[dP], (unsigned long long)(long long)sP);
-                            atomicAdd(&Cb[Lt + dP], (unsigned long long)qP);
-                        }
-                        if (dN >= 0 && dN < Lt) {
-                            atomicAdd(&Cb[dN], (unsigned long long)(long long)sN);
-                            atomicAdd(&Cb[Lt + dN], (unsigned long long)qN);
-                        }
-                    }
+                };
+                if (edge)
+                    epilogue(std::true_type{});
+                else
+                    epilogue(std::false_type{});
             }
         }
         __syncthreads();

@@ -130,7 +130,11 @@ __global__ void __launch_bounds__(256) k_transpose(ShapeDev sh, long long items)
 // each wave alone (no barrier inside a configuration), one wave per SIMD:
 // the 2 x 2 blocks of 32 x 32 of every replica's G^r = S S^T, accumulators
 // in the AGPRs, K = tau in chunks of 64, the {0,1} operands built in
-// registers from each lane's bit row.  The epilogue forms
+// registers from each lane's bit row.  With the int32 epilogue (NARROW), up
+// to 4 replicas and more configurations than CUs, two workgroups share a
+// CU, two waves a SIMD (one's MFMAs run while the other builds operands),
+// each wave on half a tile pair (the 2 x 1 blocks of a column half) above 2
+// replicas.  The epilogue forms
 // G = Ltau - 2 (n_x + n_y) + 4 (B B^T)_xy and the products G^a G^b.
 //
 // An element (x, y) of an off-diagonal pair stands for (y, x) too, with the
@@ -147,12 +151,22 @@ __global__ void __launch_bounds__(256) k_transpose(ShapeDev sh, long long items)
 // them in registers and adds 8 bucket values per pair and block, not 32.
 // Otherwise tile X holds the sites 64X .. 64X + 63 and every element adds
 // its own two.
+//
+// NARROW (BLK and Ltau <= 8192): the products and the lane sums are int32
+// (24-bit multiplies), and a lane's x1 - y1 sums, the same in every block
+// of a tile pair, are flushed once per pair; otherwise they are int64.
 // ---------------------------------------------------------------------------
 constexpr int kGramWaves = 4;
+constexpr int kNarrowLt = 8192;  // the int32 epilogue: |G| <= 2^13
+// waves per SIMD: two where a wave's accumulators (RR x 2 x NV blocks of
+// 16 per lane) fit in half the register file, with the int32 epilogue
+constexpr int gram_wpe(int RR, int NV, bool narrow) { return narrow && RR * NV <= 4 ? 2 : 1; }
 
-template <int RR, int NV, bool BLK>
-__global__ void __launch_bounds__(64 * kGramWaves) __attribute__((amdgpu_waves_per_eu(1, 1)))
+template <int RR, int NV, bool BLK, bool NARROW>
+__global__ void __launch_bounds__(64 * kGramWaves)
+    __attribute__((amdgpu_waves_per_eu(gram_wpe(RR, NV, NARROW), gram_wpe(RR, NV, NARROW))))
 k_gram_mfma(ShapeDev sh, int cfg0, int ncfg) {
+    static_assert(BLK || !NARROW, "the int32 epilogue takes the 8 x 8 site blocks");
     constexpr int PP = RR * (RR - 1) / 2;
     extern __shared__ __align__(16) uint8_t smem[];
     const int L = sh.L, L2 = sh.L2, Lt = sh.Lt, nc = sh.nc, nxp = sh.nxp;
@@ -253,12 +267,79 @@ k_gram_mfma(ShapeDev sh, int cfg0, int ncfg) {
                 }
                 if (nc & 1) chunk(w0a, w0b);
             };
-            const bool diag = X == Y;
-            if (diag)
-                kloop(std::true_type{});
-            else
-                kloop(std::false_type{});
+            // the K loop and the epilogue of a diagonal or an off-diagonal
+            // pair, each its own straight code (the accumulators never meet
+            // at a branch join)
+            auto finish = [&](auto diagC) {
+            constexpr bool diag = decltype(diagC)::value;
+            kloop(diagC);
             // epilogue, block by block
+            if constexpr (NARROW) {
+                // |G| <= Ltau <= 8192: a product is below 2^26 and a sum of
+                // 16 of them below 2^30, so both are formed in int32 with
+                // 24-bit multiplies.  The x1 - y1 buckets of a lane are the
+                // same in every block of the tile, so an off-diagonal pair
+                // sums them over its blocks and flushes them once.
+                const int x1 = 8 * (X % nbl) + 4 * h, y1 = 8 * (Y % nbl) + (i & 7);
+                int sxa[PP][4];
+#pragma unroll
+                for (int p = 0; p < PP; ++p)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) sxa[p][j] = 0;
+                auto flush_x = [&](unsigned long long* Db) {
+#pragma unroll
+                    for (int p = 0; p < PP; ++p)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            atomicAdd(&Db[(p * 2 + 0) * L + (x1 + j - y1 + L) % L],
+                                      (unsigned long long)(long long)sxa[p][j]);
+                            sxa[p][j] = 0;
+                        }
+                };
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    int rn[RR][16];  // 2 n^r of the rows of this lane's elements
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) {
+                        const int xs = site(X, 32 * u + 8 * (q >> 2) + 4 * h + (q & 3));
+#pragma unroll
+                        for (int r = 0; r < RR; ++r) rn[r][q] = 2 * nS[r * nxp + xs];
+                    }
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        const int V = v0 + v;
+                        if (diag && NV == 2 && u == 1 && V == 0) continue;
+                        unsigned long long* Db = (diag && (NV == 1 || u == V)) ? Fb : Ub;
+                        const int x2 = 8 * (X / nbl) + 4 * u, y2 = 8 * (Y / nbl) + ((32 * V + i) >> 3);
+                        int G[RR][16];
+#pragma unroll
+                        for (int r = 0; r < RR; ++r) {
+                            const int nb = Lt - 2 * nS[r * nxp + sb[v]];
+#pragma unroll
+                            for (int q = 0; q < 16; ++q) G[r][q] = nb - rn[r][q] + 4 * acc[r][u][v][q];
+                        }
+                        int p = 0;
+#pragma unroll
+                        for (int a = 0; a < RR; ++a)
+#pragma unroll
+                            for (int b = a + 1; b < RR; ++b, ++p) {
+                                int sy[4] = {0, 0, 0, 0};
+#pragma unroll
+                                for (int q = 0; q < 16; ++q) {
+                                    const int hv = __mul24(G[a][q], G[b][q]);
+                                    sxa[p][q & 3] += hv;
+                                    sy[q >> 2] += hv;
+                                }
+#pragma unroll
+                                for (int j = 0; j < 4; ++j)
+                                    atomicAdd(&Db[(p * 2 + 1) * L + (x2 + j - y2 + L) % L],
+                                              (unsigned long long)(long long)sy[j]);
+                            }
+                        if (diag) flush_x(Db);
+                    }
+                }
+                if (!diag) flush_x(Ub);
+            } else
 #pragma unroll
             for (int u = 0; u < 2; ++u)
 #pragma unroll
@@ -328,6 +409,11 @@ k_gram_mfma(ShapeDev sh, int cfg0, int ncfg) {
                         }
                     }
                 }
+            };
+            if (X == Y)
+                finish(std::true_type{});
+            else
+                finish(std::false_type{});
         }
         __syncthreads();
         // D[d] = F[d] + U[d] + U[-d]; sum Q^2 = sum_xy G^a_xy G^b_xy =
@@ -765,12 +851,16 @@ hipError_t launch_mfma(const ShapeDev& sh, int cfg0, int ncfg, hipStream_t st) {
     int dev = 0, ncu = 256;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    // a wave holds every replica's G of its tile: 64 x 64 up to 4 replicas,
-    // 64 x 32 above
+    // a wave holds every replica's G of its unit: 64 x 64 up to 4 replicas,
+    // 64 x 32 above; with the int32 epilogue and more configurations than
+    // CUs two waves share a SIMD, each with at most 128 accumulators (64 x 64
+    // for 2 replicas, else 64 x 32)
     constexpr int NV = RR <= 4 ? 2 : 1;
+    constexpr int NVn = RR <= 2 ? 2 : 1;
     static bool lds_set = false;
     if (!lds_set) {
-        for (const void* f : {(const void*)k_gram_mfma<RR, NV, true>, (const void*)k_gram_mfma<RR, NV, false>}) {
+        for (const void* f : {(const void*)k_gram_mfma<RR, NVn, true, true>, (const void*)k_gram_mfma<RR, NV, true, true>,
+                              (const void*)k_gram_mfma<RR, NV, true, false>, (const void*)k_gram_mfma<RR, NV, false, false>}) {
             const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                      (int)gram_lds(RR, 32));
             if (e != hipSuccess) return e;
@@ -778,12 +868,21 @@ hipError_t launch_mfma(const ShapeDev& sh, int cfg0, int ncfg, hipStream_t st) {
         lds_set = true;
     }
     const int ggrid = std::min(ncfg, ncu);
-    if (sh.L % 8 == 0)
-        hipLaunchKernelGGL((k_gram_mfma<RR, NV, true>), dim3(ggrid), dim3(64 * kGramWaves), gram_lds(RR, sh.L), st,
-                           sh, cfg0, ncfg);
-    else
-        hipLaunchKernelGGL((k_gram_mfma<RR, NV, false>), dim3(ggrid), dim3(64 * kGramWaves), gram_lds(RR, sh.L),
+    auto narrow = [&](auto nvC) {
+        constexpr int nv = decltype(nvC)::value;
+        hipLaunchKernelGGL((k_gram_mfma<RR, nv, true, true>), dim3(std::min(ncfg, gram_wpe(RR, nv, true) * ncu)),
+                           dim3(64 * kGramWaves), gram_lds(RR, sh.L), st, sh, cfg0, ncfg);
+    };
+    if (sh.L % 8 == 0 && sh.Lt <= kNarrowLt && ncfg > ncu)
+        narrow(std::integral_constant<int, NVn>{});
+    else if (sh.L % 8 == 0 && sh.Lt <= kNarrowLt)
+        narrow(std::integral_constant<int, NV>{});
+    else if (sh.L % 8 == 0)
+        hipLaunchKernelGGL((k_gram_mfma<RR, NV, true, false>), dim3(ggrid), dim3(64 * kGramWaves), gram_lds(RR, sh.L),
                            st, sh, cfg0, ncfg);
+    else
+        hipLaunchKernelGGL((k_gram_mfma<RR, NV, false, false>), dim3(ggrid), dim3(64 * kGramWaves),
+                           gram_lds(RR, sh.L), st, sh, cfg0, ncfg);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // overlap: two workgroups of kTeamWaves waves per CU; teams of wc waves,

@@ -105,7 +105,6 @@ k_gram_store(ShapeDev sh, int cfg0, int ncfg, int nb, int8_t* __restrict__ ws) {
             int X = 0, rem = tp;
             while (rem >= nt - X) { rem -= nt - X; ++X; }
             const int Y = X + rem;
-            const bool diag = X == Y;
             const int xa[2] = {site(X, i), site(X, 32 + i)};
             int xb[NV];
 #pragma unroll
@@ -173,10 +172,11 @@ k_gram_store(ShapeDev sh, int cfg0, int ncfg, int nb, int8_t* __restrict__ ws) {
                 }
                 if (nc & 1) chunk(w0a, w0b);
             };
-            if (diag)
-                kloop(std::true_type{});
-            else
-                kloop(std::false_type{});
+            // the K loop and the epilogue of a diagonal or an off-diagonal
+            // pair, each its own straight code
+            auto finish = [&](auto diagC) {
+            constexpr bool diag = decltype(diagC)::value;
+            kloop(diagC);
             // G = Ltau - 2 (n_row + n_col) + 4 (B B^T), G' = G / 2 as two
             // digits G' = 64 h + l, zero on padding
 #pragma unroll
@@ -219,6 +219,11 @@ k_gram_store(ShapeDev sh, int cfg0, int ncfg, int nb, int8_t* __restrict__ ws) {
                         }
                     }
                 }
+            };
+            if (X == Y)
+                finish(std::true_type{});
+            else
+                finish(std::false_type{});
         }
     }
 }

@@ -34,6 +34,7 @@
 // thread with an int32 multiply-accumulate loop over unpacked spins, one
 // launch per configuration: the reference point for the batched form.
 #include <algorithm>
+#include <type_traits>
 
 #include "tfim_internal.h"
 
@@ -41,7 +42,24 @@ namespace tfim {
 namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v8i __attribute__((ext_vector_type(8)));
 typedef int v16i __attribute__((ext_vector_type(16)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+// v_mfma_scale_f32_32x32x64_f8f6f4 operands: format code 4 = e2m1 (fp4) on
+// both sides, four registers of 8 nibbles each; block scales are E8M0
+// (2^(e - 127)): 2^4 on the row side, 1 on the column side
+constexpr int kFp4 = 4;
+constexpr int kScaleRow = 127 + 4;
+constexpr int kScaleOne = 127;
+// Bit 4j + m of x (m < 4, j < 8) as the fp4 nibble j of register m: 0 or
+// 0.5; the upper four registers are not read in the fp4 form.
+__device__ __forceinline__ v8i fp4_bits_operand(uint32_t x) {
+    v4i o;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) o[m] = (int)((x >> m) & 0x11111111u);
+    return __builtin_shufflevector(o, o, 0, 1, 2, 3, -1, -1, -1, -1);
+}
 
 constexpr int kMaxR = 6;       // replicas handled by the MFMA kernels
 constexpr int kMaxP = kMaxR * (kMaxR - 1) / 2;
@@ -203,7 +221,9 @@ k_gram_mfma(ShapeDev sh, int cfg0, int ncfg) {
             int sb[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) sb[v] = site(Y, 32 * (v0 + v) + i);
-            v16i acc[RR][2][NV];
+            // NARROW: fp32 accumulators of the fp4 form (below), else int32
+            using Acc = std::conditional_t<NARROW, v16f, v16i>;
+            Acc acc[RR][2][NV];
 #pragma unroll
             for (int r = 0; r < RR; ++r)
 #pragma unroll
@@ -212,6 +232,57 @@ k_gram_mfma(ShapeDev sh, int cfg0, int ncfg) {
                     for (int v = 0; v < NV; ++v)
 #pragma unroll
                         for (int q = 0; q < 16; ++q) acc[r][u][v][q] = 0;
+            // The fp4 K loop: 64 values of tau per MFMA.  Lane (i, h) feeds
+            // row i with the 32 bits of half h of its chunk word, element
+            // 8m + j (register m, nibble j) being bit 4j + m, as the e2m1
+            // values 0 and 0.5 (nibble 0 or 1: one mask per register).  The
+            // row side's block scale 2^4 makes each coincidence add 4, so the
+            // accumulator holds 4 (B B^T), exact in fp32 (at most 4 Ltau).
+            auto kloop4 = [&](auto diagC) {
+                constexpr bool kDiag = decltype(diagC)::value;
+                constexpr int NB = kDiag ? 0 : NV;
+                const uint32_t* const pt32 = (const uint32_t*)pt;
+                auto fetch = [&](int c, uint32_t (&wa)[2][RR], uint32_t (&wb)[NV][RR]) {
+#pragma unroll
+                    for (int r = 0; r < RR; ++r) {
+                        const size_t o = ((size_t)r * nc + c) * nxp;
+#pragma unroll
+                        for (int u = 0; u < 2; ++u) wa[u][r] = pt32[2 * (o + sa[u]) + h];
+#pragma unroll
+                        for (int v = 0; v < NB; ++v) wb[v][r] = pt32[2 * (o + sb[v]) + h];
+                    }
+                };
+                auto chunk = [&](const uint32_t (&wa)[2][RR], const uint32_t (&wb)[NV][RR]) {
+                    v8i A[2][RR], B[NV][RR];
+#pragma unroll
+                    for (int r = 0; r < RR; ++r) {
+#pragma unroll
+                        for (int u = 0; u < 2; ++u) A[u][r] = fp4_bits_operand(wa[u][r]);
+#pragma unroll
+                        for (int v = 0; v < NB; ++v) B[v][r] = fp4_bits_operand(wb[v][r]);
+                    }
+#pragma unroll
+                    for (int r = 0; r < RR; ++r)
+#pragma unroll
+                        for (int u = 0; u < 2; ++u)
+#pragma unroll
+                            for (int v = 0; v < NV; ++v) {
+                                if (kDiag && NV == 2 && u == 1 && v == 0) continue;
+                                const v8i b = kDiag ? A[NV == 2 ? v : v0][r] : B[v][r];
+                                acc[r][u][v] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                                    A[u][r], b, acc[r][u][v], kFp4, kFp4, 0, kScaleRow, 0, kScaleOne);
+                            }
+                };
+                uint32_t w0a[2][RR], w0b[NV][RR], w1a[2][RR], w1b[NV][RR];
+                fetch(0, w0a, w0b);
+                for (int c = 0; c + 1 < nc; c += 2) {
+                    fetch(c + 1, w1a, w1b);
+                    chunk(w0a, w0b);
+                    fetch(min(c + 2, nc - 1), w0a, w0b);
+                    chunk(w1a, w1b);
+                }
+                if (nc & 1) chunk(w0a, w0b);
+            };
             // the K loop; kDiag: Y = X, the column rows are row rows (no
             // loads of their own) and, with both column blocks, the block
             // (1, 0) is skipped
@@ -272,7 +343,10 @@ k_gram_mfma(ShapeDev sh, int cfg0, int ncfg) {
             // at a branch join)
             auto finish = [&](auto diagC) {
             constexpr bool diag = decltype(diagC)::value;
-            kloop(diagC);
+            if constexpr (NARROW)
+                kloop4(diagC);
+            else
+                kloop(diagC);
             // epilogue, block by block
             if constexpr (NARROW) {
                 // |G| <= Ltau <= 8192: a product is below 2^26 and a sum of
@@ -316,7 +390,7 @@ k_gram_mfma(ShapeDev sh, int cfg0, int ncfg) {
                         for (int r = 0; r < RR; ++r) {
                             const int nb = Lt - 2 * nS[r * nxp + sb[v]];
 #pragma unroll
-                            for (int q = 0; q < 16; ++q) G[r][q] = nb - rn[r][q] + 4 * acc[r][u][v][q];
+                            for (int q = 0; q < 16; ++q) G[r][q] = nb - rn[r][q] + (int)acc[r][u][v][q];
                         }
                         int p = 0;
 #pragma unroll

@@ -24,7 +24,8 @@
 //    a wavefront (six xor-shuffle butterfly stages).
 // 2. k_gram_mfma: one workgroup per configuration at a time, 64x64 tiles of
 //    G (upper triangle of tile pairs), all replicas at once, bucket sums in
-//    LDS, flushed once per configuration.
+//    LDS, flushed once per configuration; for Ltau <= 8192 on fp4 MFMAs
+//    (v_mfma_scale_f32_32x32x64_f8f6f4: {0, 0.5} operands, exact in fp32).
 // 3. k_overlap_mfma: every wave alone (no LDS, no barrier) on 64x64 tiles of
 //    a group of 2 pairs at once that share a replica on one side (one launch
 //    per group, two waves per SIMD), operands unpacked in registers, the rank-one corrections folded into one more
@@ -42,24 +43,9 @@ namespace tfim {
 namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
-typedef int v8i __attribute__((ext_vector_type(8)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
-// v_mfma_scale_f32_32x32x64_f8f6f4 operands: format code 4 = e2m1 (fp4) on
-// both sides, four registers of 8 nibbles each; block scales are E8M0
-// (2^(e - 127)): 2^4 on the row side, 1 on the column side
-constexpr int kFp4 = 4;
-constexpr int kScaleRow = 127 + 4;
-constexpr int kScaleOne = 127;
-// Bit 4j + m of x (m < 4, j < 8) as the fp4 nibble j of register m: 0 or
-// 0.5; the upper four registers are not read in the fp4 form.
-__device__ __forceinline__ v8i fp4_bits_operand(uint32_t x) {
-    v4i o;
-#pragma unroll
-    for (int m = 0; m < 4; ++m) o[m] = (int)((x >> m) & 0x11111111u);
-    return __builtin_shufflevector(o, o, 0, 1, 2, 3, -1, -1, -1, -1);
-}
 
 constexpr int kMaxR = 6;       // replicas handled by the MFMA kernels
 constexpr int kMaxP = kMaxR * (kMaxR - 1) / 2;
@@ -253,7 +239,7 @@ k_gram_mfma(ShapeDev sh, int cfg0, int ncfg) {
                     }
                 };
                 auto chunk = [&](const uint32_t (&wa)[2][RR], const uint32_t (&wb)[NV][RR]) {
-                    v8i A[2][RR], B[NV][RR];
+                    i32x8 A[2][RR], B[NV][RR];
 #pragma unroll
                     for (int r = 0; r < RR; ++r) {
 #pragma unroll
@@ -268,7 +254,7 @@ k_gram_mfma(ShapeDev sh, int cfg0, int ncfg) {
 #pragma unroll
                             for (int v = 0; v < NV; ++v) {
                                 if (kDiag && NV == 2 && u == 1 && v == 0) continue;
-                                const v8i b = kDiag ? A[NV == 2 ? v : v0][r] : B[v][r];
+                                const i32x8 b = kDiag ? A[NV == 2 ? v : v0][r] : B[v][r];
                                 acc[r][u][v] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
                                     A[u][r], b, acc[r][u][v], kFp4, kFp4, 0, kScaleRow, 0, kScaleOne);
                             }

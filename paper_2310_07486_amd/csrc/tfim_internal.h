@@ -138,6 +138,7 @@ __device__ __forceinline__ uint64_t wave_transpose64(uint64_t v) {
 // is the popcount of the AND of the two rows.  x is the half already shifted
 // right by 4h; byte j of dword m is bit 8j + m of x, times 4 when kTimes4.
 typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
 
 template <bool kTimes4>
 __device__ __forceinline__ i32x4 mfma_bits_operand(uint32_t x) {
@@ -151,6 +152,21 @@ __device__ __forceinline__ i32x4 mfma_bits_operand(uint32_t x) {
         for (int m = 0; m < 4; ++m) o[m] = (int)((x >> m) & 0x01010101u);
     }
     return o;
+}
+
+// v_mfma_scale_f32_32x32x64_f8f6f4 operands: format code 4 = e2m1 (fp4) on
+// both sides, four registers of 8 nibbles each; block scales are E8M0
+// (2^(e - 127)): 2^4 on the row side, 1 on the column side
+constexpr int kFp4 = 4;
+constexpr int kScaleRow = 127 + 4;
+constexpr int kScaleOne = 127;
+// Bit 4j + m of x (m < 4, j < 8) as the fp4 nibble j of register m: 0 or
+// 0.5; the upper four registers are not read in the fp4 form.
+__device__ __forceinline__ i32x8 fp4_bits_operand(uint32_t x) {
+    i32x4 o;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) o[m] = (int)((x >> m) & 0x11111111u);
+    return __builtin_shufflevector(o, o, 0, 1, 2, 3, -1, -1, -1, -1);
 }
 
 // Sixteen int8 bytes summing to v, |v| <= 1792: fifteen of floor(v / 16) and

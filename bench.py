@@ -183,12 +183,20 @@ def measure_leg(plan, sh, torch, args):
     # xi^(2) of every k from the buckets (FP64, host)
     A = plan.measure(0, tfim.TFIM_MEASURE_BUCKETS)
     xi = tfim.tfim_xi2(np.ascontiguousarray(A[:, 0]), sh.L)
+    # the Gram runs on fp4 MFMAs (peak 10.1 POP/s) where L is a multiple of 8
+    # and Ltau <= 8192, else on int8 (5 POP/s) like the overlaps
+    gram_fp4 = sh.L % 8 == 0 and sh.Ltau <= 8192
+    peak_mixed = (g_ops + q_ops) / (g_ops / (10100.0 if gram_fp4 else 5000.0) + q_ops / 5000.0)
     return {
         "configurations": ncfg, "replicas": sh.n_replicas,
         "ops_per_configuration": per_cfg, "gram_ops": g_ops * ncfg, "overlap_ops": q_ops * ncfg,
+        "mfma_forms": {"gram": "fp4 (e2m1 {0, 0.5} operands, fp32 accumulate)" if gram_fp4 else "int8",
+                       "overlap": "int8"},
         "transpose_ms": round(t_tr, 3),
         "batched_mfma": {"ms": round(t_all, 3), "int8_tops": round(tops, 2),
                           "frac_of_int8_peak": round(tops / 5000.0, 4),
+                          "peak_of_the_forms_tops": round(peak_mixed, 1),
+                          "frac_of_the_forms_peak": round(tops / peak_mixed, 4),
                           "int8_tops_with_transpose": round(tops_tr, 2),
                           "frac_with_transpose": round(tops_tr / 5000.0, 4)},
         "per_configuration_mfma": {"configurations": n_un, "ms_per_cfg": round(t_un / n_un, 4),
